@@ -1,0 +1,47 @@
+"""Tucker-compressed NTF objective and gradient (Appendix A), float64.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The data tensor is given in Tucker format T = (U^(1) (x) ... (x) U^(N)) G with core G of
+shape (r_1, ..., r_N) and bases U^(p) of shape n_p x r_p. The objective F_t is eq.
+objFunTucker; its gradient (Appendix A) only needs the small products (U^(p))^T A^(p):
+
+  grad_{A^(i)} F_t = - U^(i) G_[i] [KR of (U^(p))^T A^(p), p != i] + A^(i) [Hadamard of the
+                     other Grams],
+
+where the Khatri-Rao product is taken in the same order as for the uncompressed MTTKRP,
+so the first term is U^(i) times the MTTKRP of the core with the projected factors.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .tensor import hadamard_gram, kruskal, mttkrp
+
+
+def tucker_full(core: np.ndarray, bases) -> np.ndarray:
+    """Expand (U^(1) (x) ... (x) U^(N)) G to a dense tensor (n-mode products)."""
+    X = np.asarray(core, dtype=np.float64)
+    for p, U in enumerate(bases):
+        U = np.asarray(U, dtype=np.float64)
+        X = np.moveaxis(np.tensordot(U, X, axes=([1], [p])), 0, p)
+    return X
+
+
+def tucker_mttkrp(core: np.ndarray, bases, factors, i: int) -> np.ndarray:
+    """MTTKRP of the Tucker-format tensor in mode i: U^(i) [ G_[i] KR((U^(p))^T A^(p)) ]."""
+    proj = [np.asarray(U, dtype=np.float64).T @ np.asarray(A, dtype=np.float64)
+            for U, A in zip(bases, factors)]
+    return np.asarray(bases[i], dtype=np.float64) @ mttkrp(core, proj, i)
+
+
+def tucker_objective(core: np.ndarray, bases, factors) -> float:
+    """F_t = 1/2 || (U (x) ...) G - [[A]] ||_F^2 from the explicit residual (eq. objFunTucker)."""
+    R = tucker_full(core, bases) - kruskal(factors)
+    return 0.5 * float(np.sum(R * R))
+
+
+def tucker_gradient(core: np.ndarray, bases, factors, i: int) -> np.ndarray:
+    """grad_{A^(i)} F_t as written in Appendix A."""
+    A = np.asarray(factors[i], dtype=np.float64)
+    return -tucker_mttkrp(core, bases, factors, i) + A @ hadamard_gram(factors, i)
