@@ -1,0 +1,212 @@
+/*
+ * ntf.h - C ABI of the MI355X (gfx950) library for nonnegative CP tensor factorization
+ * (NTF) by block-coordinate descent with A-HALS block updates, accelerated by heuristic
+ * extrapolation with restarts (HER).
+ *
+ * Method: A. M. S. Ang, J. E. Cohen, L. T. K. Hien, N. Gillis, "Accelerating block
+ * coordinate descent for nonnegative tensor factorization", arXiv 2001.04321. Citations
+ * below name the paper's sections, equations (by their labels) and algorithms.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Modes are 0-based here (1-based in the paper). 2 <= order <= NTF_MAX_ORDER.
+ *  - A tensor is dense and C-contiguous: the last mode is the fastest-varying index.
+ *  - A factor A^(n) is an I_n x r float32 matrix, row-major (row j holds the r entries
+ *    a_1^(n)[j] .. a_r^(n)[j] contiguously). 1 <= r <= NTF_MAX_RANK.
+ *  - Every data pointer is a DEVICE pointer on the handle's device unless stated
+ *    otherwise. Arrays of pointers (`const float* const* A`) are HOST arrays holding
+ *    device pointers. The caller allocates and owns all buffers; the library never frees
+ *    caller memory. Buffers must stay valid until the enqueued work has completed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the legacy default stream). All
+ *    calls enqueue work asynchronously and return; results are valid after the stream
+ *    has been synchronized.
+ *  - Errors: a call returns NTF_OK or an error status. On an argument error nothing is
+ *    enqueued and no caller buffer is written. C++ exceptions never cross this ABI.
+ *    ntf_last_error() returns a thread-local message describing the last error.
+ *  - A handle is bound to one device, owns the library's workspace (MTTKRP split
+ *    partials, Gram partials, inner-solver synchronization slots, captured graphs) and
+ *    is not thread-safe: one host thread at a time, calls on one handle must not overlap
+ *    on different streams.
+ *  - Kernels report rare runtime conditions (a bounded wait that timed out, a non-finite
+ *    objective) in a device-side flag word; read it with ntf_device_flags().
+ */
+#ifndef NTF_H
+#define NTF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NTF_MAX_ORDER 8
+#define NTF_MAX_RANK 256
+
+typedef enum ntf_status {
+  NTF_OK = 0,
+  NTF_EINVAL = 1,         /* invalid argument (null pointer, bad size/mode/rank/dtype) */
+  NTF_ENOMEM = 2,         /* device allocation of the handle's workspace failed */
+  NTF_EDEVICE = 3,        /* a HIP runtime call failed */
+  NTF_EUNSUPPORTED = 4,   /* valid but outside what the kernels implement */
+  NTF_ENUMERIC = 5        /* non-finite value where a finite one is required */
+} ntf_status;
+
+typedef enum ntf_dtype {
+  NTF_F32 = 0,            /* IEEE float32 */
+  NTF_BF16 = 1            /* bfloat16 (upper 16 bits of a float32) */
+} ntf_dtype;
+
+/* Device flag bits reported by ntf_device_flags(). */
+#define NTF_FLAG_WAIT_TIMEOUT 0x1u   /* a cross-workgroup wait gave up; results invalid */
+#define NTF_FLAG_NONFINITE 0x2u      /* a restart surrogate F-hat was NaN or infinite */
+
+/* Dense tensor descriptor (paper Sec. 1: T in R^{I_1 x ... x I_N}). */
+typedef struct ntf_tensor {
+  int32_t order;                 /* N, 2..NTF_MAX_ORDER */
+  int32_t dtype;                 /* ntf_dtype of the elements */
+  int64_t dims[NTF_MAX_ORDER];   /* I_1..I_N, each >= 1; entries past `order` ignored */
+  const void* data;              /* device pointer, C-contiguous, 16-byte aligned */
+} ntf_tensor;
+
+typedef struct ntf_handle ntf_handle;
+
+/* HER parameters (Sec. 3.1.4, table of HER parameters; defaults of Sec. 4.1) and the
+ * inner stopping rule of Sec. 4.1. Validation: 0 <= beta0 < 1 (beta0 = 0 gives plain
+ * Algorithm 1), 1 <= gamma_bar <= gamma <= eta, 1 <= max_inner <= 1000, inner_tol >= 0. */
+typedef struct ntf_her_params {
+  double beta0;        /* initial extrapolation weight, default 0.5 */
+  double gamma;        /* growth rate of beta, default 1.05 */
+  double gamma_bar;    /* growth rate of beta_bar, default 1.01 */
+  double eta;          /* decay rate of beta, default 1.5 */
+  int32_t max_inner;   /* A-HALS sweeps per block at most, default 50 */
+  int32_t reserved;    /* must be 0 */
+  double inner_tol;    /* stop when ||W_s - W_{s-1}||_F <= inner_tol ||W_1 - W_0||_F, default 1e-2 */
+} ntf_her_params;
+
+/* HER scalar state, kept in DEVICE memory (Algorithm 2: beta_k, beta_bar_k, F-hat_k). */
+typedef struct ntf_her_state {
+  double beta;         /* extrapolation weight used by the next extrapolation step */
+  double beta_bar;     /* upper bound of beta */
+  double fhat_prev;    /* F-hat of the last completed iteration (F(A_0) after INIT) */
+  double fhat;         /* F-hat_k of the last DECIDE */
+  int64_t k;           /* completed outer iterations since INIT */
+  int32_t restart;     /* 1 if the last DECIDE restarted, else 0 */
+  int32_t nrestarts;   /* restarts since INIT */
+  int64_t it;          /* iterations completed in the current ntf_solve call (trace index) */
+} ntf_her_state;
+
+/* Per-iteration record written by ntf_solve (device arrays, each may be NULL; each
+ * array has room for `iters` entries, `sweeps` for iters * order). */
+typedef struct ntf_trace {
+  double* fhat;        /* F-hat_k */
+  double* beta;        /* beta after iteration k's update */
+  double* beta_bar;    /* beta_bar after iteration k's update */
+  int32_t* restart;    /* 1 if iteration k restarted */
+  int32_t* sweeps;     /* A-HALS sweeps of block n at iteration k: [k * order + n] */
+} ntf_trace;
+
+typedef enum ntf_her_op {
+  NTF_HER_INIT = 0,         /* state <- (beta0, beta_bar = 1, fhat_prev = *fhat, k = 0) */
+  NTF_HER_EXTRAPOLATE = 1,  /* A_hat[b] <- max(0, A_new[b] + beta (A_new[b] - A[b])) */
+  NTF_HER_DECIDE = 2        /* restart test on *fhat, beta update, A[l] <- survivor */
+} ntf_her_op;
+
+/* ---------------------------------------------------------------- handle, errors --- */
+
+/* Create a handle on HIP device `device`. */
+ntf_status ntf_handle_create(ntf_handle** out, int device);
+/* Release the handle's workspace (synchronizes the device first). NULL is a no-op. */
+void ntf_handle_destroy(ntf_handle* h);
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char* ntf_last_error(void);
+/* Static name of a status code. */
+const char* ntf_status_string(ntf_status s);
+/* Library version string. */
+const char* ntf_version(void);
+/* Synchronize `stream`, then read and clear the handle's device flag word (NTF_FLAG_*). */
+ntf_status ntf_device_flags(ntf_handle* h, void* stream, uint32_t* flags_out);
+
+/* ------------------------------------------------------------------ hot-path steps --- */
+
+/* ||T||_F^2 accumulated in float64 (needed by the restart surrogate F-hat, Sec. 3.1.3).
+ * out: one device double. Deterministic (fixed reduction order). */
+ntf_status ntf_norm2(ntf_handle* h, const ntf_tensor* T, double* out, void* stream);
+
+/* bfloat16 copy of a float32 array, round to nearest even (the stored-tensor form).
+ * src: n floats; dst: n uint16 bit patterns. Finite inputs round exactly like the
+ * IEEE-style rule; NaN inputs give a quiet NaN. */
+ntf_status ntf_cast_bf16(ntf_handle* h, const float* src, uint16_t* dst, int64_t n,
+                         void* stream);
+
+/* MTTKRP of mode `mode` (Sec. 2, eq. def:grad, data term T_[n] B^(n) with B^(n) of eq.
+ * def:B): P[j, p] = sum over all indices but j_n of T[j_1..j_N] * prod_{l != n} A_l[j_l, p].
+ * A: host array of `order` device pointers (A[mode] is ignored and may be NULL).
+ * P: I_mode x r float32, row-major, overwritten. float32 tensors use float32 matrix
+ * cores, bfloat16 tensors use bfloat16 matrix cores; both accumulate in float32. The
+ * Khatri-Rao rows are formed on chip and never written to memory. Deterministic. */
+ntf_status ntf_mttkrp(ntf_handle* h, const ntf_tensor* T, const float* const* A, int32_t r,
+                      int32_t mode, float* P, void* stream);
+
+/* Hadamard product of factor Grams, G = (*)_{l != exclude} A_l^T A_l (r x r, row-major);
+ * with exclude = n this is (B^(n))^T B^(n) (Appendix A gradient; Sec. 2.2 Lipschitz
+ * matrix). rows: host array of the I_l. exclude = -1 multiplies all `nfac` Grams.
+ * Grams accumulate in float64. G32 (float) and/or G64 (double) may be NULL, not both. */
+ntf_status ntf_gram(ntf_handle* h, const float* const* A, const int64_t* rows, int32_t nfac,
+                    int32_t r, int32_t exclude, float* G32, double* G64, void* stream);
+
+/* A-HALS on one block (Sec. 2.1.4): repeated cyclic sweeps over the columns j = 1..r,
+ * W[:, j] <- max(0, P[:, j] - sum_{l != j} W[:, l] G[l, j]) / G[j, j], stopping after
+ * max_sweeps sweeps or after the first sweep s with ||W_s - W_{s-1}||_F <= tol *
+ * ||W_1 - W_0||_F (Sec. 4.1; norms in float64). tol = 0 runs until a sweep changes
+ * nothing or max_sweeps is reached. A column with G[j, j] = 0 is set to 0.
+ * W: rows x r, in place (input = warm start). P: rows x r. G: r x r float32, symmetric.
+ * sweeps_done: device int32 or NULL. rows <= 8192 for r <= 32, <= 4096 otherwise. */
+ntf_status ntf_hals_update(ntf_handle* h, float* W, const float* P, const float* G,
+                           int64_t rows, int32_t r, int32_t max_sweeps, double tol,
+                           int32_t* sweeps_done, void* stream);
+
+/* One HER step of Algorithm 2 on caller buffers.
+ *  INIT:        state <- {beta0, 1, *fhat, ...}; `fhat` must point to F(A_0).
+ *  EXTRAPOLATE: block `block`: eq. extproj_her, A_hat = max(0, A_new + beta (A_new - A)),
+ *               with beta = state->beta (= beta_{k-1}); computed in float64, stored float32.
+ *  DECIDE:      Algorithm 2 restart test with *fhat = F-hat_k: if F-hat_k > F-hat_{k-1}
+ *               restart (beta_bar <- beta, beta <- beta / eta; A[l] <- A_new[l]), else
+ *               accept (beta <- min(beta_bar, gamma beta), beta_bar <- min(1, gamma_bar
+ *               beta_bar); A[l] <- A_hat[l]) for every block l (eqs. HER_eq:beta_update,
+ *               HER_eq:beta_bar_update). Equality accepts.
+ * nblocks/rows/A/A_new/A_hat describe all blocks (rows: host array). `block` is used by
+ * EXTRAPOLATE only; `params` by INIT and DECIDE; `fhat` (device double) by INIT and DECIDE. */
+ntf_status ntf_her_step(ntf_handle* h, ntf_her_op op, ntf_her_state* state,
+                        const ntf_her_params* params, int32_t nblocks, const int64_t* rows,
+                        int32_t r, float* const* A, float* const* A_new, float* const* A_hat,
+                        int32_t block, const double* fhat, void* stream);
+
+/* Restart surrogate (Sec. 3.1.3; Algorithm 2's F-hat) from the last block's quantities:
+ * F = 1/2 (||T||^2 - 2 <P, A> + <G, A^T A>), all in float64. normT2: device double.
+ * P, A: rows x r float32; G: r x r float64. fhat: device double (overwritten). */
+ntf_status ntf_error(ntf_handle* h, const double* normT2, const float* P, const float* A,
+                     const double* G, int64_t rows, int32_t r, double* fhat, void* stream);
+
+/* Algorithm 2 (HER) with A-HALS blocks for `iters` outer iterations (Sec. 3.1). The
+ * factors A (host array of `order` device pointers) hold A_0 on entry and the final
+ * iterates on return. state (device, may be NULL): if `resume` is nonzero it must hold
+ * the state a previous ntf_solve left and A its factors; otherwise it is initialized
+ * (beta0, beta_bar = 1, F-hat_0 = F(A_0)). On return it holds the final state. trace may
+ * be NULL. The outer iteration is captured once into a HIP graph and replayed.
+ * The solver runs A-HALS with the stopping rule of `params` and the restart test on
+ * F-hat in float64 on the device; the host never synchronizes inside the loop. */
+ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, float* const* A,
+                     const ntf_her_params* params, int32_t iters, ntf_her_state* state,
+                     int32_t resume, const ntf_trace* trace, void* stream);
+
+/* || T - [[A_1..A_N]] ||_F^2 from the explicit residual, float64 accumulation (the data
+ * fitting error of Sec. 4.1, eq. err_true_def, times 2). out: device double. */
+ntf_status ntf_residual_norm2(ntf_handle* h, const ntf_tensor* T, const float* const* A,
+                              int32_t r, double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NTF_H */

@@ -23,7 +23,7 @@ loss    : the squared-error loss without the 1/2 and its gradient.
 tucker  : the Tucker-compressed objective and its gradient (Appendix A).
 """
 from .tensor import (kron_columns, khatri_rao, unfold, fold, kruskal, block_matrix, mttkrp,
-                     gram, hadamard_gram, objective, gradient)
+                     mttkrp_rows, gram, hadamard_gram, objective, gradient)
 from .hals import hals_column, hals
 from .her import (HERParams, extrapolate, update_beta, f_hat, her_solve, ao_solve,
                   HERResult)
@@ -32,6 +32,7 @@ from .loss import cp_loss, cp_loss_grad
 
 __all__ = [
     "kron_columns", "khatri_rao", "unfold", "fold", "kruskal", "block_matrix", "mttkrp",
+    "mttkrp_rows",
     "gram", "hadamard_gram", "objective", "gradient", "hals_column", "hals", "HERParams",
     "extrapolate", "update_beta", "f_hat", "her_solve", "ao_solve", "HERResult",
     "residual_norm", "relative_error", "fit", "factor_error", "cp_loss", "cp_loss_grad",

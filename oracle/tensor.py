@@ -115,6 +115,20 @@ def mttkrp(T: np.ndarray, factors, i: int) -> np.ndarray:
     return _unfold_fast(T, i) @ block_matrix(factors, i)
 
 
+def mttkrp_rows(T: np.ndarray, factors, i: int, rows) -> np.ndarray:
+    """Rows `rows` of the mode-i MTTKRP, (rows of T_[i]) B^(i), without unfolding all of T.
+
+    Row j of T_[i] is the slice of T at index j in mode i, read with the lowest remaining
+    mode fastest (the column order of `unfold`).
+    """
+    B = block_matrix(factors, i)
+    out = []
+    for j in rows:
+        row = np.ravel(np.take(np.asarray(T), j, axis=i), order="F").astype(np.float64)
+        out.append(row @ B)
+    return np.stack(out)
+
+
 def gram(A: np.ndarray) -> np.ndarray:
     """A^T A (r x r)."""
     A = np.asarray(A, dtype=np.float64)

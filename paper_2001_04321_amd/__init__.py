@@ -1,0 +1,244 @@
+"""NTF with HER-accelerated A-HALS on MI355X (gfx950): thin Python binding of libntf.so.
+
+Every function here marshals torch tensors (device memory, current stream) into the C ABI
+declared in include/ntf.h and calls it; all arithmetic runs in the library's HIP kernels.
+There is no CPU fallback: if libntf.so is missing the import of a call raises.
+
+Functions carry the C names: ntf_norm2, ntf_cast_bf16, ntf_mttkrp, ntf_gram,
+ntf_hals_update, ntf_her_step, ntf_error, ntf_solve, ntf_residual_norm2, plus the
+autograd loss in `paper_2001_04321_amd.autograd`.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _abi
+from ._abi import NtfError, check, i64_array, lib, ptr_array
+
+__all__ = [
+    "Handle", "HerParams", "NtfError", "handle", "ntf_norm2", "ntf_cast_bf16", "ntf_mttkrp",
+    "ntf_gram", "ntf_hals_update", "ntf_her_step", "ntf_error", "ntf_solve",
+    "ntf_residual_norm2", "ntf_device_flags", "new_state", "state_dict",
+]
+
+_DTYPES = {torch.float32: _abi.NTF_F32, torch.bfloat16: _abi.NTF_BF16}
+
+
+class Handle:
+    """Owns an ntf_handle on one device (workspace, cached graphs)."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        check(lib().ntf_handle_create(C.byref(h), int(device)))
+        self.ptr = h
+        self.device = int(device)
+
+    def close(self):
+        if self.ptr:
+            lib().ntf_handle_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_handles: dict[int, Handle] = {}
+
+
+def handle(device: int | None = None) -> Handle:
+    d = torch.cuda.current_device() if device is None else int(device)
+    if d not in _handles:
+        _handles[d] = Handle(d)
+    return _handles[d]
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None) -> int:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _tensor_desc(T: torch.Tensor) -> _abi.NtfTensor:
+    if T.dtype not in _DTYPES:
+        raise ValueError(f"tensor dtype {T.dtype} not supported (float32 or bfloat16)")
+    d = _abi.NtfTensor()
+    d.order = T.dim()
+    d.dtype = _DTYPES[T.dtype]
+    for i, s in enumerate(T.shape):
+        d.dims[i] = int(s)
+    d.data = _dev(T, "T")
+    return d
+
+
+def _h(h):
+    return (h or handle()).ptr
+
+
+@dataclass
+class HerParams:
+    """HER parameters (defaults of the paper's experiments) and inner stopping rule."""
+    beta0: float = 0.5
+    gamma: float = 1.05
+    gamma_bar: float = 1.01
+    eta: float = 1.5
+    max_inner: int = 50
+    inner_tol: float = 1e-2
+
+    def to_c(self) -> _abi.NtfHerParams:
+        p = _abi.NtfHerParams()
+        p.beta0, p.gamma, p.gamma_bar, p.eta = self.beta0, self.gamma, self.gamma_bar, self.eta
+        p.max_inner, p.reserved, p.inner_tol = int(self.max_inner), 0, float(self.inner_tol)
+        return p
+
+
+def new_state(device=None) -> torch.Tensor:
+    """Device buffer holding one ntf_her_state (opaque bytes)."""
+    n = C.sizeof(_abi.NtfHerState)
+    return torch.zeros(n, dtype=torch.uint8, device=device or "cuda")
+
+
+def state_dict(state: torch.Tensor) -> dict:
+    raw = bytes(state.cpu().numpy().tobytes())
+    s = _abi.NtfHerState.from_buffer_copy(raw)
+    return {f: getattr(s, f) for f, _ in _abi.NtfHerState._fields_}
+
+
+def ntf_norm2(T: torch.Tensor, out: torch.Tensor | None = None, h=None, stream=None):
+    out = torch.empty((), dtype=torch.float64, device=T.device) if out is None else out
+    d = _tensor_desc(T)
+    check(lib().ntf_norm2(_h(h), C.byref(d), _dev(out, "out", torch.float64), _stream(stream)))
+    return out
+
+
+def ntf_cast_bf16(x: torch.Tensor, h=None, stream=None) -> torch.Tensor:
+    out = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
+    check(lib().ntf_cast_bf16(_h(h), _dev(x, "x", torch.float32), out.data_ptr(), x.numel(),
+                              _stream(stream)))
+    return out
+
+
+def ntf_mttkrp(T: torch.Tensor, factors, mode: int, out: torch.Tensor | None = None, h=None,
+               stream=None) -> torch.Tensor:
+    r = int(factors[(mode + 1) % T.dim()].shape[1])
+    out = torch.empty((T.shape[mode], r), dtype=torch.float32, device=T.device) if out is None else out
+    d = _tensor_desc(T)
+    ptrs = ptr_array([(_dev(A, f"A[{l}]", torch.float32) if (A is not None and l != mode) else None)
+                      for l, A in enumerate(factors)])
+    check(lib().ntf_mttkrp(_h(h), C.byref(d), ptrs, r, int(mode), _dev(out, "P", torch.float32),
+                           _stream(stream)))
+    return out
+
+
+def ntf_gram(factors, exclude: int = -1, want32: bool = True, want64: bool = True, h=None,
+             stream=None):
+    r = int(factors[0].shape[1]) if exclude != 0 else int(factors[-1].shape[1])
+    dev = factors[0].device
+    G32 = torch.empty((r, r), dtype=torch.float32, device=dev) if want32 else None
+    G64 = torch.empty((r, r), dtype=torch.float64, device=dev) if want64 else None
+    ptrs = ptr_array([_dev(A, f"A[{l}]", torch.float32) for l, A in enumerate(factors)])
+    rows = i64_array([A.shape[0] for A in factors])
+    check(lib().ntf_gram(_h(h), ptrs, rows, len(factors), r, int(exclude),
+                         G32.data_ptr() if G32 is not None else None,
+                         G64.data_ptr() if G64 is not None else None, _stream(stream)))
+    return G32, G64
+
+
+def ntf_hals_update(W: torch.Tensor, P: torch.Tensor, G: torch.Tensor, max_sweeps: int = 50,
+                    tol: float = 1e-2, sweeps: torch.Tensor | None = None, h=None, stream=None):
+    """In-place A-HALS on W; returns a device int32 tensor with the sweeps done."""
+    sweeps = torch.zeros((), dtype=torch.int32, device=W.device) if sweeps is None else sweeps
+    rows, r = W.shape
+    check(lib().ntf_hals_update(_h(h), _dev(W, "W", torch.float32), _dev(P, "P", torch.float32),
+                                _dev(G, "G", torch.float32), rows, r, int(max_sweeps),
+                                float(tol), _dev(sweeps, "sweeps", torch.int32),
+                                _stream(stream)))
+    return sweeps
+
+
+def ntf_her_step(op: int, state: torch.Tensor, params: HerParams | None = None, A=(),
+                 A_new=(), A_hat=(), block: int = 0, fhat: torch.Tensor | None = None,
+                 h=None, stream=None):
+    p = (params or HerParams()).to_c()
+    nb = len(A)
+    r = int(A[0].shape[1]) if nb else 1
+    rows = i64_array([a.shape[0] for a in A]) if nb else None
+    pa = ptr_array([_dev(a, "A", torch.float32) for a in A]) if nb else None
+    pn = ptr_array([_dev(a, "A_new", torch.float32) for a in A_new]) if nb else None
+    ph = ptr_array([_dev(a, "A_hat", torch.float32) for a in A_hat]) if nb else None
+    check(lib().ntf_her_step(_h(h), int(op), _dev(state, "state"), C.byref(p), nb, rows, r,
+                             pa, pn, ph, int(block),
+                             _dev(fhat, "fhat", torch.float64) if fhat is not None else None,
+                             _stream(stream)))
+
+
+def ntf_error(normT2: torch.Tensor, P: torch.Tensor, A: torch.Tensor, G64: torch.Tensor,
+              out: torch.Tensor | None = None, h=None, stream=None) -> torch.Tensor:
+    out = torch.empty((), dtype=torch.float64, device=P.device) if out is None else out
+    rows, r = A.shape
+    check(lib().ntf_error(_h(h), _dev(normT2, "normT2", torch.float64),
+                          _dev(P, "P", torch.float32), _dev(A, "A", torch.float32),
+                          _dev(G64, "G", torch.float64), rows, r, _dev(out, "fhat", torch.float64),
+                          _stream(stream)))
+    return out
+
+
+def ntf_residual_norm2(T: torch.Tensor, factors, h=None, stream=None) -> torch.Tensor:
+    out = torch.empty((), dtype=torch.float64, device=T.device)
+    d = _tensor_desc(T)
+    ptrs = ptr_array([_dev(A, f"A[{l}]", torch.float32) for l, A in enumerate(factors)])
+    check(lib().ntf_residual_norm2(_h(h), C.byref(d), ptrs, int(factors[0].shape[1]),
+                                   out.data_ptr(), _stream(stream)))
+    return out
+
+
+def ntf_solve(T: torch.Tensor, factors, iters: int, params: HerParams | None = None,
+              state: torch.Tensor | None = None, resume: bool = False, trace: bool = True,
+              h=None, stream=None):
+    """Run `iters` HER outer iterations in place on `factors` (list of float32 tensors).
+
+    Returns (state, trace) where trace is a dict of device tensors (or None).
+    """
+    p = (params or HerParams()).to_c()
+    N = T.dim()
+    r = int(factors[0].shape[1])
+    dev = T.device
+    if state is None:
+        state = new_state(dev)
+    tr = None
+    ctr = None
+    if trace and iters > 0:
+        tr = dict(fhat=torch.zeros(iters, dtype=torch.float64, device=dev),
+                  beta=torch.zeros(iters, dtype=torch.float64, device=dev),
+                  beta_bar=torch.zeros(iters, dtype=torch.float64, device=dev),
+                  restart=torch.zeros(iters, dtype=torch.int32, device=dev),
+                  sweeps=torch.zeros((iters, N), dtype=torch.int32, device=dev))
+        ctr = _abi.NtfTrace(tr["fhat"].data_ptr(), tr["beta"].data_ptr(),
+                            tr["beta_bar"].data_ptr(), tr["restart"].data_ptr(),
+                            tr["sweeps"].data_ptr())
+    d = _tensor_desc(T)
+    ptrs = ptr_array([_dev(A, f"A[{l}]", torch.float32) for l, A in enumerate(factors)])
+    check(lib().ntf_solve(_h(h), C.byref(d), r, ptrs, C.byref(p), int(iters),
+                          _dev(state, "state"), 1 if resume else 0,
+                          C.byref(ctr) if ctr is not None else None, _stream(stream)))
+    return state, tr
+
+
+def ntf_device_flags(h=None, stream=None) -> int:
+    v = C.c_uint32()
+    check(lib().ntf_device_flags(_h(h), _stream(stream), C.byref(v)))
+    return int(v.value)

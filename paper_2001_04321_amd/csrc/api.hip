@@ -1,0 +1,415 @@
+// C-ABI entry points: handle lifetime, error reporting, argument validation and the
+// per-step calls of the hot path. Validation happens before any HIP call, so argument
+// errors leave the device and every caller buffer untouched.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "ntf_internal.h"
+
+namespace ntf {
+
+namespace {
+thread_local char g_err[1024] = "";
+
+// Makes the handle's device current for the duration of a call, then restores it.
+struct DeviceGuard {
+  int old = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old) != hipSuccess) old = -1;
+    if (old != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+  }
+};
+
+inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+ntf_status ensure_workspace(ntf_handle* h, size_t bytes) {
+  if (bytes <= h->ws_size) return NTF_OK;
+  NTF_HIP(hipDeviceSynchronize());
+  if (h->ws) {
+    NTF_HIP(hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_size = 0;
+  }
+  const size_t want = align_up(bytes + bytes / 4, size_t(1) << 20);
+  if (hipMalloc(&h->ws, want) != hipSuccess) {
+    (void)hipGetLastError();
+    h->ws = nullptr;
+    set_error("workspace allocation of %zu bytes failed", want);
+    return NTF_ENOMEM;
+  }
+  h->ws_size = want;
+  h->ws_generation += 1;
+  return NTF_OK;
+}
+
+ntf_status check_tensor(const ntf_tensor* T) {
+  NTF_RETURN_IF(!T, NTF_EINVAL, "tensor descriptor is NULL");
+  NTF_RETURN_IF(T->order < 2 || T->order > NTF_MAX_ORDER, NTF_EINVAL,
+                "tensor order %d outside [2, %d]", T->order, NTF_MAX_ORDER);
+  NTF_RETURN_IF(T->dtype != NTF_F32 && T->dtype != NTF_BF16, NTF_EINVAL,
+                "unsupported tensor dtype %d", T->dtype);
+  NTF_RETURN_IF(!T->data, NTF_EINVAL, "tensor data pointer is NULL");
+  NTF_RETURN_IF(reinterpret_cast<uintptr_t>(T->data) % 16 != 0, NTF_EINVAL,
+                "tensor data must be 16-byte aligned");
+  int64_t total = 1;
+  for (int l = 0; l < T->order; ++l) {
+    NTF_RETURN_IF(T->dims[l] < 1, NTF_EINVAL, "tensor dim %d is %lld (< 1)", l,
+                  (long long)T->dims[l]);
+    NTF_RETURN_IF(T->dims[l] > (int64_t(1) << 31) - 1, NTF_EUNSUPPORTED,
+                  "tensor dim %d exceeds 2^31-1", l);
+    NTF_RETURN_IF(total > (int64_t(1) << 62) / T->dims[l], NTF_EUNSUPPORTED,
+                  "tensor too large");
+    total *= T->dims[l];
+  }
+  // every mode view (L, I, R) must keep L and R below 2^31 (32-bit index arithmetic)
+  for (int n = 0; n < T->order; ++n) {
+    const ModeView v = make_mode_view(*T, n);
+    NTF_RETURN_IF(v.L >= (int64_t(1) << 31) || v.R >= (int64_t(1) << 31), NTF_EUNSUPPORTED,
+                  "mode %d: prefix/suffix extents must stay below 2^31", n);
+  }
+  return NTF_OK;
+}
+
+ntf_status check_rank(int32_t r) {
+  NTF_RETURN_IF(r < 1 || r > NTF_MAX_RANK, NTF_EINVAL, "rank %d outside [1, %d]", r,
+                NTF_MAX_RANK);
+  return NTF_OK;
+}
+
+ntf_status check_params(const ntf_her_params* p) {
+  NTF_RETURN_IF(!p, NTF_EINVAL, "params is NULL");
+  NTF_RETURN_IF(!(p->beta0 >= 0.0 && p->beta0 < 1.0), NTF_EINVAL, "beta0 must lie in [0, 1)");
+  NTF_RETURN_IF(!(1.0 <= p->gamma_bar && p->gamma_bar <= p->gamma && p->gamma <= p->eta),
+                NTF_EINVAL, "need 1 <= gamma_bar <= gamma <= eta");
+  NTF_RETURN_IF(p->max_inner < 1 || p->max_inner > kMaxSweeps, NTF_EINVAL,
+                "max_inner must lie in [1, %d]", kMaxSweeps);
+  NTF_RETURN_IF(!(p->inner_tol >= 0.0), NTF_EINVAL, "inner_tol must be >= 0");
+  NTF_RETURN_IF(p->reserved != 0, NTF_EINVAL, "reserved field must be 0");
+  return NTF_OK;
+}
+
+}  // namespace ntf
+
+using namespace ntf;
+
+#define NTF_GUARD(h)                                                   \
+  NTF_RETURN_IF(!(h), NTF_EINVAL, "handle is NULL");                   \
+  DeviceGuard guard_((h)->device);                                     \
+  NTF_RETURN_IF(!guard_.ok, NTF_EDEVICE, "cannot select device %d", (h)->device)
+
+extern "C" {
+
+const char* ntf_last_error(void) { return g_err; }
+
+const char* ntf_status_string(ntf_status s) {
+  switch (s) {
+    case NTF_OK: return "NTF_OK";
+    case NTF_EINVAL: return "NTF_EINVAL";
+    case NTF_ENOMEM: return "NTF_ENOMEM";
+    case NTF_EDEVICE: return "NTF_EDEVICE";
+    case NTF_EUNSUPPORTED: return "NTF_EUNSUPPORTED";
+    case NTF_ENUMERIC: return "NTF_ENUMERIC";
+  }
+  return "NTF_UNKNOWN";
+}
+
+const char* ntf_version(void) { return "ntf-her-gfx950 0.1"; }
+
+ntf_status ntf_handle_create(ntf_handle** out, int device) {
+  clear_error();
+  NTF_RETURN_IF(!out, NTF_EINVAL, "output handle pointer is NULL");
+  *out = nullptr;
+  int count = 0;
+  NTF_HIP(hipGetDeviceCount(&count));
+  NTF_RETURN_IF(device < 0 || device >= count, NTF_EINVAL, "device %d not present (%d devices)",
+                device, count);
+  DeviceGuard guard(device);
+  NTF_RETURN_IF(!guard.ok, NTF_EDEVICE, "cannot select device %d", device);
+  hipDeviceProp_t prop;
+  NTF_HIP(hipGetDeviceProperties(&prop, device));
+  NTF_RETURN_IF(std::strncmp(prop.gcnArchName, "gfx950", 6) != 0, NTF_EUNSUPPORTED,
+                "device %d is %s; this library is built for gfx950 only", device,
+                prop.gcnArchName);
+  ntf_handle* h = new ntf_handle();
+  h->device = device;
+  h->num_cus = prop.multiProcessorCount;
+  h->lds_per_block = prop.sharedMemPerBlock;
+  if (hipMalloc(&h->dev_flags, sizeof(uint32_t)) != hipSuccess) {
+    delete h;
+    set_error("flag allocation failed");
+    return NTF_ENOMEM;
+  }
+  if (hipMemset(h->dev_flags, 0, sizeof(uint32_t)) != hipSuccess ||
+      hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipFree(h->dev_flags);
+    delete h;
+    set_error("handle initialisation failed");
+    return NTF_EDEVICE;
+  }
+  *out = h;
+  return NTF_OK;
+}
+
+void ntf_handle_destroy(ntf_handle* h) {
+  if (!h) return;
+  DeviceGuard guard(h->device);
+  (void)hipDeviceSynchronize();
+  release_solve_graph(h);
+  if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->dev_flags) (void)hipFree(h->dev_flags);
+  delete h;
+}
+
+ntf_status ntf_device_flags(ntf_handle* h, void* stream, uint32_t* flags_out) {
+  clear_error();
+  NTF_GUARD(h);
+  NTF_RETURN_IF(!flags_out, NTF_EINVAL, "flags_out is NULL");
+  NTF_HIP(hipStreamSynchronize(as_stream(stream)));
+  uint32_t v = 0;
+  NTF_HIP(hipMemcpy(&v, h->dev_flags, sizeof(v), hipMemcpyDeviceToHost));
+  NTF_HIP(hipMemset(h->dev_flags, 0, sizeof(uint32_t)));
+  *flags_out = v;
+  return NTF_OK;
+}
+
+ntf_status ntf_norm2(ntf_handle* h, const ntf_tensor* T, double* out, void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_tensor(T);
+  if (st) return st;
+  NTF_RETURN_IF(!out, NTF_EINVAL, "out is NULL");
+  int64_t n = 1;
+  for (int l = 0; l < T->order; ++l) n *= T->dims[l];
+  st = ensure_workspace(h, sizeof(double) * norm2_partials() + 256);
+  if (st) return st;
+  NTF_HIP(launch_norm2(T->data, T->dtype, n, reinterpret_cast<double*>(h->ws), out,
+                       as_stream(stream)));
+  return NTF_OK;
+}
+
+ntf_status ntf_cast_bf16(ntf_handle* h, const float* src, uint16_t* dst, int64_t n,
+                         void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  NTF_RETURN_IF(n < 0, NTF_EINVAL, "n < 0");
+  if (n == 0) return NTF_OK;
+  NTF_RETURN_IF(!src || !dst, NTF_EINVAL, "src/dst is NULL");
+  NTF_RETURN_IF(reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 8,
+                NTF_EINVAL, "src must be 16-byte and dst 8-byte aligned");
+  NTF_HIP(launch_cast_bf16(src, dst, n, as_stream(stream)));
+  return NTF_OK;
+}
+
+ntf_status ntf_mttkrp(ntf_handle* h, const ntf_tensor* T, const float* const* A, int32_t r,
+                      int32_t mode, float* P, void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_tensor(T);
+  if (st) return st;
+  if ((st = check_rank(r))) return st;
+  NTF_RETURN_IF(mode < 0 || mode >= T->order, NTF_EINVAL, "mode %d outside [0, %d)", mode,
+                T->order);
+  NTF_RETURN_IF(!A || !P, NTF_EINVAL, "factor array or output is NULL");
+  FactorPtrs fp{};
+  for (int l = 0; l < T->order; ++l) {
+    if (l == mode) continue;
+    NTF_RETURN_IF(!A[l], NTF_EINVAL, "factor %d is NULL", l);
+    fp.p[l] = A[l];
+  }
+  fp.p[mode] = A[(mode + 1) % T->order];  // never read; keeps the slot non-null
+  const MttkrpPlan pl = plan_mttkrp(*T, mode, r, h->num_cus);
+  NTF_RETURN_IF(pl.chunks >= (int64_t(1) << 31), NTF_EUNSUPPORTED, "reduction too long");
+  st = ensure_workspace(h, pl.partial_floats() * sizeof(float) + 256);
+  if (st) return st;
+  NTF_HIP(launch_mttkrp(pl, T->data, fp, P, reinterpret_cast<float*>(h->ws), nullptr, 0,
+                        as_stream(stream)));
+  return NTF_OK;
+}
+
+ntf_status ntf_gram(ntf_handle* h, const float* const* A, const int64_t* rows, int32_t nfac,
+                    int32_t r, int32_t exclude, float* G32, double* G64, void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_rank(r);
+  if (st) return st;
+  NTF_RETURN_IF(nfac < 1 || nfac > NTF_MAX_ORDER, NTF_EINVAL, "nfac %d outside [1, %d]", nfac,
+                NTF_MAX_ORDER);
+  NTF_RETURN_IF(exclude < -1 || exclude >= nfac, NTF_EINVAL, "exclude %d outside [-1, %d)",
+                exclude, nfac);
+  NTF_RETURN_IF(!A || !rows, NTF_EINVAL, "factor or rows array is NULL");
+  NTF_RETURN_IF(!G32 && !G64, NTF_EINVAL, "both outputs are NULL");
+  GramJob job{};
+  HadamardJob hj{};
+  Arena dry;
+  for (int l = 0; l < nfac; ++l) {
+    if (l == exclude) continue;
+    NTF_RETURN_IF(!A[l], NTF_EINVAL, "factor %d is NULL", l);
+    NTF_RETURN_IF(rows[l] < 1, NTF_EINVAL, "rows[%d] < 1", l);
+    dry.take<double>(size_t(gram_chunks(rows[l])) * r * r);
+  }
+  st = ensure_workspace(h, dry.off + 256);
+  if (st) return st;
+  Arena ar{h->ws, 0};
+  for (int l = 0; l < nfac; ++l) {
+    if (l == exclude) continue;
+    double* part = ar.take<double>(size_t(gram_chunks(rows[l])) * r * r);
+    job.A[job.nfac] = A[l];
+    job.out[job.nfac] = part;
+    job.rows[job.nfac] = rows[l];
+    job.nfac++;
+    hj.part[hj.nfac] = part;
+    hj.nchunks[hj.nfac] = gram_chunks(rows[l]);
+    hj.nfac++;
+  }
+  hipStream_t s = as_stream(stream);
+  if (job.nfac > 0) NTF_HIP(launch_gram_partials(job, r, s));
+  NTF_HIP(launch_hadamard(hj, r, G32, G64, s));
+  return NTF_OK;
+}
+
+ntf_status ntf_hals_update(ntf_handle* h, float* W, const float* P, const float* G,
+                           int64_t rows, int32_t r, int32_t max_sweeps, double tol,
+                           int32_t* sweeps_done, void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_rank(r);
+  if (st) return st;
+  NTF_RETURN_IF(!W || !P || !G, NTF_EINVAL, "W, P or G is NULL");
+  NTF_RETURN_IF(rows < 1, NTF_EINVAL, "rows < 1");
+  NTF_RETURN_IF(max_sweeps < 1 || max_sweeps > kMaxSweeps, NTF_EINVAL,
+                "max_sweeps outside [1, %d]", kMaxSweeps);
+  NTF_RETURN_IF(!(tol >= 0.0), NTF_EINVAL, "tol must be >= 0");
+  NTF_RETURN_IF(!hals_supported(rows, r, h->num_cus), NTF_EUNSUPPORTED,
+                "A-HALS kernel supports r <= 128 and at most 256 workgroups of rows");
+  const int64_t nslots = hals_slot_count(rows, r, max_sweeps);
+  st = ensure_workspace(h, size_t(nslots) * sizeof(double) + 256);
+  if (st) return st;
+  hipStream_t s = as_stream(stream);
+  double* slots = reinterpret_cast<double*>(h->ws);
+  NTF_HIP(launch_fill_sentinel(slots, nslots, s));
+  HalsArgs a{};
+  a.W0 = W;
+  a.W = W;
+  a.P = P;
+  a.G = G;
+  a.rows = rows;
+  a.r = r;
+  a.max_sweeps = max_sweeps;
+  a.tol = tol;
+  a.sweeps_out = sweeps_done;
+  a.slots = slots;
+  a.flags = h->dev_flags;
+  NTF_HIP(launch_hals(a, h->num_cus, s));
+  return NTF_OK;
+}
+
+ntf_status ntf_her_step(ntf_handle* h, ntf_her_op op, ntf_her_state* state,
+                        const ntf_her_params* params, int32_t nblocks, const int64_t* rows,
+                        int32_t r, float* const* A, float* const* A_new, float* const* A_hat,
+                        int32_t block, const double* fhat, void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  NTF_RETURN_IF(!state, NTF_EINVAL, "state is NULL");
+  hipStream_t s = as_stream(stream);
+  if (op == NTF_HER_INIT) {
+    ntf_status st = check_params(params);
+    if (st) return st;
+    NTF_RETURN_IF(!fhat, NTF_EINVAL, "INIT needs fhat = F(A_0)");
+    NTF_HIP(launch_her_init(state, *params, fhat, s));
+    return NTF_OK;
+  }
+  ntf_status st = check_rank(r);
+  if (st) return st;
+  NTF_RETURN_IF(nblocks < 1 || nblocks > NTF_MAX_ORDER, NTF_EINVAL, "nblocks outside [1, %d]",
+                NTF_MAX_ORDER);
+  NTF_RETURN_IF(!rows || !A || !A_new || !A_hat, NTF_EINVAL, "block arrays are NULL");
+  if (op == NTF_HER_EXTRAPOLATE) {
+    NTF_RETURN_IF(block < 0 || block >= nblocks, NTF_EINVAL, "block %d outside [0, %d)", block,
+                  nblocks);
+    NTF_RETURN_IF(!A[block] || !A_new[block] || !A_hat[block], NTF_EINVAL,
+                  "block %d has a NULL buffer", block);
+    NTF_RETURN_IF(rows[block] < 1, NTF_EINVAL, "rows[%d] < 1", block);
+    NTF_HIP(launch_extrapolate(A_new[block], A[block], A_hat[block], rows[block] * r,
+                               &state->beta, s));
+    return NTF_OK;
+  }
+  NTF_RETURN_IF(op != NTF_HER_DECIDE, NTF_EINVAL, "unknown op %d", int(op));
+  if ((st = check_params(params))) return st;
+  NTF_RETURN_IF(!fhat, NTF_EINVAL, "DECIDE needs fhat");
+  SelectJob j{};
+  j.nblocks = nblocks;
+  for (int b = 0; b < nblocks; ++b) {
+    NTF_RETURN_IF(!A[b] || !A_new[b] || !A_hat[b], NTF_EINVAL, "block %d has a NULL buffer", b);
+    NTF_RETURN_IF(rows[b] < 1, NTF_EINVAL, "rows[%d] < 1", b);
+    j.dst[b] = A[b];
+    j.a_new[b] = A_new[b];
+    j.a_hat[b] = A_hat[b];
+    j.n[b] = rows[b] * r;
+  }
+  DecideArgs d{};
+  d.st = state;
+  d.p = *params;
+  d.fhat = fhat;
+  d.flags = h->dev_flags;
+  d.order = nblocks;
+  NTF_HIP(launch_her_decide(d, s));
+  NTF_HIP(launch_select(j, state, s));
+  return NTF_OK;
+}
+
+ntf_status ntf_error(ntf_handle* h, const double* normT2, const float* P, const float* A,
+                     const double* G, int64_t rows, int32_t r, double* fhat, void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_rank(r);
+  if (st) return st;
+  NTF_RETURN_IF(!normT2 || !P || !A || !G || !fhat, NTF_EINVAL, "NULL argument");
+  NTF_RETURN_IF(rows < 1, NTF_EINVAL, "rows < 1");
+  const int64_t np = error_partial_count(rows, r);
+  st = ensure_workspace(h, size_t(np) * sizeof(double) + 256);
+  if (st) return st;
+  hipStream_t s = as_stream(stream);
+  double* part = reinterpret_cast<double*>(h->ws);
+  NTF_HIP(launch_error_partials(P, A, G, rows, r, part, s));
+  NTF_HIP(launch_error_finalize(normT2, part, np, fhat, h->dev_flags, s));
+  return NTF_OK;
+}
+
+ntf_status ntf_residual_norm2(ntf_handle* h, const ntf_tensor* T, const float* const* A,
+                              int32_t r, double* out, void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_tensor(T);
+  if (st) return st;
+  if ((st = check_rank(r))) return st;
+  NTF_RETURN_IF(!A || !out, NTF_EINVAL, "NULL argument");
+  FactorPtrs fp{};
+  for (int l = 0; l < T->order; ++l) {
+    NTF_RETURN_IF(!A[l], NTF_EINVAL, "factor %d is NULL", l);
+    fp.p[l] = A[l];
+  }
+  st = ensure_workspace(h, sizeof(double) * residual_partials() + 256);
+  if (st) return st;
+  NTF_HIP(launch_residual(*T, fp, r, reinterpret_cast<double*>(h->ws), out, as_stream(stream)));
+  return NTF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,237 @@
+// Internal declarations of the NTF library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstddef>
+#include <cstdint>
+#include <type_traits>
+
+#include "ntf.h"
+
+namespace ntf {
+
+// ------------------------------------------------------------------------- errors ---
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+
+#define NTF_RETURN_IF(cond, status, ...)  \
+  do {                                    \
+    if (cond) {                           \
+      ::ntf::set_error(__VA_ARGS__);      \
+      return (status);                    \
+    }                                     \
+  } while (0)
+
+#define NTF_HIP(expr)                                                           \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      ::ntf::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
+                       __FILE__, __LINE__);                                     \
+      return NTF_EDEVICE;                                                       \
+    }                                                                           \
+  } while (0)
+
+// Launch-error check after a kernel launch.
+#define NTF_LAUNCHED() NTF_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------- constants ---
+constexpr int kMaxOrder = NTF_MAX_ORDER;
+constexpr int kMaxRank = NTF_MAX_RANK;
+constexpr int kGramChunk = 64;        // rows per Gram partial (LDS: 64 x r floats)
+constexpr int kMaxSweeps = 1000;      // upper bound accepted for max_inner
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
+
+// Pointers to the factors of one problem, passed to kernels by value.
+struct FactorPtrs {
+  const float* p[kMaxOrder];
+};
+
+// Tensor geometry seen from mode n: T viewed as (L, I_n, R), C-order.
+struct ModeView {
+  int order;
+  int mode;
+  int64_t dims[kMaxOrder];
+  int64_t L;   // prod_{l < n} I_l
+  int64_t I;   // I_n
+  int64_t R;   // prod_{l > n} I_l
+};
+ModeView make_mode_view(const ntf_tensor& T, int mode);
+
+// --------------------------------------------------------------- workspace arena ---
+// Bump allocator over the handle's device workspace. Sizes are computed first with a
+// dry run (base == nullptr), so a call can grow the workspace once before enqueueing.
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct SolveGraph;  // defined in solve.hip
+
+}  // namespace ntf
+
+struct ntf_handle {
+  int device = 0;
+  int num_cus = 256;
+  size_t lds_per_block = 65536;
+  char* ws = nullptr;          // general workspace
+  size_t ws_size = 0;
+  uint64_t ws_generation = 0;  // bumped on every reallocation
+  uint32_t* dev_flags = nullptr;
+  hipStream_t capture_stream = nullptr;
+  ntf::SolveGraph* graph = nullptr;
+};
+
+namespace ntf {
+
+// Destroy the handle's cached solver graph (if any).
+void release_solve_graph(ntf_handle* h);
+
+// Make sure the handle's workspace holds at least `bytes` (synchronizes the device when
+// it has to grow, invalidating cached graphs).
+ntf_status ensure_workspace(ntf_handle* h, size_t bytes);
+
+// Validation helpers shared by the entry points (set the thread-local error message).
+ntf_status check_tensor(const ntf_tensor* T);
+ntf_status check_rank(int32_t r);
+ntf_status check_params(const ntf_her_params* p);
+
+// --------------------------------------------------------------- kernel launchers ---
+// Every launcher enqueues on `s` and returns hipSuccess or the launch error.
+
+// ||T||^2 into *out (float64). `partials` holds at least norm2_partials() doubles.
+int norm2_partials();
+hipError_t launch_norm2(const void* data, int dtype, int64_t n, double* partials, double* out,
+                        hipStream_t s);
+hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t n, hipStream_t s);
+
+// MTTKRP plan: chooses the kernel variant, tile and split count for one mode.
+struct MttkrpPlan {
+  ModeView v;
+  int dtype;
+  int r;
+  int rpad;        // r rounded up to the kernel's N tile
+  int variant;     // index into the kernel table
+  int layout;      // 0: reduction runs along the contiguous last index; 1: mode is last
+  int wm, wk;      // waves along rows / along the reduction
+  int64_t mtiles;  // row tiles
+  int64_t chunks;  // reduction chunks
+  int64_t splits;  // reduction splits (grid.y)
+  size_t partial_floats() const { return splits > 1 ? size_t(splits) * v.I * r : 0; }
+};
+MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus);
+// P (I x r) = MTTKRP. `partials` must hold plan.partial_floats() floats (may be null
+// when splits == 1). If `slots`/`nslots` are given, the final reduction also resets
+// those doubles to the inner-solver sentinel (saves a launch before A-HALS).
+hipError_t launch_mttkrp(const MttkrpPlan& plan, const void* T, const FactorPtrs& A, float* P,
+                         float* partials, double* slots, int64_t nslots, hipStream_t s);
+
+// Gram partials: for factor f (rows[f] x r), out[f] gets ceil(rows/kGramChunk) partial
+// r x r float64 Grams. Up to kMaxOrder factors per launch (blockIdx.y = factor).
+struct GramJob {
+  const float* A[kMaxOrder];
+  double* out[kMaxOrder];
+  int64_t rows[kMaxOrder];
+  int nfac;
+};
+int64_t gram_chunks(int64_t rows);
+hipError_t launch_gram_partials(const GramJob& job, int r, hipStream_t s);
+
+// Hadamard of summed Gram partials: G = prod_f sum_c part[f][c]. Writes G32 and/or G64.
+struct HadamardJob {
+  const double* part[kMaxOrder];
+  int64_t nchunks[kMaxOrder];
+  int nfac;
+};
+hipError_t launch_hadamard(const HadamardJob& job, int r, float* G32, double* G64,
+                           hipStream_t s);
+
+// A-HALS on one block. `slots` holds hals_slot_count(rows, r, max_sweeps) doubles that
+// are set to the sentinel (launch_fill_sentinel) before the call.
+int64_t hals_slot_count(int64_t rows, int r, int max_sweeps);
+// Workgroups never exceed min(256, CU count) so that all of them are resident at once.
+bool hals_supported(int64_t rows, int r, int num_cus);
+hipError_t launch_fill_sentinel(double* slots, int64_t n, hipStream_t s);
+struct HalsArgs {
+  const float* W0;     // warm start (may equal W)
+  float* W;            // result
+  const float* P;
+  const float* G;      // r x r float32
+  int64_t rows;
+  int r;
+  int max_sweeps;
+  double tol;
+  int32_t* sweeps_out;  // may be null
+  double* slots;
+  uint32_t* flags;
+  // optional fused extrapolation: A_hat = max(0, W + beta (W - W0)), beta = *beta_src
+  float* A_hat;          // null: no extrapolation
+  const double* beta_src;
+};
+hipError_t launch_hals(const HalsArgs& a, int num_cus, hipStream_t s);
+
+// Extrapolate-project: out = max(0, a_new + beta (a_new - a_old)), beta = *beta_src.
+hipError_t launch_extrapolate(const float* a_new, const float* a_old, float* out, int64_t n,
+                              const double* beta_src, hipStream_t s);
+
+// Restart surrogate pieces: per-block partial sums of 2<p_i,a_i> - a_i^T G a_i (float64).
+int64_t error_partial_count(int64_t rows, int r);
+hipError_t launch_error_partials(const float* P, const float* A, const double* G, int64_t rows,
+                                 int r, double* partials, hipStream_t s);
+// F-hat = 1/2 (normT2 - sum partials) into *fhat.
+hipError_t launch_error_finalize(const double* normT2, const double* partials, int64_t nparts,
+                                 double* fhat, uint32_t* flags, hipStream_t s);
+
+// HER state kernels.
+hipError_t launch_her_init(ntf_her_state* st, const ntf_her_params& p, const double* fhat0,
+                           hipStream_t s);
+// Decide: F-hat from `fhat` (or from error partials when `partials` != null), update the
+// state, write the trace entry.
+struct DecideArgs {
+  ntf_her_state* st;
+  ntf_her_params p;
+  const double* fhat;         // used when partials == null
+  const double* normT2;       // with partials
+  const double* partials;
+  int64_t nparts;
+  double* fhat_out;           // may be null
+  ntf_trace trace;
+  int order;
+  const int32_t* sweeps_src;  // per-block sweep counters of this iteration (may be null)
+  uint32_t* flags;
+};
+hipError_t launch_her_decide(const DecideArgs& a, hipStream_t s);
+// After DECIDE: dst[b] <- restart ? a_new[b] : a_hat[b] for every block (and the same
+// selection for optional float64 side buffers).
+struct SelectJob {
+  float* dst[kMaxOrder];
+  const float* a_new[kMaxOrder];
+  const float* a_hat[kMaxOrder];
+  int64_t n[kMaxOrder];
+  double* ddst[kMaxOrder];
+  const double* dnew[kMaxOrder];
+  const double* dhat[kMaxOrder];
+  int64_t dn[kMaxOrder];
+  int nblocks;
+};
+hipError_t launch_select(const SelectJob& j, const ntf_her_state* st, hipStream_t s);
+hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_reset_call(ntf_her_state* st, hipStream_t s);
+
+// || T - [[A]] ||^2 (explicit residual, float64).
+int residual_partials();
+hipError_t launch_residual(const ntf_tensor& T, const FactorPtrs& A, int r, double* partials,
+                           double* out, hipStream_t s);
+
+}  // namespace ntf

@@ -1,0 +1,318 @@
+// ntf_solve: Algorithm 2 (HER) with A-HALS blocks, driven entirely on the device.
+//
+// One outer iteration (paper Algorithm 2; block problem eq. NNLS_her_exact, extrapolation
+// eq. extproj_her, restart test on F-hat, beta schedule eqs. HER_eq:beta_update /
+// HER_eq:beta_bar_update) is captured once into a HIP graph and replayed `iters` times:
+//
+//   for block n:  G^(n)   = Hadamard of cached Grams (A-hat_k for l < n, A_{k-1} for l > n)
+//                 P       = MTTKRP_n(T; A-hat_k^(l<n), A_{k-1}^(l>n))      (the hot kernel)
+//                 A_new   = A-HALS(warm start A_{k-1}^(n); P, G^(n)), fused with
+//                 A_hat   = max(0, A_new + beta (A_new - A_{k-1}^(n)))
+//                 Grams of A_new and A_hat (float64 partials, cached)
+//   F-hat_k = 1/2 (||T||^2 - 2 <P_N, A_new^(N)> + <G^(N), A_new^T A_new>)   (Sec. 3.1.3)
+//   decide (restart / accept, beta update, trace) and select A_k (and its Gram cache).
+//
+// A-hat_{k-1} = A_{k-1} after every decision, so the caller's factor buffers always hold
+// the current iterate and every block needs only two extra buffers (A_new, A_hat). The
+// restart decision lives in device memory; the host never synchronizes inside the loop.
+#include <cstring>
+
+#include "ntf_internal.h"
+
+namespace ntf {
+
+struct SolveKey {
+  const void* T;
+  int32_t dtype, order, r;
+  int64_t dims[kMaxOrder];
+  float* A[kMaxOrder];
+  ntf_her_params p;
+  ntf_her_state* state;
+  ntf_trace trace;
+  uint64_t ws_generation;
+  bool operator==(const SolveKey& o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
+};
+
+struct SolveGraph {
+  SolveKey key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// Device buffers of one solve, carved from the handle's workspace.
+struct SolveBufs {
+  double* norm_part;
+  double* normT2;
+  double* fhat0;
+  ntf_her_state* state;
+  float* A_new[kMaxOrder];
+  float* A_hat[kMaxOrder];
+  double* gp_cur[kMaxOrder];
+  double* gp_new[kMaxOrder];
+  double* gp_hat[kMaxOrder];
+  float* G32;
+  double* G64;
+  float* P;
+  float* mt_part;
+  double* slots;
+  int64_t nslots;
+  int32_t* sweeps;
+  double* err_part;
+  int64_t nerr;
+};
+
+void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
+           const MttkrpPlan* plans, bool own_state) {
+  const int N = T.order;
+  const size_t rr = size_t(r) * r;
+  b.norm_part = ar.take<double>(norm2_partials());
+  b.normT2 = ar.take<double>(1);
+  b.fhat0 = ar.take<double>(1);
+  b.state = own_state ? ar.take<ntf_her_state>(1) : nullptr;
+  int64_t maxI = 0;
+  size_t maxpart = 0;
+  int64_t maxslots = 0;
+  for (int n = 0; n < N; ++n) {
+    const int64_t I = T.dims[n];
+    maxI = std::max(maxI, I);
+    b.A_new[n] = ar.take<float>(size_t(I) * r);
+    b.A_hat[n] = ar.take<float>(size_t(I) * r);
+    const size_t g = size_t(gram_chunks(I)) * rr;
+    b.gp_cur[n] = ar.take<double>(g);
+    b.gp_new[n] = ar.take<double>(g);
+    b.gp_hat[n] = ar.take<double>(g);
+    maxpart = std::max(maxpart, plans[n].partial_floats());
+    maxslots = std::max(maxslots, hals_slot_count(I, r, max_inner));
+  }
+  b.G32 = ar.take<float>(rr);
+  b.G64 = ar.take<double>(rr);
+  b.P = ar.take<float>(size_t(maxI) * r);
+  b.mt_part = ar.take<float>(std::max<size_t>(maxpart, 1));
+  b.nslots = maxslots;
+  b.slots = ar.take<double>(size_t(maxslots));
+  b.sweeps = ar.take<int32_t>(kMaxOrder);
+  b.nerr = std::max(error_partial_count(T.dims[N - 1], r),
+                    error_partial_count(T.dims[N - 1], r));
+  b.err_part = ar.take<double>(size_t(b.nerr));
+}
+
+FactorPtrs factors_for(int n, int N, float* const* A, const SolveBufs& b) {
+  FactorPtrs fp{};
+  for (int l = 0; l < N; ++l) fp.p[l] = l < n ? b.A_hat[l] : A[l];
+  fp.p[n] = A[n];  // not read by the MTTKRP
+  return fp;
+}
+
+// Enqueue one outer iteration on stream s.
+hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* const* A,
+                             const ntf_her_params& p, const SolveBufs& b,
+                             const MttkrpPlan* plans, const ntf_trace& trace, hipStream_t s) {
+  const int N = T.order;
+  hipError_t e;
+  for (int n = 0; n < N; ++n) {
+    const int64_t I = T.dims[n];
+    HadamardJob hj{};
+    for (int l = 0; l < N; ++l) {
+      if (l == n) continue;
+      hj.part[hj.nfac] = l < n ? b.gp_hat[l] : b.gp_cur[l];
+      hj.nchunks[hj.nfac] = gram_chunks(T.dims[l]);
+      hj.nfac++;
+    }
+    if ((e = launch_hadamard(hj, r, b.G32, b.G64, s)) != hipSuccess) return e;
+    const int64_t nslots = hals_slot_count(I, r, p.max_inner);
+    if ((e = launch_mttkrp(plans[n], T.data, factors_for(n, N, A, b), b.P, b.mt_part, b.slots,
+                           nslots, s)) != hipSuccess)
+      return e;
+    HalsArgs ha{};
+    ha.W0 = A[n];
+    ha.W = b.A_new[n];
+    ha.P = b.P;
+    ha.G = b.G32;
+    ha.rows = I;
+    ha.r = r;
+    ha.max_sweeps = p.max_inner;
+    ha.tol = p.inner_tol;
+    ha.sweeps_out = b.sweeps + n;
+    ha.slots = b.slots;
+    ha.flags = h->dev_flags;
+    ha.A_hat = b.A_hat[n];
+    ha.beta_src = &b.state->beta;
+    if ((e = launch_hals(ha, h->num_cus, s)) != hipSuccess) return e;
+    GramJob gj{};
+    gj.nfac = 2;
+    gj.A[0] = b.A_new[n];
+    gj.out[0] = b.gp_new[n];
+    gj.rows[0] = I;
+    gj.A[1] = b.A_hat[n];
+    gj.out[1] = b.gp_hat[n];
+    gj.rows[1] = I;
+    if ((e = launch_gram_partials(gj, r, s)) != hipSuccess) return e;
+  }
+  const int64_t IN = T.dims[N - 1];
+  if ((e = launch_error_partials(b.P, b.A_new[N - 1], b.G64, IN, r, b.err_part, s)) !=
+      hipSuccess)
+    return e;
+  DecideArgs d{};
+  d.st = b.state;
+  d.p = p;
+  d.normT2 = b.normT2;
+  d.partials = b.err_part;
+  d.nparts = error_partial_count(IN, r);
+  d.trace = trace;
+  d.order = N;
+  d.sweeps_src = b.sweeps;
+  d.flags = h->dev_flags;
+  if ((e = launch_her_decide(d, s)) != hipSuccess) return e;
+  SelectJob sj{};
+  sj.nblocks = N;
+  for (int l = 0; l < N; ++l) {
+    sj.dst[l] = A[l];
+    sj.a_new[l] = b.A_new[l];
+    sj.a_hat[l] = b.A_hat[l];
+    sj.n[l] = T.dims[l] * r;
+    sj.ddst[l] = b.gp_cur[l];
+    sj.dnew[l] = b.gp_new[l];
+    sj.dhat[l] = b.gp_hat[l];
+    sj.dn[l] = gram_chunks(T.dims[l]) * int64_t(r) * r;
+  }
+  return launch_select(sj, b.state, s);
+}
+
+}  // namespace
+
+void release_solve_graph(ntf_handle* h) {
+  if (!h->graph) return;
+  if (h->graph->exec) (void)hipGraphExecDestroy(h->graph->exec);
+  if (h->graph->graph) (void)hipGraphDestroy(h->graph->graph);
+  delete h->graph;
+  h->graph = nullptr;
+}
+
+}  // namespace ntf
+
+using namespace ntf;
+
+extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, float* const* A,
+                                const ntf_her_params* params, int32_t iters,
+                                ntf_her_state* state, int32_t resume, const ntf_trace* trace,
+                                void* stream) {
+  clear_error();
+  NTF_RETURN_IF(!h, NTF_EINVAL, "handle is NULL");
+  int old_dev = -1;
+  (void)hipGetDevice(&old_dev);
+  if (old_dev != h->device) NTF_HIP(hipSetDevice(h->device));
+  struct Restore {
+    int dev;
+    ~Restore() {
+      if (dev >= 0) (void)hipSetDevice(dev);
+    }
+  } restore{old_dev != h->device ? old_dev : -1};
+
+  ntf_status st = check_tensor(T);
+  if (st) return st;
+  if ((st = check_rank(r))) return st;
+  if ((st = check_params(params))) return st;
+  NTF_RETURN_IF(iters < 0, NTF_EINVAL, "iters < 0");
+  NTF_RETURN_IF(!A, NTF_EINVAL, "factor array is NULL");
+  NTF_RETURN_IF(resume && !state, NTF_EINVAL, "resume needs a state");
+  const int N = T->order;
+  for (int n = 0; n < N; ++n) {
+    NTF_RETURN_IF(!A[n], NTF_EINVAL, "factor %d is NULL", n);
+    NTF_RETURN_IF(!hals_supported(T->dims[n], r, h->num_cus), NTF_EUNSUPPORTED,
+                  "mode %d: A-HALS kernel supports r <= 128 and at most 256 row workgroups", n);
+  }
+  MttkrpPlan plans[kMaxOrder];
+  for (int n = 0; n < N; ++n) {
+    plans[n] = plan_mttkrp(*T, n, r, h->num_cus);
+    NTF_RETURN_IF(plans[n].chunks >= (int64_t(1) << 31), NTF_EUNSUPPORTED, "reduction too long");
+  }
+  ntf_trace tr{};
+  if (trace) tr = *trace;
+
+  Arena dry;
+  SolveBufs b{};
+  carve(dry, b, *T, r, params->max_inner, plans, state == nullptr);
+  if ((st = ensure_workspace(h, dry.off + 256))) return st;
+  Arena ar{h->ws, 0};
+  carve(ar, b, *T, r, params->max_inner, plans, state == nullptr);
+  if (state) b.state = state;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int64_t n_all = 1;
+  for (int l = 0; l < N; ++l) n_all *= T->dims[l];
+
+  // ---- set-up: ||T||^2, Gram cache of A, F-hat_0 = F(A_0) (or resume) ----
+  NTF_HIP(launch_norm2(T->data, T->dtype, n_all, b.norm_part, b.normT2, s));
+  GramJob gj{};
+  gj.nfac = N;
+  for (int l = 0; l < N; ++l) {
+    gj.A[l] = A[l];
+    gj.out[l] = b.gp_cur[l];
+    gj.rows[l] = T->dims[l];
+  }
+  NTF_HIP(launch_gram_partials(gj, r, s));
+  if (!resume) {
+    HadamardJob hj{};
+    for (int l = 0; l < N - 1; ++l) {
+      hj.part[hj.nfac] = b.gp_cur[l];
+      hj.nchunks[hj.nfac] = gram_chunks(T->dims[l]);
+      hj.nfac++;
+    }
+    NTF_HIP(launch_hadamard(hj, r, b.G32, b.G64, s));
+    FactorPtrs fp{};
+    for (int l = 0; l < N; ++l) fp.p[l] = A[l];
+    NTF_HIP(launch_mttkrp(plans[N - 1], T->data, fp, b.P, b.mt_part, nullptr, 0, s));
+    const int64_t IN = T->dims[N - 1];
+    NTF_HIP(launch_error_partials(b.P, A[N - 1], b.G64, IN, r, b.err_part, s));
+    NTF_HIP(launch_error_finalize(b.normT2, b.err_part, error_partial_count(IN, r), b.fhat0,
+                                  h->dev_flags, s));
+    NTF_HIP(launch_her_init(b.state, *params, b.fhat0, s));
+  } else {
+    NTF_HIP(launch_reset_call(b.state, s));
+  }
+  if (iters == 0) return NTF_OK;
+
+  // ---- capture (or reuse) the graph of one outer iteration ----
+  SolveKey key;
+  std::memset(&key, 0, sizeof(key));
+  key.T = T->data;
+  key.dtype = T->dtype;
+  key.order = N;
+  key.r = r;
+  for (int l = 0; l < N; ++l) {
+    key.dims[l] = T->dims[l];
+    key.A[l] = A[l];
+  }
+  key.p = *params;
+  key.state = b.state;
+  key.trace = tr;
+  key.ws_generation = h->ws_generation;
+  if (!h->graph || !(h->graph->key == key)) {
+    release_solve_graph(h);
+    SolveGraph* g = new SolveGraph();
+    g->key = key;
+    NTF_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed));
+    hipError_t e = enqueue_iteration(h, *T, r, A, *params, b, plans, tr, h->capture_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(h->capture_stream, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      delete g;
+      set_error("graph capture failed: %s / %s", hipGetErrorString(e), hipGetErrorString(e2));
+      return NTF_EDEVICE;
+    }
+    g->graph = graph;
+    hipError_t e3 = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      delete g;
+      set_error("graph instantiate failed: %s", hipGetErrorString(e3));
+      return NTF_EDEVICE;
+    }
+    h->graph = g;
+  }
+  for (int k = 0; k < iters; ++k) NTF_HIP(hipGraphLaunch(h->graph->exec, s));
+  return NTF_OK;
+}

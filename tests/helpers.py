@@ -1,0 +1,43 @@
+"""Shared helpers of the test suite (input marshalling, error measures, library build)."""
+import os
+
+import numpy as np
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2001_04321_amd", "libntf.so")
+
+
+def ensure_built():
+    """Build libntf.so if nothing is built yet (tests load what is built)."""
+    if not os.path.exists(LIB):
+        from paper_2001_04321_amd import build
+        build.build(verbose=False)
+
+
+def rel_fro(x, ref) -> float:
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = np.linalg.norm(ref.ravel())
+    return float(np.linalg.norm((x - ref).ravel()) / (den if den > 0 else 1.0))
+
+
+def dev_f32(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def dev_tensor(T, dtype: str):
+    """Device copy of T in float32 or bfloat16 and the float64 values it holds."""
+    import torch
+    T32 = np.ascontiguousarray(T, dtype=np.float32)
+    if dtype == "f32":
+        return torch.from_numpy(T32).cuda(), T32.astype(np.float64)
+    bits = synth.bf16_bits(T32)
+    t = torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16)
+    return t, synth.bf16_to_f32(bits).astype(np.float64)
+
+
+def to_np(t):
+    return t.detach().cpu().double().numpy()

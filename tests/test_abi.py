@@ -1,0 +1,74 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every function the
+header declares, and rejects NULL handles / bad arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from tests.helpers import ROOT, ensure_built
+
+HEADER = os.path.join(ROOT, "include", "ntf.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ntf_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    ensure_built()
+    from paper_2001_04321_amd import _abi
+    return _abi.lib()
+
+
+def test_header_declares_the_hot_path_calls():
+    names = _declared()
+    for n in ["ntf_mttkrp", "ntf_gram", "ntf_hals_update", "ntf_her_step", "ntf_error",
+              "ntf_solve", "ntf_norm2", "ntf_handle_create", "ntf_handle_destroy",
+              "ntf_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_2001_04321_amd import _abi
+    assert set(_declared()) == set(_abi.SIGNATURES)
+
+
+def test_version_and_status_strings(lib):
+    assert lib.ntf_version().decode().startswith("ntf")
+    assert lib.ntf_status_string(1) == b"NTF_EINVAL"
+    assert lib.ntf_status_string(4) == b"NTF_EUNSUPPORTED"
+
+
+def test_null_handle_is_rejected_without_device_work(lib):
+    from paper_2001_04321_amd import _abi
+    T = _abi.NtfTensor()
+    p = _abi.NtfHerParams(0.5, 1.05, 1.01, 1.5, 50, 0, 1e-2)
+    calls = [
+        lambda: lib.ntf_norm2(None, C.byref(T), None, None),
+        lambda: lib.ntf_mttkrp(None, C.byref(T), None, 4, 0, None, None),
+        lambda: lib.ntf_gram(None, None, None, 3, 4, -1, None, None, None),
+        lambda: lib.ntf_hals_update(None, None, None, None, 10, 4, 50, 1e-2, None, None),
+        lambda: lib.ntf_her_step(None, 0, None, C.byref(p), 3, None, 4, None, None, None, 0,
+                                 None, None),
+        lambda: lib.ntf_error(None, None, None, None, None, 10, 4, None, None),
+        lambda: lib.ntf_solve(None, C.byref(T), 4, None, C.byref(p), 10, None, 0, None, None),
+        lambda: lib.ntf_residual_norm2(None, C.byref(T), None, 4, None, None),
+        lambda: lib.ntf_cast_bf16(None, None, None, 4, None),
+    ]
+    for call in calls:
+        assert call() == _abi.NTF_EINVAL
+        assert b"handle" in lib.ntf_last_error()
+
+
+def test_handle_create_rejects_bad_pointer(lib):
+    from paper_2001_04321_amd import _abi
+    assert lib.ntf_handle_create(None, 0) == _abi.NTF_EINVAL

@@ -179,3 +179,14 @@ def test_gradient_matches_central_differences_and_gram_form():
             Am[i][idx] -= h
             fd[idx] = (oracle.objective(T, Ap) - oracle.objective(T, Am)) / (2 * h)
         assert np.allclose(grad, fd, rtol=1e-6, atol=1e-8)
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+def test_mttkrp_rows_match_full_mttkrp(dims):
+    g = np.random.default_rng(14)
+    T = g.random(dims)
+    A = _rand_factors(g, dims, 3)
+    for i in range(len(dims)):
+        P = _mttkrp_loops(T, A, i)
+        rows = list(range(dims[i]))
+        assert np.allclose(oracle.mttkrp_rows(T, A, i, rows), P, rtol=1e-13, atol=1e-13)
