@@ -1,21 +1,32 @@
-// Dense MTTKRP on gfx950 matrix cores.
+// Dense MTTKRP on gfx950 matrix cores, in factored form.
 //
-// P[i, p] = sum_{(a, b)} T[a, i, b] * K[(a, b), p],   K[(a,b), p] = prod_{l != n} A_l[j_l, p]
+//   P[i, p] = sum over all j_{-n} of T[j] * prod_{l != n} A_l[j_l, p]
 //
-// (paper Sec. 2, eqs. def:B and def:grad: the data term T_[n] B^(n)). T is viewed from
-// mode n as a C-order (L, I_n, R) array, L = prod_{l<n} I_l, R = prod_{l>n} I_l. The
-// reduction index (a, b) is split into chunks of KC consecutive values:
-//   layout 0 (R > 1): a chunk is one a and KC consecutive b, so each output row reads a
-//                     contiguous KC-element segment of T;
-//   layout 1 (R = 1): a chunk is KC consecutive a; rows i are contiguous in memory and the
-//                     tile is transposed while it is stored to LDS.
-// A workgroup (4 waves) owns MT = 32*WM output rows and a contiguous range of chunks
-// (one reduction split); WK waves share a chunk along the reduction. Per chunk it streams
-// the T tile from HBM into registers one chunk ahead, forms the Khatri-Rao rows of the
-// chunk in LDS from factor rows (never in HBM), and runs 32x32 MFMAs: float32 tensors on
-// v_mfma_f32_32x32x2_f32, bfloat16 tensors on v_mfma_f32_32x32x16_bf16, accumulating in
-// float32. Splits write partial tiles that a second kernel sums in a fixed order, so the
-// result is deterministic.
+// (paper Sec. 2, eqs. def:B and def:grad: the data term T_[n] B^(n)). Let v be the
+// fastest-varying mode other than n (the last mode, or mode N-2 when n is the last mode)
+// and let u enumerate the remaining modes in C order. The Khatri-Rao row of (u, v) is the
+// Hadamard product X[u] (*) A_v[v] with X[u][p] = prod_{l != n, v} A_l[u_l, p], so
+//
+//   P[i, p] = sum_u X[u][p] * Y_u[i, p],      Y_u[i, p] = sum_v T(u, i, v) A_v[v, p].
+//
+// Y_u is a plain matrix product whose right operand A_v is the same for every u: a
+// workgroup keeps a block of A_v in LDS as the MFMA B operand for its whole run, streams
+// T once from HBM as the A operand, and folds each Y_u into the float32 accumulators
+// with one FMA per accumulator register (X[u][p] is a per-lane scalar because the
+// accumulator column is the lane's column). The Khatri-Rao product is never formed,
+// neither in HBM nor in LDS.
+//
+// Layouts: case A (n < N-1): v is the last mode, so every output row reads a contiguous
+// run of T along v; lanes load their MFMA A fragments straight from global memory.
+// Case B (n = N-1): i is the contiguous index. float32: one element per lane per
+// v_mfma_f32_32x32x2_f32 step, already in MFMA layout (32 lanes cover 32 consecutive i).
+// bfloat16: the wave stages a 64 x 32 tile in LDS in memory order and reads it back with
+// ds_read_b64_tr_b16, which returns 4 consecutive v of one i per lane.
+//
+// Work split: grid = (row tiles of 32*WM rows, splits of the (v-block, u) sequence). WK
+// waves share a row tile and take interleaved 64-element (bf16) / 32-element (f32) chunks
+// of v; their accumulators are summed once at the end. Splits write partial tiles that
+// a second pass sums in a fixed order: the result is deterministic.
 #include "ntf_internal.h"
 
 namespace ntf {
@@ -23,30 +34,33 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
 
 constexpr int kThreads = 256;
+constexpr int kStageLd = 40;  // bf16 case-B staging row stride (32 columns + 8 pad)
 
-// Magic-number division for 0 <= x < 2^31 (Granlund-Montgomery round-up method):
-// q = (x * m) >> (31 + l) with l = ceil(log2 d), m = ceil(2^(31+l) / d) < 2^32.
+// Magic-number division for 0 <= x < 2^31 (round-up method of Granlund and Montgomery):
+// q = floor(x * m / 2^(31 + l)), l = ceil(log2 d), m = ceil(2^(31 + l) / d) < 2^32.
 struct FastDiv {
   uint32_t d;
   uint32_t m;
-  uint32_t sh;  // l - 1 (shift applied to the high product word), or 0xffffffff for d == 1
+  uint32_t sh;  // l - 1, or 0xffffffff for d == 1
 };
 
 FastDiv make_fastdiv(uint32_t d) {
   FastDiv f;
   f.d = d;
-  if (d == 1) {
+  if (d <= 1) {
+    f.d = 1;
     f.m = 0;
     f.sh = 0xffffffffu;
     return f;
   }
   uint32_t l = 0;
   while ((uint64_t(1) << l) < d) ++l;
-  __uint128_t num = (__uint128_t(1) << (31 + l));
-  uint64_t m = uint64_t((num + d - 1) / d);
-  f.m = uint32_t(m);
+  const unsigned __int128 num = (unsigned __int128)1 << (31 + l);
+  f.m = uint32_t((num + d - 1) / d);
   f.sh = l - 1;
   return f;
 }
@@ -58,394 +72,380 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f) {
 
 struct KArgs {
   const void* T;
-  float* out;               // P (splits == 1) or partials
-  FactorPtrs A;
-  int64_t L, I, R;          // mode view
-  int64_t chunks;           // total reduction chunks
-  int64_t nb;               // chunks per a (layout 0)
-  int64_t chunks_per_split; // floor
-  int64_t extra;            // first `extra` splits take one more chunk
-  int order, mode, r;
-  FastDiv fd[kMaxOrder];    // per-mode divisors
-  FastDiv fd_nb;            // divisor nb (chunk -> (a, b-chunk), layout 0)
-  int32_t dims[kMaxOrder];
-  int vec_ok;               // 16-byte vector loads allowed along the contiguous index
+  float* out;                  // P (one split) or partials [split][I][r]
+  const float* Av;             // I_v x r
+  const float* Ao[kMaxOrder];  // factors of the u modes, slowest first
+  FastDiv fd_o[kMaxOrder];
+  int n_o;
+  int64_t I, Iv, U;
+  int64_t R;                   // case A: row stride of T (prod of modes after n)
+  int64_t a_stride;            // case A: T offset of one step of the modes before n
+  FastDiv fd_Rp;               // case A: u = a * Rp + b_hi, Rp = R / I_v
+  int64_t Rp;
+  int64_t per_split, extra;
+  int r;
+  int vb;                      // v-block length (multiple of the chunk)
+  int ub;                      // u values per X batch
+  int vec_ok;
 };
 
-template <bool BF16>
-struct Cfg {
-  static constexpr int S = BF16 ? 2 : 4;       // bytes per element
-  static constexpr int KCW = BF16 ? 64 : 32;   // reduction elements per wave per chunk
-  static constexpr int VEC = 16 / S;           // elements per 16-byte vector
-  static constexpr int PAD = BF16 ? 8 : 1;     // LDS row padding (elements)
-};
-
-__device__ __forceinline__ float bf16_to_float(uint16_t h) {
-  return __uint_as_float(uint32_t(h) << 16);
-}
-
-__device__ __forceinline__ uint16_t float_to_bf16_rne(float f) {
-  uint32_t b = __float_as_uint(f);
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  const uint32_t b = __float_as_uint(f);
   if ((b & 0x7fffffffu) > 0x7f800000u) return uint16_t((b >> 16) | 0x40u);
   return uint16_t((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
 }
 
-// Mixed-radix digits of x over modes [lo, hi] (C order: mode hi fastest).
-__device__ __forceinline__ void digits_of(uint32_t x, int lo, int hi, const KArgs& k,
-                                          uint32_t* d) {
-  for (int l = hi; l >= lo; --l) {
-    uint32_t q = fdiv(x, k.fd[l]);
-    d[l] = x - q * k.fd[l].d;
-    x = q;
+// X[u][p] = prod over the u modes of A_l[u_l, p].
+__device__ __forceinline__ float x_value(const KArgs& k, uint32_t u, int p) {
+  float x = 1.f;
+  for (int q = k.n_o - 1; q >= 0; --q) {
+    const uint32_t qq = fdiv(u, k.fd_o[q]);
+    const uint32_t d = u - qq * k.fd_o[q].d;
+    u = qq;
+    x *= k.Ao[q][int64_t(d) * k.r + p];
   }
+  return x;
 }
 
-// E consecutive Khatri-Rao values  v[e] = scale * prod_{l in [lo,hi]} A_l[digit_l(x0+e), p]
-// (zero when x0 + e >= xmax or p >= r). Digits advance by one per element with carries.
-template <int E>
-__device__ __forceinline__ void kr_run(float (&v)[E], const KArgs& k, int lo, int hi,
-                                       uint32_t x0, int64_t xmax, int p, float scale) {
-  if (int64_t(x0) >= xmax) {  // whole run past the end: digits of x0 may be out of range
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = 0.f;
-    return;
-  }
-  if (p >= k.r || lo > hi) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = (p < k.r && int64_t(x0) + e < xmax) ? scale : 0.f;
-    return;
-  }
-  uint32_t d[kMaxOrder];
-  digits_of(x0, lo, hi, k, d);
-  const int r = k.r;
-  float head = scale;
-  for (int l = lo; l < hi; ++l) head *= k.A.p[l][int64_t(d[l]) * r + p];
-  const float* last = k.A.p[hi];
-  const uint32_t dim_last = uint32_t(k.dims[hi]);
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const bool ok = int64_t(x0) + e < xmax;
-    v[e] = ok ? head * last[int64_t(d[hi]) * r + p] : 0.f;
-    if (e + 1 < E) {
-      d[hi] += 1;
-      if (d[hi] == dim_last) {  // carry into the slower modes (rare)
-        d[hi] = 0;
-        int l = hi - 1;
-        while (l >= lo) {
-          d[l] += 1;
-          if (d[l] < uint32_t(k.dims[l])) break;
-          d[l] = 0;
-          --l;
-        }
-        head = scale;
-        for (int m = lo; m < hi; ++m) head *= k.A.p[m][int64_t(d[m]) * r + p];
-      }
-    }
-  }
+template <bool LAST>
+__device__ __forceinline__ int64_t t_base(const KArgs& k, uint32_t u) {
+  if (LAST) return int64_t(u) * k.Iv * k.I;
+  const uint32_t a = fdiv(u, k.fd_Rp);
+  const int64_t bhi = int64_t(u) - int64_t(a) * k.Rp;
+  return int64_t(a) * k.a_stride + bhi * k.Iv;
 }
 
-template <bool BF16, int NT, int WM, int WK, int LAYOUT>
+template <bool BF16, int NT, int WM, int WK, bool LAST>
 __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
-  using C = Cfg<BF16>;
-  constexpr int MT = 32 * WM;
-  constexpr int KC = C::KCW * WK;
   constexpr int RP = 32 * NT;
-  constexpr int LDT = KC + C::PAD;                 // T tile row stride ([m][k])
-  constexpr int LDK = BF16 ? (KC + C::PAD) : RP;   // KR tile stride: bf16 [p][k], f32 [k][p]
-  constexpr int T_ELEMS = MT * LDT;
-  constexpr int K_ELEMS = BF16 ? RP * LDK : KC * LDK;
-  constexpr int NV = (MT * KC * C::S) / (16 * kThreads);   // 16-byte vectors per thread
-  static_assert(NV >= 1, "tile too small");
+  constexpr int KCH = BF16 ? 64 : 32;
+  constexpr int MT = 32 * WM;
   using TE = typename std::conditional<BF16, uint16_t, float>::type;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
 
-  __shared__ __attribute__((aligned(16))) TE s_t[2][T_ELEMS];
-  __shared__ __attribute__((aligned(16))) TE s_k[2][K_ELEMS];
+  const int vb = k.vb;
+  const int ldb = BF16 ? vb + 8 : RP;
+  const size_t av_bytes = align_up(size_t(BF16 ? RP * ldb * 2 : vb * RP * 4), 16);
+  TE* s_av = reinterpret_cast<TE*>(smem);
+  float* s_x = reinterpret_cast<float*>(smem + av_bytes);
+  uint16_t* s_stage =
+      reinterpret_cast<uint16_t*>(smem + av_bytes + align_up(size_t(k.ub) * RP * 4, 16));
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave % WM;
   const int wk = wave / WM;
+  const int col = lane & 31;
+  const int half = lane >> 5;
   const int64_t i0 = int64_t(blockIdx.x) * MT;
+  const int64_t row = i0 + wm * 32 + col;  // case A / f32 case B: the lane's output row
+  const bool row_ok = row < k.I;
   const int64_t split = blockIdx.y;
-  const int64_t c_beg = split * k.chunks_per_split + (split < k.extra ? split : k.extra);
-  const int64_t c_end = c_beg + k.chunks_per_split + (split < k.extra ? 1 : 0);
+  const int64_t w_beg = split * k.per_split + (split < k.extra ? split : k.extra);
+  const int64_t w_end = w_beg + k.per_split + (split < k.extra ? 1 : 0);
   const TE* __restrict__ T = static_cast<const TE*>(k.T);
+  uint16_t* stage = s_stage + wave * 64 * kStageLd;
 
-  f32x16 acc[NT];
+  f32x16 acc[NT], y[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[nt][v] = 0.f;
+    for (int e = 0; e < 16; ++e) {
+      acc[nt][e] = 0.f;
+      y[nt][e] = 0.f;
+    }
 
-  // ---- T tile loads (one chunk ahead, in registers) ----
-  uint4 reg[NV];
-
-  auto load_tile = [&](int64_t c) {
-    if (LAYOUT == 0) {
-      const int64_t a = fdiv(uint32_t(c), k.fd_nb);
-      const int64_t b0 = (c - a * k.nb) * KC;
-      constexpr int VPR = KC / C::VEC;  // vectors per tile row
+  // One work item = (u, chunk kc of the current v-block) for this wave. Registers of one
+  // item: bf16 case A: 32 elements along v (4 x 16 B); f32 case A: 16 floats; f32 case B:
+  // 16 floats; bf16 case B: 4 x 16 B of the wave's 64 x 32 tile.
+  uint4 cur[4], nxt[4];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int q = v * kThreads + tid;
-        const int m = q / VPR;
-        const int kk = (q % VPR) * C::VEC;
-        const int64_t i = i0 + m;
-        const int64_t b = b0 + kk;
+  for (int q = 0; q < 4; ++q) cur[q] = nxt[q] = make_uint4(0, 0, 0, 0);
+
+  auto load_item = [&](uint4 (&reg)[4], int64_t base, int64_t v0c) {
+    if (!LAST) {
+      // lane (row, half): elements v0c + half*KCH/2 + [0, KCH/2) of its row
+      constexpr int EPL = KCH / 2;
+      const int64_t v = v0c + half * EPL;
+      const int64_t off = base + row * k.R + v;
+      if (row_ok && k.vec_ok && v + EPL <= k.Iv) {
+        const uint4* p = reinterpret_cast<const uint4*>(T + off);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) reg[q] = p[q];
+      } else {
+        TE tmp[EPL];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) tmp[e] = (row_ok && v + e < k.Iv) ? T[off + e] : TE(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) reg[q] = reinterpret_cast<uint4*>(tmp)[q];
+      }
+    } else if (!BF16) {
+      // lane (row, half): v = v0c + 2t + half, t = 0..15
+      float tmp[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int64_t v = v0c + 2 * t + half;
+        tmp[t] = (row_ok && v < k.Iv)
+                     ? reinterpret_cast<const float*>(T)[base + v * k.I + row]
+                     : 0.f;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) reg[q] = reinterpret_cast<uint4*>(tmp)[q];
+    } else {
+      // wave tile: 64 v rows x 32 i columns; lane loads rows q*16 + lane/4, columns
+      // (lane%4)*8 .. +8 (16 bytes), q = 0..3
+      const int c8 = (lane & 3) * 8;
+      const int64_t ic = i0 + wm * 32 + c8;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t v = v0c + q * 16 + (lane >> 2);
+        const int64_t off = base + v * k.I + ic;
         uint4 val = make_uint4(0, 0, 0, 0);
-        if (i < k.I) {
-          const int64_t off = (a * k.I + i) * k.R + b;
-          if (k.vec_ok && b + C::VEC <= k.R) {
+        if (v < k.Iv) {
+          if (k.vec_ok && ic + 8 <= k.I) {
             val = *reinterpret_cast<const uint4*>(T + off);
           } else {
-            TE tmp[C::VEC];
+            uint16_t tmp[8];
 #pragma unroll
-            for (int e = 0; e < C::VEC; ++e) tmp[e] = (b + e < k.R) ? T[off + e] : TE(0);
+            for (int e = 0; e < 8; ++e) tmp[e] = (ic + e < k.I) ? T[off + e] : uint16_t(0);
             val = *reinterpret_cast<uint4*>(tmp);
           }
         }
-        reg[v] = val;
-      }
-    } else {
-      const int64_t a0 = c * KC;
-      constexpr int VPR = MT / C::VEC;  // vectors per a-row of the tile
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int q = v * kThreads + tid;
-        const int kr = q / VPR;
-        const int ii = (q % VPR) * C::VEC;
-        const int64_t a = a0 + kr;
-        const int64_t i = i0 + ii;
-        uint4 val = make_uint4(0, 0, 0, 0);
-        if (a < k.L) {
-          const int64_t off = a * k.I + i;
-          if (k.vec_ok && i + C::VEC <= k.I) {
-            val = *reinterpret_cast<const uint4*>(T + off);
-          } else {
-            TE tmp[C::VEC];
-#pragma unroll
-            for (int e = 0; e < C::VEC; ++e) tmp[e] = (i + e < k.I) ? T[off + e] : TE(0);
-            val = *reinterpret_cast<uint4*>(tmp);
-          }
-        }
-        reg[v] = val;
+        reg[q] = val;
       }
     }
   };
 
-  auto store_tile = [&](int buf) {
-    TE* st = s_t[buf];
-    if (LAYOUT == 0) {
-      constexpr int VPR = KC / C::VEC;
+  auto compute_item = [&](const uint4 (&reg)[4], int kc) {
+    if (BF16 && !LAST) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int q = v * kThreads + tid;
-        const int m = q / VPR;
-        const int kk = (q % VPR) * C::VEC;
-        const TE* src = reinterpret_cast<const TE*>(&reg[v]);
-        if (BF16) {
-          *reinterpret_cast<uint4*>(&st[m * LDT + kk]) = reg[v];  // LDT*2 bytes is 16-aligned
-        } else {
-#pragma unroll
-          for (int e = 0; e < C::VEC; ++e) st[m * LDT + kk + e] = src[e];
-        }
-      }
-    } else {
-      constexpr int VPR = MT / C::VEC;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int q = v * kThreads + tid;
-        const int kr = q / VPR;
-        const int ii = (q % VPR) * C::VEC;
-        const TE* src = reinterpret_cast<const TE*>(&reg[v]);
-#pragma unroll
-        for (int e = 0; e < C::VEC; ++e) st[(ii + e) * LDT + kr] = src[e];
-      }
-    }
-  };
-
-  // ---- Khatri-Rao rows of a chunk into LDS ----
-  // Thread t owns column p = t % RP and E consecutive reduction positions.
-  constexpr int E = (KC * RP) / kThreads;
-  static_assert(E >= 1 && (KC * RP) % kThreads == 0, "KR split");
-  auto form_kr = [&](int64_t c, int buf) {
-    TE* sk = s_k[buf];
-    const int p = tid % RP;
-    const int kg = tid / RP;
-    const int kk0 = kg * E;
-    float v[E];
-    if (LAYOUT == 0) {
-      const int64_t a = fdiv(uint32_t(c), k.fd_nb);
-      const int64_t b0 = (c - a * k.nb) * KC + kk0;
-      // left product over modes [0, n-1] at a, right run over modes [n+1, N-1]
-      float left = 1.f;
-      if (p < k.r && k.mode > 0) {
-        uint32_t d[kMaxOrder];
-        digits_of(uint32_t(a), 0, k.mode - 1, k, d);
-        for (int l = 0; l < k.mode; ++l) left *= k.A.p[l][int64_t(d[l]) * k.r + p];
-      }
-      kr_run<E>(v, k, k.mode + 1, k.order - 1, uint32_t(b0), k.R, p, left);
-    } else {
-      const int64_t a0 = c * KC + kk0;
-      kr_run<E>(v, k, 0, k.order - 2, uint32_t(a0), k.L, p, 1.f);
-    }
-    if (BF16) {
-      // [p][k]: E consecutive k, 8 per 16-byte store
-#pragma unroll
-      for (int e0 = 0; e0 < E; e0 += 8) {
-        uint16_t h[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) h[e] = (e0 + e < E) ? float_to_bf16_rne(v[e0 + e]) : 0;
-        *reinterpret_cast<uint4*>(&sk[p * LDK + kk0 + e0]) = *reinterpret_cast<uint4*>(h);
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < E; ++e) reinterpret_cast<float*>(sk)[(kk0 + e) * LDK + p] = v[e];
-    }
-  };
-
-  // ---- MFMA over one chunk ----
-  auto compute = [&](int buf) {
-    const TE* st = s_t[buf];
-    const TE* sk = s_k[buf];
-    const int row = wm * 32 + (lane & 31);
-    const int half = lane >> 5;
-    const int kb = wk * C::KCW;
-    if (BF16) {
-#pragma unroll
-      for (int s = 0; s < C::KCW / 16; ++s) {
-        const int kk = kb + s * 16 + half * 8;
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&st[row * LDT + kk]);
+      for (int t = 0; t < 4; ++t) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&reg[t]);
+        const int kk = kc * KCH + half * 32 + t * 8;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          const bf16x8 b =
-              *reinterpret_cast<const bf16x8*>(&sk[(nt * 32 + (lane & 31)) * LDK + kk]);
-          acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[nt], 0, 0, 0);
+          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&s_av[(nt * 32 + col) * ldb + kk]);
+          y[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, y[nt], 0, 0, 0);
+        }
+      }
+    } else if (BF16 && LAST) {
+      // stage the tile in memory order; transposing reads give K-contiguous fragments
+      const int c8 = (lane & 3) * 8;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        *reinterpret_cast<uint4*>(&stage[(q * 16 + (lane >> 2)) * kStageLd + c8]) = reg[q];
+      const int g = lane >> 4;
+      const int m0 = 16 * (g & 1);
+      const int src = lane & 15;
+      const int jj = src >> 2;
+      const int s4 = (src & 3) * 4;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int kq = 16 * t + 8 * (g >> 1);
+        union {
+          i16x4 h[2];
+          bf16x8 v;
+        } a;
+        a.h[0] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (lds_i16x4*)(&stage[(kq + jj) * kStageLd + m0 + s4]));
+        a.h[1] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (lds_i16x4*)(&stage[(kq + 4 + jj) * kStageLd + m0 + s4]));
+        const int kk = kc * KCH + 16 * t + 8 * half;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&s_av[(nt * 32 + col) * ldb + kk]);
+          y[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, b, y[nt], 0, 0, 0);
         }
       }
     } else {
-      const float* stf = reinterpret_cast<const float*>(st);
-      const float* skf = reinterpret_cast<const float*>(sk);
+      const float* rf = reinterpret_cast<const float*>(reg);
+      const float* sf = reinterpret_cast<const float*>(s_av);
 #pragma unroll
-      for (int s = 0; s < C::KCW / 2; ++s) {
-        const int kk = kb + s * 2 + half;
-        const float a = stf[row * LDT + kk];
+      for (int t = 0; t < 16; ++t) {
+        const int kk = LAST ? kc * KCH + 2 * t + half : kc * KCH + half * 16 + t;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          const float b = skf[kk * LDK + nt * 32 + (lane & 31)];
-          acc[nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[nt], 0, 0, 0);
+          const float b = sf[kk * RP + nt * 32 + col];
+          y[nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(rf[t], b, y[nt], 0, 0, 0);
         }
       }
     }
   };
 
-  if (c_beg < c_end) {
-    load_tile(c_beg);
-    int buf = 0;
-    for (int64_t c = c_beg; c < c_end; ++c) {
-      store_tile(buf);
-      form_kr(c, buf);
+  int cur_vb = -1;
+  int64_t w = w_beg;
+  while (w < w_end) {
+    const int vbi = int(w / k.U);
+    const int64_t v0 = int64_t(vbi) * vb;
+    const int nkc = int(ceil_div(std::min<int64_t>(vb, k.Iv - v0), KCH));  // chunks with data
+    const int ipu = (nkc + WK - 1) / WK;                                 // items per u (this wave)
+    // ---- A_v block into LDS (zero beyond I_v and r) ----
+    if (vbi != cur_vb) {
       __syncthreads();
-      if (c + 1 < c_end) load_tile(c + 1);
-      compute(buf);
-      buf ^= 1;
+      for (int e = tid; e < vb * RP; e += kThreads) {
+        const int kk = e / RP;
+        const int p = e - kk * RP;
+        const int64_t v = v0 + kk;
+        const float val = (p < k.r && v < k.Iv) ? k.Av[v * k.r + p] : 0.f;
+        if (BF16)
+          reinterpret_cast<uint16_t*>(s_av)[p * ldb + kk] = f2bf(val);
+        else
+          reinterpret_cast<float*>(s_av)[kk * RP + p] = val;
+      }
+      cur_vb = vbi;
     }
-  }
+    // ---- a batch of u values within this v-block ----
+    const int64_t u0 = w - int64_t(vbi) * k.U;
+    const int64_t w_stop = std::min<int64_t>(w_end, int64_t(vbi + 1) * k.U);
+    const int nu = int(std::min<int64_t>(k.ub, w_stop - w));
+    __syncthreads();
+    for (int e = tid; e < nu * RP; e += kThreads) {
+      const int uu = e / RP;
+      const int p = e - uu * RP;
+      s_x[e] = p < k.r ? x_value(k, uint32_t(u0 + uu), p) : 0.f;
+    }
+    __syncthreads();
 
-  // ---- reduce the WK waves that share rows, then write ----
-  if (WK > 1) {
-    __syncthreads();
-    float* red = reinterpret_cast<float*>(&s_t[0][0]);  // reuse LDS
-    static_assert((WK - 1) * WM * 64 * 16 * NT * 4 <= 2 * T_ELEMS * (int)sizeof(TE) +
-                                                          2 * K_ELEMS * (int)sizeof(TE),
-                  "reduction scratch");
-    if (wk > 0) {
-      float* dst = red + ((wk - 1) * WM + wm) * (64 * 16 * NT);
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) dst[(nt * 16 + v) * 64 + lane] = acc[nt][v];
+    const int nitems = nu * ipu;
+    {
+      const int kc = wk;
+      if (kc < nkc) load_item(cur, t_base<LAST>(k, uint32_t(u0)), v0 + int64_t(kc) * KCH);
     }
-    __syncthreads();
-    if (wk == 0) {
-      for (int w = 1; w < WK; ++w) {
-        const float* src = red + ((w - 1) * WM + wm) * (64 * 16 * NT);
+    for (int it = 0; it < nitems; ++it) {
+      const int uu = it / ipu;
+      const int j = it - uu * ipu;
+      const int kc = wk + j * WK;
+      if (it + 1 < nitems) {
+        const int un = (it + 1) / ipu;
+        const int kn = wk + ((it + 1) - un * ipu) * WK;
+        if (kn < nkc)
+          load_item(nxt, t_base<LAST>(k, uint32_t(u0 + un)), v0 + int64_t(kn) * KCH);
+      }
+      if (j == 0) {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-          for (int v = 0; v < 16; ++v) acc[nt][v] += src[(nt * 16 + v) * 64 + lane];
+          for (int e = 0; e < 16; ++e) y[nt][e] = 0.f;
       }
+      if (kc < nkc) compute_item(cur, kc);
+      if (j == ipu - 1) {
+        const float* xs = s_x + uu * RP;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const float x = xs[nt * 32 + col];
+#pragma unroll
+          for (int e = 0; e < 16; ++e) acc[nt][e] = fmaf(x, y[nt][e], acc[nt][e]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
     }
+    w += nu;
   }
+
+  // ---- sum the WK waves of each row tile (fixed order), write rows < I, cols < r ----
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(smem);
+  if (WK > 1 && wk > 0) {
+    float* dst = red + ((wk - 1) * WM + wm) * (64 * 16 * NT);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) dst[(nt * 16 + e) * 64 + lane] = acc[nt][e];
+  }
+  __syncthreads();
   if (wk == 0) {
+    for (int ww = 1; ww < WK; ++ww) {
+      const float* src = red + ((ww - 1) * WM + wm) * (64 * 16 * NT);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[nt][e] += src[(nt * 16 + e) * 64 + lane];
+    }
     float* out = k.out + split * k.I * k.r;
-    const int col0 = lane & 31;
-    const int hi4 = (lane >> 5) * 4;
+    const int hi4 = half * 4;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const int p = nt * 32 + col0;
+      const int p = nt * 32 + col;
       if (p >= k.r) continue;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t i = i0 + wm * 32 + 8 * (v >> 2) + hi4 + (v & 3);
-        if (i < k.I) out[i * k.r + p] = acc[nt][v];
+      for (int e = 0; e < 16; ++e) {
+        const int64_t i = i0 + wm * 32 + 8 * (e >> 2) + hi4 + (e & 3);
+        if (i < k.I) out[i * k.r + p] = acc[nt][e];
       }
     }
   }
 }
 
-// Fixed-order sum of split partials; optionally resets inner-solver slots.
+// Fixed-order sum of split partials: each output element is summed by 4 threads over
+// interleaved splits (float64), then combined in thread order; optionally resets
+// inner-solver slots.
 __global__ __launch_bounds__(256) void mttkrp_reduce_kernel(const float* __restrict__ part,
                                                             int64_t splits, int64_t n,
                                                             float* __restrict__ P,
                                                             double* slots, int64_t nslots) {
-  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t e = tid; e < n; e += stride) {
-    double s = 0.0;
-    for (int64_t q = 0; q < splits; ++q) s += double(part[q * n + e]);
-    P[e] = float(s);
+  __shared__ double s[4][64];
+  const int o = threadIdx.x & 63;
+  const int g = threadIdx.x >> 6;
+  for (int64_t e0 = int64_t(blockIdx.x) * 64; e0 < n; e0 += int64_t(gridDim.x) * 64) {
+    const int64_t e = e0 + o;
+    double acc = 0.0;
+    if (e < n)
+      for (int64_t q = g; q < splits; q += 4) acc += double(part[q * n + e]);
+    s[g][o] = acc;
+    __syncthreads();
+    if (g == 0 && e < n) P[e] = float(((s[0][o] + s[1][o]) + s[2][o]) + s[3][o]);
+    __syncthreads();
   }
-  for (int64_t e = tid; e < nslots; e += stride)
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (int64_t e = tid; e < nslots; e += int64_t(gridDim.x) * blockDim.x)
     slots[e] = __longlong_as_double(-1ll);
 }
 
 using KernelFn = void (*)(KArgs);
 
-template <bool BF16, int NT, int WM, int WK, int LAYOUT>
+template <bool BF16, int NT, int WM, int WK, bool LAST>
 KernelFn pick() {
-  return mttkrp_kernel<BF16, NT, WM, WK, LAYOUT>;
+  return mttkrp_kernel<BF16, NT, WM, WK, LAST>;
 }
 
-// Instantiated shapes keep LDS <= ~65 KB (two or more workgroups per CU): the Khatri-Rao
-// tile grows with NT * WK, so wide ranks use WK = 1.
-template <bool BF16, int LAYOUT>
-KernelFn pick_w(int wm, int nt) {
+// WM x WK = 4 waves. Ranks above 64 use row tiles of at least 64 rows.
+template <bool BF16, bool LAST>
+KernelFn pick_shape(int wm, int nt) {
   if (nt == 1) {
-    if (wm == 1) return pick<BF16, 1, 1, 4, LAYOUT>();
-    if (wm == 2) return pick<BF16, 1, 2, 2, LAYOUT>();
-    return pick<BF16, 1, 4, 1, LAYOUT>();
+    if (wm == 1) return pick<BF16, 1, 1, 4, LAST>();
+    if (wm == 2) return pick<BF16, 1, 2, 2, LAST>();
+    return pick<BF16, 1, 4, 1, LAST>();
   }
   if (nt == 2) {
-    if (wm == 2) return pick<BF16, 2, 2, 2, LAYOUT>();
-    return pick<BF16, 2, 4, 1, LAYOUT>();
+    if (wm == 1) return pick<BF16, 2, 1, 4, LAST>();
+    if (wm == 2) return pick<BF16, 2, 2, 2, LAST>();
+    return pick<BF16, 2, 4, 1, LAST>();
   }
-  if (nt == 4) return pick<BF16, 4, 4, 1, LAYOUT>();
-  return pick<BF16, 8, 4, 1, LAYOUT>();
+  if (nt == 4) {
+    if (wm == 4) return pick<BF16, 4, 4, 1, LAST>();
+    return pick<BF16, 4, 2, 2, LAST>();
+  }
+  if (wm == 4) return pick<BF16, 8, 4, 1, LAST>();
+  return pick<BF16, 8, 2, 2, LAST>();
 }
 
-KernelFn select_kernel(bool bf16, int layout, int wm, int nt) {
-  if (bf16) return layout ? pick_w<true, 1>(wm, nt) : pick_w<true, 0>(wm, nt);
-  return layout ? pick_w<false, 1>(wm, nt) : pick_w<false, 0>(wm, nt);
+KernelFn select_kernel(bool bf16, bool last, int wm, int nt) {
+  if (bf16) return last ? pick_shape<true, true>(wm, nt) : pick_shape<true, false>(wm, nt);
+  return last ? pick_shape<false, true>(wm, nt) : pick_shape<false, false>(wm, nt);
 }
 
 int n_tiles(int r) {
-  int nt = (r + 31) / 32;
-  if (nt <= 1) return 1;
-  if (nt <= 2) return 2;
-  if (nt <= 4) return 4;
-  return 8;
+  const int nt = (r + 31) / 32;
+  return nt <= 1 ? 1 : nt <= 2 ? 2 : nt <= 4 ? 4 : 8;
+}
+
+size_t lds_bytes(bool bf16, bool last, int rp, int vb, int ub) {
+  const size_t av = bf16 ? size_t(rp) * (vb + 8) * 2 : size_t(vb) * rp * 4;
+  size_t b = align_up(av, 16) + align_up(size_t(ub) * rp * 4, 16);
+  if (bf16 && last) b += size_t(4) * 64 * kStageLd * 2;
+  return b;
 }
 
 }  // namespace
@@ -470,90 +470,103 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus) {
   pl.r = r;
   const int nt = n_tiles(r);
   pl.rpad = 32 * nt;
-  pl.layout = pl.v.R == 1 ? 1 : 0;
-  // rows per workgroup: the largest of 128 / 64 / 32 whose padding wastes <= 12.5%
-  // Allowed shapes: NT = 1 any WM; NT = 2 WM in {2, 4}; NT >= 4 WM = 4 (LDS budget).
+  pl.variant = nt;
+  const bool bf16 = T.dtype == NTF_BF16;
+  const bool last = mode == T.order - 1;
+  pl.layout = last ? 1 : 0;
+  pl.vmode = last ? T.order - 2 : T.order - 1;
+  pl.Iv = T.dims[pl.vmode];
+  pl.U = 1;
+  for (int l = 0; l < T.order; ++l)
+    if (l != mode && l != pl.vmode) pl.U *= T.dims[l];
+  // row tile: least padding among the instantiated shapes (ties: the taller tile)
   const int64_t I = pl.v.I;
-  const int wm_min = nt == 1 ? 1 : (nt == 2 ? 2 : 4);
-  pl.wm = 0;
+  const int wm_min = nt >= 4 ? 2 : 1;
+  int64_t best = -1;
+  pl.wm = 4;
   for (int wm : {4, 2, 1}) {
-    if (wm < wm_min) break;
-    const int64_t mt = 32 * wm;
-    const int64_t padded = ceil_div(I, mt) * mt;
-    if (padded * 8 <= I * 9) {
+    if (wm < wm_min) continue;
+    const int64_t padded = ceil_div(I, 32 * wm) * 32 * wm;
+    if (best < 0 || padded < best) {
+      best = padded;
       pl.wm = wm;
-      break;
-    }
-  }
-  if (pl.wm == 0) {  // no shape within 12.5% padding: take the least padded allowed one
-    int64_t best = -1;
-    for (int wm : {4, 2, 1}) {
-      if (wm < wm_min) break;
-      const int64_t padded = ceil_div(I, 32 * wm) * 32 * wm;
-      if (best < 0 || padded < best) {
-        best = padded;
-        pl.wm = wm;
-      }
     }
   }
   pl.wk = 4 / pl.wm;
-  const int kcw = T.dtype == NTF_BF16 ? 64 : 32;
-  const int64_t kc = int64_t(kcw) * pl.wk;
+  // v-block: all of I_v when its A_v block fits 64 KB of LDS
+  const int kch = bf16 ? 64 : 32;
+  const int64_t per_k = bf16 ? int64_t(pl.rpad) * 2 : int64_t(pl.rpad) * 4;
+  int64_t vbmax = (64 * 1024) / per_k - (bf16 ? 8 : 0);
+  vbmax = std::max<int64_t>(kch, vbmax / kch * kch);
+  const int64_t iv_pad = ceil_div(pl.Iv, kch) * kch;
+  pl.vb = int(std::min(iv_pad, vbmax));
+  pl.nvb = int(ceil_div(pl.Iv, pl.vb));
   pl.mtiles = ceil_div(I, 32 * pl.wm);
-  if (pl.layout == 0) {
-    const int64_t nb = ceil_div(pl.v.R, kc);
-    pl.chunks = pl.v.L * nb;
-  } else {
-    pl.chunks = ceil_div(pl.v.L, kc);
-  }
-  const int64_t target = int64_t(num_cus) * 4;
+  pl.chunks = pl.U * pl.nvb;  // work items (v-block, u)
+  const int64_t target = int64_t(num_cus) * 2;
   int64_t splits = ceil_div(target, pl.mtiles);
   splits = std::max<int64_t>(1, std::min<int64_t>(splits, pl.chunks));
   splits = std::min<int64_t>(splits, 65535);
   pl.splits = splits;
-  pl.variant = nt;
+  const int64_t per = ceil_div(pl.chunks, splits);
+  pl.ub = int(std::max<int64_t>(1, std::min<int64_t>({per, int64_t(8192 / pl.rpad), pl.U})));
+  // the end-of-kernel reduction of the WK waves reuses the same LDS
+  const size_t red = size_t(pl.wk - 1) * pl.wm * 64 * 16 * nt * sizeof(float);
+  pl.lds = std::max(lds_bytes(bf16, last, pl.rpad, pl.vb, pl.ub), red);
   return pl;
 }
 
 hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& A, float* P,
                          float* partials, double* slots, int64_t nslots, hipStream_t s) {
-  KArgs k;
+  KArgs k{};
   k.T = T;
-  k.A = A;
-  k.L = pl.v.L;
-  k.I = pl.v.I;
-  k.R = pl.v.R;
-  k.order = pl.v.order;
-  k.mode = pl.v.mode;
-  k.r = pl.r;
-  const bool bf16 = pl.dtype == NTF_BF16;
-  const int kcw = bf16 ? 64 : 32;
-  const int64_t kc = int64_t(kcw) * pl.wk;
-  k.nb = pl.layout == 0 ? ceil_div(pl.v.R, kc) : 1;
-  k.fd_nb = make_fastdiv(uint32_t(k.nb));
-  k.chunks = pl.chunks;
-  k.chunks_per_split = pl.chunks / pl.splits;
-  k.extra = pl.chunks % pl.splits;
-  for (int l = 0; l < kMaxOrder; ++l) {
-    const int64_t d = l < pl.v.order ? pl.v.dims[l] : 1;
-    k.dims[l] = int32_t(d);
-    k.fd[l] = make_fastdiv(uint32_t(d));
+  const int N = pl.v.order;
+  const int n = pl.v.mode;
+  const bool last = pl.layout == 1;
+  k.Av = A.p[pl.vmode];
+  k.n_o = 0;
+  for (int l = 0; l < N; ++l) {
+    if (l == n || l == pl.vmode) continue;
+    k.Ao[k.n_o] = A.p[l];
+    k.fd_o[k.n_o] = make_fastdiv(uint32_t(pl.v.dims[l]));
+    k.n_o++;
   }
+  k.I = pl.v.I;
+  k.Iv = pl.Iv;
+  k.U = pl.U;
+  k.R = pl.v.R;
+  k.a_stride = pl.v.I * pl.v.R;
+  k.Rp = last ? 1 : pl.v.R / pl.Iv;
+  k.fd_Rp = make_fastdiv(uint32_t(k.Rp));
+  k.per_split = pl.chunks / pl.splits;
+  k.extra = pl.chunks % pl.splits;
+  k.r = pl.r;
+  k.vb = pl.vb;
+  k.ub = pl.ub;
+  const bool bf16 = pl.dtype == NTF_BF16;
   const int vec = bf16 ? 8 : 4;
-  k.vec_ok = pl.layout == 0 ? (pl.v.R % vec == 0) : (pl.v.I % vec == 0);
+  k.vec_ok = last ? (pl.v.I % vec == 0) : (pl.v.R % vec == 0 && pl.Iv % vec == 0);
   const bool split = pl.splits > 1;
   k.out = split ? partials : P;
-  KernelFn fn = select_kernel(bf16, pl.layout, pl.wm, pl.variant);
+  KernelFn fn = select_kernel(bf16, last, pl.wm, pl.variant);
+  static bool attr_done[2][2][4][8] = {};
+  bool& done = attr_done[bf16][last][pl.wm - 1][pl.variant - 1];
+  if (!done) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    done = true;
+  }
   dim3 grid(unsigned(pl.mtiles), unsigned(pl.splits));
-  hipLaunchKernelGGL(fn, grid, dim3(kThreads), 0, s, k);
+  hipLaunchKernelGGL(fn, grid, dim3(kThreads), pl.lds, s, k);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (split || nslots > 0) {
-    const int64_t n = split ? pl.v.I * pl.r : 0;
-    const int64_t work = std::max<int64_t>(n, nslots);
-    const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(ceil_div(work, 256), 2048)));
+    const int64_t nout = split ? pl.v.I * pl.r : 0;
+    const int64_t work = std::max<int64_t>(ceil_div(nout, 64), ceil_div(nslots, 256));
+    const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(work, 4096)));
     hipLaunchKernelGGL(mttkrp_reduce_kernel, dim3(blocks), dim3(256), 0, s, partials,
-                       pl.splits, n, P, slots, nslots);
+                       pl.splits, nout, P, slots, nslots);
     e = hipGetLastError();
   }
   return e;

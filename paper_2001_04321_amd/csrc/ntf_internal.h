@@ -43,8 +43,8 @@ constexpr int kMaxRank = NTF_MAX_RANK;
 constexpr int kGramChunk = 64;        // rows per Gram partial (LDS: 64 x r floats)
 constexpr int kMaxSweeps = 1000;      // upper bound accepted for max_inner
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
-inline size_t align_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline size_t align_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
 
 // Pointers to the factors of one problem, passed to kernels by value.
 struct FactorPtrs {
@@ -122,12 +122,18 @@ struct MttkrpPlan {
   int dtype;
   int r;
   int rpad;        // r rounded up to the kernel's N tile
-  int variant;     // index into the kernel table
-  int layout;      // 0: reduction runs along the contiguous last index; 1: mode is last
-  int wm, wk;      // waves along rows / along the reduction
+  int variant;     // number of 32-column N tiles
+  int layout;      // 0: mode is not the last (v = last mode); 1: mode is the last
+  int wm, wk;      // waves along rows / along v
+  int vmode;       // the fastest other mode (its factor is the MFMA B operand)
+  int64_t Iv;      // I_v
+  int64_t U;       // product of the remaining other modes
+  int vb, nvb;     // v-block length and count
+  int ub;          // u values per X batch
+  size_t lds;      // dynamic LDS bytes
   int64_t mtiles;  // row tiles
-  int64_t chunks;  // reduction chunks
-  int64_t splits;  // reduction splits (grid.y)
+  int64_t chunks;  // work items (v-block, u)
+  int64_t splits;  // splits of the work items (grid.y)
   size_t partial_floats() const { return splits > 1 ? size_t(splits) * v.I * r : 0; }
 };
 MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus);
