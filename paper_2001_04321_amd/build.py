@@ -31,13 +31,21 @@ COMMON = [
 ]
 
 
+# per-file additions. A-HALS: without the atomic optimizer, the per-sweep arrival counter's
+# fetch-add is not rewritten into a form that waits for the returned value at once (the
+# value is first needed one sweep later).
+EXTRA = {
+    "k_hals.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
 def _compile(src: str, debug: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if debug:
         cmd += ["-g"]
     p = subprocess.run(cmd, capture_output=True, text=True)

@@ -239,7 +239,7 @@ ntf_status ntf_mttkrp(ntf_handle* h, const ntf_tensor* T, const float* const* A,
   NTF_RETURN_IF(pl.chunks >= (int64_t(1) << 31), NTF_EUNSUPPORTED, "reduction too long");
   st = ensure_workspace(h, pl.partial_floats() * sizeof(float) + 256);
   if (st) return st;
-  NTF_HIP(launch_mttkrp(pl, T->data, fp, P, reinterpret_cast<float*>(h->ws), nullptr, 0,
+  NTF_HIP(launch_mttkrp(pl, T->data, fp, P, reinterpret_cast<float*>(h->ws), true,
                         as_stream(stream)));
   return NTF_OK;
 }
@@ -263,25 +263,25 @@ ntf_status ntf_gram(ntf_handle* h, const float* const* A, const int64_t* rows, i
     if (l == exclude) continue;
     NTF_RETURN_IF(!A[l], NTF_EINVAL, "factor %d is NULL", l);
     NTF_RETURN_IF(rows[l] < 1, NTF_EINVAL, "rows[%d] < 1", l);
-    dry.take<double>(size_t(gram_chunks(rows[l])) * r * r);
+    dry.take<double>(size_t(gram_chunks(rows[l], r)) * r * r);
   }
   st = ensure_workspace(h, dry.off + 256);
   if (st) return st;
   Arena ar{h->ws, 0};
   for (int l = 0; l < nfac; ++l) {
     if (l == exclude) continue;
-    double* part = ar.take<double>(size_t(gram_chunks(rows[l])) * r * r);
+    double* part = ar.take<double>(size_t(gram_chunks(rows[l], r)) * r * r);
     job.A[job.nfac] = A[l];
     job.out[job.nfac] = part;
     job.rows[job.nfac] = rows[l];
     job.nfac++;
     hj.part[hj.nfac] = part;
-    hj.nchunks[hj.nfac] = gram_chunks(rows[l]);
+    hj.nchunks[hj.nfac] = gram_chunks(rows[l], r);
     hj.nfac++;
   }
   hipStream_t s = as_stream(stream);
   if (job.nfac > 0) NTF_HIP(launch_gram_partials(job, r, s));
-  NTF_HIP(launch_hadamard(hj, r, G32, G64, s));
+  NTF_HIP(launch_hadamard(hj, r, G32, G64, nullptr, 0, s));
   return NTF_OK;
 }
 

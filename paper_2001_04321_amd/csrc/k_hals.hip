@@ -1,31 +1,46 @@
-// A-HALS block solver (paper Sec. 2.1.4) with the inner stopping rule of Sec. 4.1.
+// A-HALS block solver (paper Sec. 2.1.4) with the inner stopping rule of Sec. 4.1, fused
+// with what surrounds it in an outer iteration of Algorithm 2.
 //
 // Rows of the block are independent NNLS problems coupled only through the stopping rule.
-// A group of L lanes owns one row and C columns per lane (blocked: lane g holds columns
-// g*C .. g*C+C-1), W and P of the row live in registers, G in LDS. Column j of a sweep:
-//   each lane forms its share of sum_{l != j} W[l] G[l, j], a DPP butterfly sums the
-//   group (all lanes end with the same value), and the owner lane sets
-//   W[j] = max(0, P[j] - sum) / G[j, j]   (0 if G[j, j] = 0: a dead component).
+// A group of L lanes owns one row and C columns per lane (lane g holds columns g*C ..
+// g*C+C-1); W and P of the row live in registers, G in LDS. Column j of a sweep: each
+// lane forms its share of sum_{l != j} W[l] G[l, j] (the term of the column updated just
+// before is added last, so the rest of the sum is off the dependency chain), a DPP
+// butterfly sums the group (every lane ends with the same bits), and the owner lane sets
+//   W[j] = max(0, P[j] - sum) / G[j, j]     (0 if G[j, j] = 0: a dead component).
+//
 // Stopping rule: after sweep s every workgroup publishes its share of ||W_s - W_{s-1}||^2
-// (float64) in slot (s, wg); the rule for sweep s-1 is evaluated after sweep s has been
-// computed, so the cross-workgroup wait overlaps a sweep of work. Every workgroup sums the
-// slots in the same order and takes the same decision; when sweep s-1 met the rule the
-// workgroup restores its snapshot of W_{s-1}. Waits are bounded by a wall-clock deadline
-// (a timeout sets NTF_FLAG_WAIT_TIMEOUT and ends the kernel). The grid never exceeds the
-// CU count, so every workgroup can be resident at once.
+// (float64) in slot (s, wg) and counts itself in; the last workgroup to arrive sums the
+// slots in workgroup order and publishes the total, so every workgroup sees the same value
+// and takes the same decision. The rule for sweep s - K + 1 is evaluated after sweep s,
+// with the load of its total issued before the sweep, so the wait overlaps K - 1 sweeps of
+// work; a ring of the last K iterates (in LDS) restores the iterate the rule stops at.
+// Waits are bounded by a wall-clock deadline (timeout: NTF_FLAG_WAIT_TIMEOUT). The grid
+// never exceeds the CU count, so all workgroups are resident together.
+//
+// Fused around the sweeps (each optional):
+//  - prologue: P rows as the fixed-order sum of the MTTKRP's split partials;
+//  - epilogue: extrapolation A_hat = max(0, W + beta (W - W_0)) (eq. extproj_her), the
+//    float64 partial Grams of the new and extrapolated rows (Gram cache of the solver), and
+//    the workgroup's share of 2 <P, W> - <G, W^T W> for the restart surrogate F-hat.
+#include "gram_chunk.h"
 #include "ntf_internal.h"
 
 namespace ntf {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kWindow = 6;  // sweeps between publishing a slot and waiting on it
 constexpr uint64_t kSentinel = ~uint64_t(0);
 
 struct HKArgs {
   const float* W0;
   float* W;
-  const float* P;
-  const float* G;
+  const float* P;        // rows x r, or null when Ppart is used
+  const float* Ppart;    // [nsplit][rows][r] partial MTTKRP sums
+  int64_t nsplit;
+  const float* G;        // r x r float32
+  const double* G64;     // r x r float64 (for the F-hat share)
   int64_t rows;
   int r;
   int max_sweeps;
@@ -35,6 +50,9 @@ struct HKArgs {
   uint32_t* flags;
   float* A_hat;
   const double* beta_src;
+  double* gp_new;
+  double* gp_hat;
+  double* err_part;
   int nwg;
   uint64_t timeout_ticks;
 };
@@ -44,210 +62,476 @@ __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double x) {
+  const int64_t b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((int64_t(hi) << 32) | uint32_t(lo));
+}
+
+__device__ __forceinline__ double readlane64(double x, int lane) {
+  const int64_t b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffff), lane);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+  return __longlong_as_double((int64_t(hi) << 32) | uint32_t(lo));
+}
+
 // Sum over aligned groups of L lanes (L <= 16); every lane of a group gets the same bits.
 template <int L>
 __device__ __forceinline__ float group_sum(float x) {
   if (L >= 2) x += dpp<0xB1>(x);    // quad_perm [1,0,3,2]: partner lane ^ 1
   if (L >= 4) x += dpp<0x4E>(x);    // quad_perm [2,3,0,1]: partner lane ^ 2
-  if (L >= 8) x += dpp<0x141>(x);   // row_half_mirror: other quad of the 8
-  if (L >= 16) x += dpp<0x140>(x);  // row_mirror: other half of the 16
+  if (L >= 8) x += dpp<0x141>(x);   // row_half_mirror: the other quad of the 8
+  if (L >= 16) x += dpp<0x140>(x);  // row_mirror: the other 8 of the 16
   return x;
 }
 
-// Block-wide float64 sum with a fixed tree; result returned to every thread.
-__device__ double block_sum_all(double v, double* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  return ((red[0] + red[1]) + red[2]) + red[3];
+// Wave-wide float64 sum in a fixed order (rows of 16 by DPP, then the 4 rows).
+__device__ __forceinline__ double wave_sum64(double x) {
+  x += dpp64<0xB1>(x);
+  x += dpp64<0x4E>(x);
+  x += dpp64<0x141>(x);
+  x += dpp64<0x140>(x);
+  return (readlane64(x, 0) + readlane64(x, 16)) + (readlane64(x, 32) + readlane64(x, 48));
 }
 
-template <int L, int C>
+// Broadcast lane `o` of each aligned group of G lanes (G = 16: DPP row_newbcast; G = 64:
+// readlane) to the whole group; `o` must be a compile-time constant after unrolling.
+template <int G>
+__device__ __forceinline__ float bcast(float x, int o) {
+  if (G == 16) {
+    int v = 0;
+    switch (o) {
+#define NTF_BC(n) \
+  case n: v = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x150 + n, 0xF, 0xF, false); break;
+      NTF_BC(0) NTF_BC(1) NTF_BC(2) NTF_BC(3) NTF_BC(4) NTF_BC(5) NTF_BC(6) NTF_BC(7)
+      NTF_BC(8) NTF_BC(9) NTF_BC(10) NTF_BC(11) NTF_BC(12) NTF_BC(13) NTF_BC(14) NTF_BC(15)
+#undef NTF_BC
+    }
+    return __int_as_float(v);
+  }
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), o));
+}
+
+// RPAD lanes per row group (16: four groups per wave; 64: one per wave), C columns per
+// lane (lane g owns columns g, g + RPAD, ...), NR rows per group processed in lockstep.
+template <int RPAD, int C, int NR>
 __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
-  constexpr int RPW = kThreads / L;  // rows per workgroup
-  constexpr int RP = L * C;          // padded rank
-  extern __shared__ float s_g[];     // r rows of RP floats, then r reciprocals
-  __shared__ double s_red[4];
-  __shared__ int s_timeout;
+  constexpr int GPW = 64 / RPAD;        // row groups per wave
+  constexpr int RPWV = GPW * NR;        // rows per wave
+  constexpr int WPG = kThreads / 64;    // waves per workgroup
+  constexpr int RPW = WPG * RPWV;       // rows per workgroup
+  constexpr int RMAX = RPAD * C;        // largest rank handled
+  extern __shared__ __attribute__((aligned(16))) float smem[];
+  // per-sweep LDS words alternate between two copies by sweep parity: a wave can reach the
+  // next sweep's write only after a barrier that every reader of the current copy has passed
+  __shared__ double s_part[2][WPG];
+
+  const int r = a.r;
+  float* s_g = smem;               // G, r x RMAX (row j: G[j][0..RMAX), zero padded)
+  float* s_rows = s_g + r * RMAX;  // RPW x r: P block, then new rows
+  float* s_rows2 = s_rows + RPW * r;  // RPW x r: extrapolated rows (ring follows)
 
   const int tid = threadIdx.x;
-  const int grp = tid / L;
-  const int li = tid % L;
-  const int64_t i = int64_t(blockIdx.x) * RPW + grp;
-  const bool row_ok = i < a.rows;
-  const int r = a.r;
-  float* s_inv = s_g + r * RP;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int gl = lane % RPAD;      // lane within its row group
+  const int gi = lane / RPAD;      // row group within the wave
+  const int64_t row0 = int64_t(blockIdx.x) * RPW;
+  const int nrows = int(std::min<int64_t>(RPW, a.rows - row0));
 
-  for (int e = tid; e < r * RP; e += kThreads) {
-    const int j = e / RP;
-    const int l = e - j * RP;
+  for (int e = tid; e < r * RMAX; e += kThreads) {
+    const int j = e / RMAX;
+    const int l = e - j * RMAX;
     s_g[e] = l < r ? a.G[j * r + l] : 0.f;
   }
-  for (int j = tid; j < r; j += kThreads) {
-    const float g = a.G[j * r + j];
-    s_inv[j] = g != 0.f ? 1.f / g : 0.f;
+  // P block of this workgroup: rows row0 .. row0+nrows-1 are contiguous in memory
+  {
+    const int64_t n = int64_t(nrows) * r;
+    const int64_t g0 = row0 * r;
+    const int64_t stride = a.rows * r;
+    for (int64_t e = tid; e < n; e += kThreads) {
+      if (a.Ppart) {
+        double acc = 0.0;
+        for (int64_t q = 0; q < a.nsplit; ++q) acc += double(a.Ppart[q * stride + g0 + e]);
+        s_rows[e] = float(acc);
+      } else {
+        s_rows[e] = a.P[g0 + e];
+      }
+    }
   }
-  if (tid == 0) s_timeout = 0;
   __syncthreads();
 
-  float w[C], p[C], w0[C], prev[C];
+  // local row q of this lane: wave * RPWV + q * GPW + gi
+  int lrow[NR];
+  bool rok[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    lrow[q] = wave * RPWV + q * GPW + gi;
+    rok[q] = lrow[q] < nrows;
+  }
+  float w[NR][C], p[NR][C], w0[NR][C], d[NR][C], inv[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const int j = li * C + c;
-    const bool ok = row_ok && j < r;
-    w[c] = ok ? a.W0[i * r + j] : 0.f;
-    p[c] = ok ? a.P[i * r + j] : 0.f;
-    w0[c] = w[c];
+    const int j = c * RPAD + gl;
+    const float gjj = j < r ? s_g[j * RMAX + j] : 0.f;
+    inv[c] = gjj != 0.f ? 1.f / gjj : 0.f;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const bool ok = rok[q] && j < r;
+      w0[q][c] = ok ? a.W0[(row0 + lrow[q]) * r + j] : 0.f;
+      p[q][c] = ok ? s_rows[lrow[q] * r + j] : 0.f;
+      // a dead component (G[j][j] = 0) is 0 after its first update and stays 0
+      w[q][c] = (ok && gjj != 0.f) ? w0[q][c] : 0.f;
+    }
   }
 
-  const int nown = (r + C - 1) / C;  // lanes that own at least one column
-  int done = a.max_sweeps;
-  double d1 = 0.0;
   const uint64_t t_start = wall_clock64();
 
-  for (int s = 1; s <= a.max_sweeps; ++s) {
+  // one Gauss-Seidel sweep over the columns. d = W G is formed exactly at the start of the
+  // sweep and kept current by rank-one updates: after column j changes by delta,
+  // d += delta * G[j, :]. The owner of column j then has d_j = sum_l W_l G_lj and
+  //   W_j <- max(0, W_j + (P_j - d_j) / G_jj) = max(0, P_j - sum_{l != j} W_l G_lj) / G_jj.
+  // Columns go in blocks of 8 (one branch per block); columns r .. (block end) are zero
+  // padding whose update is exactly 0. The G values of the next block are read from LDS
+  // while the current block is computed.
+  constexpr int NB = (RMAX + 7) / 8;
+  auto load_gblk = [&](int jb, float (&gb)[8][C]) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) prev[c] = w[c];
-
-#pragma unroll 1
-    for (int jo = 0; jo < nown; ++jo) {
+    for (int t = 0; t < 8; ++t) {
+      const int j = jb * 8 + t;
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const int j = jo * C + c;
-        if (j >= r) break;
-        const float* grow = s_g + j * RP + li * C;
-        float part = 0.f;
+      for (int c = 0; c < C; ++c) gb[t][c] = j < r ? s_g[j * RMAX + c * RPAD + gl] : 0.f;
+    }
+  };
+  auto is_owner = [&](int o) {
+    int g = gl;
+    asm volatile("" : "+v"(g));  // keep the compare next to its use (no hoisted masks)
+    return g == o;
+  };
+  auto sweep = [&]() {
+    float gb0[8][C], gb1[8][C];
 #pragma unroll
-        for (int c2 = 0; c2 < C; ++c2) {
-          const float wv = (li == jo && c2 == c) ? 0.f : w[c2];
-          part = fmaf(wv, grow[c2], part);
+    for (int q = 0; q < NR; ++q)
+#pragma unroll
+      for (int c = 0; c < C; ++c) d[q][c] = 0.f;
+    // d = W G
+    load_gblk(0, gb0);
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) {
+      if (jb * 8 >= r) break;
+      float (&cur)[8][C] = (jb & 1) ? gb1 : gb0;
+      float (&nxt)[8][C] = (jb & 1) ? gb0 : gb1;
+      if (jb + 1 < NB && (jb + 1) * 8 < r) load_gblk(jb + 1, nxt);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int l = jb * 8 + t;
+        const int cs = l / RPAD;
+        const int o = l % RPAD;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          const float wl = bcast<RPAD>(w[q][cs], o);
+#pragma unroll
+          for (int c = 0; c < C; ++c) d[q][c] = fmaf(wl, cur[t][c], d[q][c]);
         }
-        part = group_sum<L>(part);
-        if (li == jo) w[c] = fmaxf(p[c] - part, 0.f) * s_inv[j];
       }
     }
+    // column updates
+    load_gblk(0, gb0);
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) {
+      if (jb * 8 >= r) break;
+      float (&cur)[8][C] = (jb & 1) ? gb1 : gb0;
+      float (&nxt)[8][C] = (jb & 1) ? gb0 : gb1;
+      if (jb + 1 < NB && (jb + 1) * 8 < r) load_gblk(jb + 1, nxt);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int j = jb * 8 + t;
+        const int cs = j / RPAD;
+        const int o = j % RPAD;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          const float wn = fmaxf(fmaf(p[q][cs] - d[q][cs], inv[cs], w[q][cs]), 0.f);
+          const float delta = bcast<RPAD>(wn - w[q][cs], o);
+          if (is_owner(o)) w[q][cs] = wn;
+#pragma unroll
+          for (int c = 0; c < C; ++c) d[q][c] = fmaf(delta, cur[t][c], d[q][c]);
+        }
+      }
+    }
+  };
 
-    // this workgroup's share of ||W_s - W_{s-1}||_F^2
+  // Per sweep s (1-based) the sync area holds nwg workgroup slots, one arrival counter and
+  // one total, all starting at the sentinel (all ones; the counter then counts from -1).
+  uint64_t* const slots = a.slots;
+  uint64_t* const counters = a.slots + int64_t(a.max_sweeps) * a.nwg;
+  uint64_t* const totals = counters + a.max_sweeps;
+  auto spin_load = [&](const uint64_t* addr, bool& timeout) -> uint64_t {
+    uint64_t v = __hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (v == kSentinel) {
+      if (wall_clock64() - t_start > a.timeout_ticks) {
+        timeout = true;
+        return 0;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      v = __hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return v;
+  };
+  // Publishing this workgroup's share of ||W_s - W_{s-1}||^2 (publish(s)): the share goes
+  // to its slot and the sweep's arrival counter is incremented. Everything after the
+  // barrier runs in wave 0 and never waits for memory issued in the same call: the
+  // counter's previous value is read at publish(s + 1), where the workgroup that arrived
+  // last for sweep s issues the loads of all shares of sweep s; at publish(s + 2) it sums
+  // them in workgroup order and stores the total. The total of sweep s is first needed
+  // kWindow - 1 sweeps after sweep s.
+  uint64_t pending_old = 0;  // lane 0 of wave 0: counter value before this workgroup's add
+  uint64_t u[4];             // wave 0: shares loaded for sweep `agg` (nwg <= 256)
+  int agg = 0;               // sweep whose total this workgroup owes, 0 for none
+  bool pub_to = false;       // wave 0: a share never appeared
+  auto agg_finish = [&]() {
+    const uint64_t* sl = slots + int64_t(agg - 1) * a.nwg;
+    bool to = false;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      // a share whose store is not visible yet still reads as the sentinel
+      if (lane + 64 * k < a.nwg && u[k] == kSentinel) u[k] = spin_load(&sl[lane + 64 * k], to);
+      v += __longlong_as_double(int64_t(u[k]));
+    }
+    const double D = wave_sum64(v);
+    pub_to = pub_to || __any(to);
+    if (lane == 0)
+      __hip_atomic_store(&totals[agg - 1], uint64_t(__double_as_longlong(D)), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    agg = 0;
+  };
+  auto publish = [&](int s, const float (&prev)[NR][C]) {
     double d2 = 0.0;
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const double df = double(w[c]) - double(prev[c]);
-      d2 += df * df;
-    }
-    const double wg_d2 = block_sum_all(d2, s_red);
-    if (tid == 0)
-      __hip_atomic_store(&a.slots[int64_t(s - 1) * a.nwg + blockIdx.x],
-                         uint64_t(__double_as_longlong(wg_d2)), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-
-    if (s >= 2) {
-      // stopping rule for sweep s-1: wait for every workgroup's slot, sum in wg order
-      double v = 0.0;
-      if (tid < a.nwg) {
-        const uint64_t* slot = &a.slots[int64_t(s - 2) * a.nwg + tid];
-        uint64_t bits;
-        for (;;) {
-          bits = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (bits != kSentinel) break;
-          if (wall_clock64() - t_start > a.timeout_ticks) {
-            s_timeout = 1;
-            bits = 0;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(2);
-        }
-        v = __longlong_as_double(int64_t(bits));
+    for (int q = 0; q < NR; ++q)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const double df = double(w[q][c]) - double(prev[q][c]);
+        d2 += df * df;
       }
-      const double D = block_sum_all(v, s_red);  // includes the barrier for s_timeout
-      if (s_timeout) {
-        if (tid == 0)
-          __hip_atomic_fetch_or(a.flags, NTF_FLAG_WAIT_TIMEOUT, __ATOMIC_RELAXED,
-                                __HIP_MEMORY_SCOPE_AGENT);
-        done = s;
+    const double ws = wave_sum64(d2);
+    if (lane == 0) s_part[s & 1][wave] = ws;
+    __syncthreads();
+    if (wave == 0) {
+      // order: consume what arrived during the sweep, then issue the new memory operations,
+      // so that no wait here covers an operation issued in the same call
+      const uint64_t old =
+          (uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(pending_old >> 32)))) << 32) |
+          uint32_t(__builtin_amdgcn_readfirstlane(int(pending_old)));
+      if (agg > 0) agg_finish();
+      if (lane == 0) {
+        double t = 0.0;
+        for (int k = 0; k < WPG; ++k) t += s_part[s & 1][k];
+        __hip_atomic_store(&slots[int64_t(s - 1) * a.nwg + blockIdx.x],
+                           uint64_t(__double_as_longlong(t)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        pending_old = __hip_atomic_fetch_add(&counters[s - 1], uint64_t(1), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (s > 1 && int64_t(old) == int64_t(a.nwg) - 2) {  // last for sweep s-1 (counts from -1)
+        agg = s - 1;
+        const uint64_t* sl = slots + int64_t(agg - 1) * a.nwg;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          u[k] = lane + 64 * k < a.nwg ? __hip_atomic_load(&sl[lane + 64 * k], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                                       : 0;
+      }
+    }
+  };
+  // total of sweep sp, loaded a window ahead of use
+  uint64_t pv = 0;
+  auto issue_poll = [&](int sp) {
+    pv = __hip_atomic_load(&totals[sp - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  // stopping rule for sweep sp: 0 continue, 1 stop, 2 timed out
+  double d1 = 0.0;
+  auto decide = [&](int sp) -> int {
+    bool to = false;
+    if (pv == kSentinel) pv = spin_load(&totals[sp - 1], to);
+    if (to) return 2;
+    const double delta = sqrt(__longlong_as_double(int64_t(pv)));
+    if (sp == 1) d1 = delta;
+    return delta <= a.tol * d1 ? 1 : 0;
+  };
+
+  // ring of the last kWindow iterates in LDS: [slot][q * C + c][thread]
+  float* s_ring = s_rows2 + RPW * r;
+  auto ring_put = [&](int slot) {
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+#pragma unroll
+      for (int c = 0; c < C; ++c) s_ring[(slot * NR * C + q * C + c) * kThreads + tid] = w[q][c];
+  };
+  auto ring_get = [&](int slot) {
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+#pragma unroll
+      for (int c = 0; c < C; ++c) w[q][c] = s_ring[(slot * NR * C + q * C + c) * kThreads + tid];
+  };
+  int done = a.max_sweeps;
+  bool timed_out = false;
+  bool finished = false;
+  for (int s = 1; s <= a.max_sweeps; ++s) {
+    const int sp = s - kWindow + 1;  // rule evaluated after this sweep
+    if (sp >= 1) issue_poll(sp);
+    float prev[NR][C];
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+#pragma unroll
+      for (int c = 0; c < C; ++c) prev[q][c] = s == 1 ? w0[q][c] : w[q][c];
+    sweep();
+    ring_put(s % kWindow);
+    // the rule is checked before this sweep's share goes out, so that the wait for the
+    // total does not also wait for this sweep's counter update; on a stop every workgroup
+    // stops at the same sweep (they read the same total), so none needs the skipped share
+    if (sp >= 1) {
+      const int st = decide(sp);
+      if (st == 1) {
+        ring_get(sp % kWindow);
+        done = sp;
+        finished = true;
         break;
       }
-      const double delta = sqrt(D);
-      if (s - 1 == 1) d1 = delta;
-      if (delta <= a.tol * d1) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) w[c] = prev[c];
-        done = s - 1;
+      if (st == 2) {
+        done = s;
+        timed_out = true;
+        finished = true;
+        break;
+      }
+    }
+    publish(s, prev);
+  }
+  if (!finished) {
+    // The total of sweep S-1 may still be owed (its loads were issued at publish(S)); the
+    // total of sweep S itself is never needed.
+    const int S = a.max_sweeps;
+    if (wave == 0 && agg > 0) agg_finish();
+    // rules not evaluated yet: sweeps max(1, S-K+2) .. S-1, in order
+    for (int sp = std::max(1, S - kWindow + 2); sp <= S - 1; ++sp) {
+      issue_poll(sp);
+      const int st = decide(sp);
+      if (st == 1) {
+        ring_get(sp % kWindow);
+        done = sp;
+        break;
+      }
+      if (st == 2) {
+        timed_out = true;
         break;
       }
     }
   }
+  if ((timed_out || pub_to) && lane == 0)
+    __hip_atomic_fetch_or(a.flags, NTF_FLAG_WAIT_TIMEOUT, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
 
-  if (row_ok) {
-    double beta = 0.0;
-    if (a.A_hat) beta = *a.beta_src;
+  // ---- epilogue: write W (and A_hat); stage rows for the Gram partials ----
+  const double beta = a.A_hat ? *a.beta_src : 0.0;
+  __syncthreads();  // s_rows (P block) is no longer read
+#pragma unroll
+  for (int q = 0; q < NR; ++q)
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const int j = li * C + c;
-      if (j < r) {
-        a.W[i * r + j] = w[c];
+      const int j = c * RPAD + gl;
+      if (rok[q] && j < r) {
+        const int64_t gidx = (row0 + lrow[q]) * r + j;
+        a.W[gidx] = w[q][c];
+        s_rows[lrow[q] * r + j] = w[q][c];
         if (a.A_hat) {
-          const double x = w[c];
-          const double y = x + beta * (x - double(w0[c]));
-          a.A_hat[i * r + j] = float(y > 0.0 ? y : 0.0);
+          const double x = w[q][c];
+          const double y = x + beta * (x - double(w0[q][c]));
+          const float xh = float(y > 0.0 ? y : 0.0);
+          a.A_hat[gidx] = xh;
+          s_rows2[lrow[q] * r + j] = xh;
         }
       }
+    }
+  __syncthreads();
+  const int64_t rr = int64_t(r) * r;
+  if (a.gp_new) chunk_gram(s_rows, nrows, r, a.gp_new + blockIdx.x * rr);
+  if (a.gp_hat && a.A_hat) chunk_gram(s_rows2, nrows, r, a.gp_hat + blockIdx.x * rr);
+  if (a.err_part) {
+    // share of 2 <P, W> - <G, W^T W> = sum_rows sum_j w_j (2 p_j - (G w)_j)
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int j = c * RPAD + gl;
+        if (rok[q] && j < r) {
+          double gw = 0.0;
+          for (int l = 0; l < r; ++l)
+            gw += a.G64[int64_t(j) * r + l] * double(s_rows[lrow[q] * r + l]);
+          t += double(w[q][c]) * (2.0 * double(p[q][c]) - gw);
+        }
+      }
+    const double ws = wave_sum64(t);
+    if (lane == 0) s_part[0][wave] = ws;
+    __syncthreads();
+    if (tid == 0) {
+      double e = 0.0;
+      for (int k = 0; k < WPG; ++k) e += s_part[0][k];
+      a.err_part[blockIdx.x] = e;
     }
   }
   if (blockIdx.x == 0 && tid == 0 && a.sweeps_out) *a.sweeps_out = done;
 }
 
-struct Shape {
-  int L, C;
-};
-
-Shape hals_shape(int r) {
-  if (r <= 64) {
-    int L = 1;
-    while (L * 4 < r) L *= 2;
-    return {L, 4};
-  }
-  return {16, 8};  // r <= 128
-}
-
 using HFn = void (*)(HKArgs);
 
-HFn hals_fn(Shape sh) {
-  if (sh.C == 8) return hals_kernel<16, 8>;
-  switch (sh.L) {
-    case 1: return hals_kernel<1, 4>;
-    case 2: return hals_kernel<2, 4>;
-    case 4: return hals_kernel<4, 4>;
-    case 8: return hals_kernel<8, 4>;
-    default: return hals_kernel<16, 4>;
-  }
+template <int RPAD, int C>
+HFn pick_nr(int nr) {
+  if (nr == 1) return hals_kernel<RPAD, C, 1>;
+  if (nr == 2) return hals_kernel<RPAD, C, 2>;
+  return hals_kernel<RPAD, C, 4>;
 }
 
-int hals_wgs(int64_t rows, int r) {
-  const Shape sh = hals_shape(r);
-  return int(ceil_div(rows, kThreads / sh.L));
+HFn hals_fn(int r, int nr) {
+  if (r <= 16) return pick_nr<16, 1>(nr);
+  if (r <= 64) return pick_nr<64, 1>(nr);
+  return pick_nr<64, 2>(nr);
+}
+
+size_t hals_lds(int r, int64_t rows) {
+  const int rmax = r <= 16 ? 16 : (r <= 64 ? 64 : 128);
+  const int c = r <= 64 ? 1 : 2;
+  const int nr = hals_rows_interleaved(r, rows);
+  const int rpw = gram_chunk_rows(r, rows);
+  const size_t ring = size_t(kWindow) * nr * c * kThreads;
+  return (size_t(r) * rmax + 2 * size_t(rpw) * r + ring) * sizeof(float);
 }
 
 }  // namespace
 
+int64_t hals_wgs(int64_t rows, int r) { return ceil_div(rows, gram_chunk_rows(r, rows)); }
+
 bool hals_supported(int64_t rows, int r, int num_cus) {
-  if (r < 1 || r > 128) return false;
+  if (r < 1 || r > 128 || rows < 1) return false;
   return hals_wgs(rows, r) <= std::min(256, num_cus);
 }
 
 int64_t hals_slot_count(int64_t rows, int r, int max_sweeps) {
-  return int64_t(hals_wgs(rows, r)) * max_sweeps;
+  // per sweep: one slot per workgroup, an arrival counter and the total
+  return (hals_wgs(rows, r) + 2) * int64_t(max_sweeps);
 }
 
 hipError_t launch_hals(const HalsArgs& h, int num_cus, hipStream_t s) {
-  const Shape sh = hals_shape(h.r);
-  HKArgs a;
+  HKArgs a{};
   a.W0 = h.W0;
   a.W = h.W;
   a.P = h.P;
+  a.Ppart = h.Ppart;
+  a.nsplit = h.nsplit;
   a.G = h.G;
+  a.G64 = h.G64;
   a.rows = h.rows;
   a.r = h.r;
   a.max_sweeps = h.max_sweeps;
@@ -257,9 +541,11 @@ hipError_t launch_hals(const HalsArgs& h, int num_cus, hipStream_t s) {
   a.flags = h.flags;
   a.A_hat = h.A_hat;
   a.beta_src = h.beta_src;
-  a.nwg = hals_wgs(h.rows, h.r);
-  // wall_clock64 runs at the device's wall-clock rate (100 MHz on MI300-class parts);
-  // 2 s is far above any legitimate wait.
+  a.gp_new = h.gp_new;
+  a.gp_hat = h.gp_hat;
+  a.err_part = h.err_part;
+  a.nwg = int(hals_wgs(h.rows, h.r));
+  // wall_clock64 runs at the device's wall-clock rate; 2 s is far above any legitimate wait
   static const int rate_khz = [] {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -269,8 +555,20 @@ hipError_t launch_hals(const HalsArgs& h, int num_cus, hipStream_t s) {
   }();
   a.timeout_ticks = uint64_t(rate_khz) * 1000ull * 2ull;
   (void)num_cus;
-  const size_t lds = (size_t(h.r) * sh.L * sh.C + h.r) * sizeof(float);
-  hipLaunchKernelGGL(hals_fn(sh), dim3(a.nwg), dim3(kThreads), lds, s, a);
+  HFn fn = hals_fn(h.r, hals_rows_interleaved(h.r, h.rows));
+  const size_t lds = hals_lds(h.r, h.rows);
+  static bool attr_done = false;
+  if (!attr_done) {
+    for (int rr : {16, 64, 128})
+      for (int nr : {1, 2, 4}) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(hals_fn(rr, nr)),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024 - 8 * 1024);  // room for static LDS
+        if (e != hipSuccess) return e;
+      }
+    attr_done = true;
+  }
+  hipLaunchKernelGGL(fn, dim3(a.nwg), dim3(kThreads), lds, s, a);
   return hipGetLastError();
 }
 

@@ -158,10 +158,14 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
 
   // One work item = (u, chunk kc of the current v-block) for this wave. Registers of one
   // item: bf16 case A: 32 elements along v (4 x 16 B); f32 case A: 16 floats; f32 case B:
-  // 16 floats; bf16 case B: 4 x 16 B of the wave's 64 x 32 tile.
-  uint4 cur[4], nxt[4];
+  // 16 floats; bf16 case B: 4 x 16 B of the wave's 64 x 32 tile. PD items are in flight
+  // per wave (a ring of register buffers, indexed at compile time).
+  constexpr int PD = NT <= 2 ? 4 : 2;
+  uint4 buf[PD][4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) cur[q] = nxt[q] = make_uint4(0, 0, 0, 0);
+  for (int d = 0; d < PD; ++d)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) buf[d][q] = make_uint4(0, 0, 0, 0);
 
   auto load_item = [&](uint4 (&reg)[4], int64_t base, int64_t v0c) {
     if (!LAST) {
@@ -308,38 +312,48 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
     __syncthreads();
 
     const int nitems = nu * ipu;
-    {
-      const int kc = wk;
-      if (kc < nkc) load_item(cur, t_base<LAST>(k, uint32_t(u0)), v0 + int64_t(kc) * KCH);
-    }
-    for (int it = 0; it < nitems; ++it) {
-      const int uu = it / ipu;
-      const int j = it - uu * ipu;
-      const int kc = wk + j * WK;
-      if (it + 1 < nitems) {
-        const int un = (it + 1) / ipu;
-        const int kn = wk + ((it + 1) - un * ipu) * WK;
-        if (kn < nkc)
-          load_item(nxt, t_base<LAST>(k, uint32_t(u0 + un)), v0 + int64_t(kn) * KCH);
+    // prefetch cursor (pu, pj) and compute cursor (cu, cj) over (u, chunk) items
+    int pu = 0, pj = 0;
+    auto prefetch = [&](uint4 (&reg)[4]) {
+      const int kc = wk + pj * WK;
+      if (kc < nkc) load_item(reg, t_base<LAST>(k, uint32_t(u0 + pu)), v0 + int64_t(kc) * KCH);
+      if (++pj == ipu) {
+        pj = 0;
+        ++pu;
       }
-      if (j == 0) {
+    };
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
+    for (int d = 0; d < PD - 1; ++d)
+      if (d < nitems) prefetch(buf[d]);
+    int cu = 0, cj = 0;
+    for (int base = 0; base < nitems; base += PD) {
 #pragma unroll
-          for (int e = 0; e < 16; ++e) y[nt][e] = 0.f;
-      }
-      if (kc < nkc) compute_item(cur, kc);
-      if (j == ipu - 1) {
-        const float* xs = s_x + uu * RP;
+      for (int d = 0; d < PD; ++d) {
+        if (base + d < nitems) {
+          if (base + d + PD - 1 < nitems) prefetch(buf[(d + PD - 1) % PD]);
+          if (cj == 0) {
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const float x = xs[nt * 32 + col];
+            for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-          for (int e = 0; e < 16; ++e) acc[nt][e] = fmaf(x, y[nt][e], acc[nt][e]);
+              for (int e = 0; e < 16; ++e) y[nt][e] = 0.f;
+          }
+          const int kc = wk + cj * WK;
+          if (kc < nkc) compute_item(buf[d], kc);
+          if (cj == ipu - 1) {
+            const float* xs = s_x + cu * RP;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+              const float x = xs[nt * 32 + col];
+#pragma unroll
+              for (int e = 0; e < 16; ++e) acc[nt][e] = fmaf(x, y[nt][e], acc[nt][e]);
+            }
+          }
+          if (++cj == ipu) {
+            cj = 0;
+            ++cu;
+          }
         }
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
     }
     w += nu;
   }
@@ -379,12 +393,10 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
 }
 
 // Fixed-order sum of split partials: each output element is summed by 4 threads over
-// interleaved splits (float64), then combined in thread order; optionally resets
-// inner-solver slots.
+// interleaved splits (float64), then combined in thread order.
 __global__ __launch_bounds__(256) void mttkrp_reduce_kernel(const float* __restrict__ part,
                                                             int64_t splits, int64_t n,
-                                                            float* __restrict__ P,
-                                                            double* slots, int64_t nslots) {
+                                                            float* __restrict__ P) {
   __shared__ double s[4][64];
   const int o = threadIdx.x & 63;
   const int g = threadIdx.x >> 6;
@@ -398,9 +410,6 @@ __global__ __launch_bounds__(256) void mttkrp_reduce_kernel(const float* __restr
     if (g == 0 && e < n) P[e] = float(((s[0][o] + s[1][o]) + s[2][o]) + s[3][o]);
     __syncthreads();
   }
-  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  for (int64_t e = tid; e < nslots; e += int64_t(gridDim.x) * blockDim.x)
-    slots[e] = __longlong_as_double(-1ll);
 }
 
 using KernelFn = void (*)(KArgs);
@@ -503,21 +512,35 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus) {
   pl.nvb = int(ceil_div(pl.Iv, pl.vb));
   pl.mtiles = ceil_div(I, 32 * pl.wm);
   pl.chunks = pl.U * pl.nvb;  // work items (v-block, u)
-  const int64_t target = int64_t(num_cus) * 2;
-  int64_t splits = ceil_div(target, pl.mtiles);
-  splits = std::max<int64_t>(1, std::min<int64_t>(splits, pl.chunks));
-  splits = std::min<int64_t>(splits, 65535);
-  pl.splits = splits;
-  const int64_t per = ceil_div(pl.chunks, splits);
-  pl.ub = int(std::max<int64_t>(1, std::min<int64_t>({per, int64_t(8192 / pl.rpad), pl.U})));
   // the end-of-kernel reduction of the WK waves reuses the same LDS
   const size_t red = size_t(pl.wk - 1) * pl.wm * 64 * 16 * nt * sizeof(float);
+  // One residency wave: grid = resident workgroups per CU x CUs (a partial second wave
+  // would double the time of the tail). The X batch (and so LDS and occupancy) depends on
+  // the split count; two refinement passes settle it (LDS only shrinks between passes).
+  KernelFn fn = select_kernel(bf16, last, pl.wm, nt);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  pl.ub = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(8192 / pl.rpad), pl.U)));
+  for (int pass = 0; pass < 3; ++pass) {
+    pl.lds = std::max(lds_bytes(bf16, last, pl.rpad, pl.vb, pl.ub), red);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn),
+                                                     kThreads, pl.lds) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    const int64_t slots = int64_t(per_cu) * num_cus;
+    int64_t splits = std::max<int64_t>(1, slots / pl.mtiles);
+    splits = std::min<int64_t>({splits, pl.chunks, int64_t(65535)});
+    pl.splits = splits;
+    const int64_t per = ceil_div(pl.chunks, splits);
+    pl.ub = int(std::max<int64_t>(1, std::min<int64_t>({per, int64_t(8192 / pl.rpad), pl.U})));
+  }
   pl.lds = std::max(lds_bytes(bf16, last, pl.rpad, pl.vb, pl.ub), red);
   return pl;
 }
 
 hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& A, float* P,
-                         float* partials, double* slots, int64_t nslots, hipStream_t s) {
+                         float* partials, bool reduce, hipStream_t s) {
   KArgs k{};
   k.T = T;
   const int N = pl.v.order;
@@ -561,12 +584,11 @@ hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& 
   hipLaunchKernelGGL(fn, grid, dim3(kThreads), pl.lds, s, k);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (split || nslots > 0) {
-    const int64_t nout = split ? pl.v.I * pl.r : 0;
-    const int64_t work = std::max<int64_t>(ceil_div(nout, 64), ceil_div(nslots, 256));
-    const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(work, 4096)));
+  if (split && reduce) {
+    const int64_t nout = pl.v.I * pl.r;
+    const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(ceil_div(nout, 64), 4096)));
     hipLaunchKernelGGL(mttkrp_reduce_kernel, dim3(blocks), dim3(256), 0, s, partials,
-                       pl.splits, nout, P, slots, nslots);
+                       pl.splits, nout, P);
     e = hipGetLastError();
   }
   return e;

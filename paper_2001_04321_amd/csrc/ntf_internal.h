@@ -137,53 +137,62 @@ struct MttkrpPlan {
   size_t partial_floats() const { return splits > 1 ? size_t(splits) * v.I * r : 0; }
 };
 MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus);
-// P (I x r) = MTTKRP. `partials` must hold plan.partial_floats() floats (may be null
-// when splits == 1). If `slots`/`nslots` are given, the final reduction also resets
-// those doubles to the inner-solver sentinel (saves a launch before A-HALS).
+// MTTKRP. With one split the kernel writes P (I x r) directly. With several it writes
+// plan.partial_floats() floats of split partials; if `reduce` is set a second kernel sums
+// them into P in a fixed order, otherwise the caller (A-HALS) consumes the partials.
 hipError_t launch_mttkrp(const MttkrpPlan& plan, const void* T, const FactorPtrs& A, float* P,
-                         float* partials, double* slots, int64_t nslots, hipStream_t s);
+                         float* partials, bool reduce, hipStream_t s);
 
-// Gram partials: for factor f (rows[f] x r), out[f] gets ceil(rows/kGramChunk) partial
-// r x r float64 Grams. Up to kMaxOrder factors per launch (blockIdx.y = factor).
+// Gram partials: for factor f (rows[f] x r), out[f] gets gram_chunks(rows, r) partial
+// r x r float64 Grams (row chunks of the A-HALS workgroup size, so the A-HALS epilogue
+// produces identical partials). Up to kMaxOrder factors per launch (blockIdx.y = factor).
 struct GramJob {
   const float* A[kMaxOrder];
   double* out[kMaxOrder];
   int64_t rows[kMaxOrder];
   int nfac;
 };
-int64_t gram_chunks(int64_t rows);
+int64_t gram_chunks(int64_t rows, int r);
 hipError_t launch_gram_partials(const GramJob& job, int r, hipStream_t s);
 
-// Hadamard of summed Gram partials: G = prod_f sum_c part[f][c]. Writes G32 and/or G64.
+// Hadamard of summed Gram partials: G = prod_f sum_c part[f][c]. Writes G32 and/or G64;
+// also resets `nslots` inner-solver wait slots to the sentinel (may be 0).
 struct HadamardJob {
   const double* part[kMaxOrder];
   int64_t nchunks[kMaxOrder];
   int nfac;
 };
 hipError_t launch_hadamard(const HadamardJob& job, int r, float* G32, double* G64,
-                           hipStream_t s);
+                           double* slots, int64_t nslots, hipStream_t s);
 
 // A-HALS on one block. `slots` holds hals_slot_count(rows, r, max_sweeps) doubles that
-// are set to the sentinel (launch_fill_sentinel) before the call.
+// are set to the sentinel (launch_fill_sentinel or launch_hadamard) before the call.
 int64_t hals_slot_count(int64_t rows, int r, int max_sweeps);
+int64_t hals_wgs(int64_t rows, int r);
 // Workgroups never exceed min(256, CU count) so that all of them are resident at once.
 bool hals_supported(int64_t rows, int r, int num_cus);
 hipError_t launch_fill_sentinel(double* slots, int64_t n, hipStream_t s);
 struct HalsArgs {
-  const float* W0;     // warm start (may equal W)
-  float* W;            // result
-  const float* P;
-  const float* G;      // r x r float32
+  const float* W0;       // warm start (may equal W)
+  float* W;              // result
+  const float* P;        // MTTKRP rows x r (when Ppart is null)
+  const float* Ppart;    // or split partials [nsplit][rows][r]
+  int64_t nsplit;
+  const float* G;        // r x r float32
+  const double* G64;     // r x r float64, needed with err_part
   int64_t rows;
   int r;
   int max_sweeps;
   double tol;
-  int32_t* sweeps_out;  // may be null
+  int32_t* sweeps_out;   // may be null
   double* slots;
   uint32_t* flags;
-  // optional fused extrapolation: A_hat = max(0, W + beta (W - W0)), beta = *beta_src
-  float* A_hat;          // null: no extrapolation
+  // optional fused epilogue:
+  float* A_hat;          // A_hat = max(0, W + beta (W - W0)), beta = *beta_src
   const double* beta_src;
+  double* gp_new;        // Gram partials of W, hals_wgs(rows, r) x r x r
+  double* gp_hat;        // Gram partials of A_hat
+  double* err_part;      // per-workgroup share of 2 <P, W> - <G64, W^T W>
 };
 hipError_t launch_hals(const HalsArgs& a, int num_cus, hipStream_t s);
 

@@ -79,7 +79,7 @@ void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
     maxI = std::max(maxI, I);
     b.A_new[n] = ar.take<float>(size_t(I) * r);
     b.A_hat[n] = ar.take<float>(size_t(I) * r);
-    const size_t g = size_t(gram_chunks(I)) * rr;
+    const size_t g = size_t(gram_chunks(I, r)) * rr;
     b.gp_cur[n] = ar.take<double>(g);
     b.gp_new[n] = ar.take<double>(g);
     b.gp_hat[n] = ar.take<double>(g);
@@ -93,8 +93,7 @@ void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
   b.nslots = maxslots;
   b.slots = ar.take<double>(size_t(maxslots));
   b.sweeps = ar.take<int32_t>(kMaxOrder);
-  b.nerr = std::max(error_partial_count(T.dims[N - 1], r),
-                    error_partial_count(T.dims[N - 1], r));
+  b.nerr = std::max(error_partial_count(T.dims[N - 1], r), hals_wgs(T.dims[N - 1], r));
   b.err_part = ar.take<double>(size_t(b.nerr));
 }
 
@@ -105,7 +104,10 @@ FactorPtrs factors_for(int n, int N, float* const* A, const SolveBufs& b) {
   return fp;
 }
 
-// Enqueue one outer iteration on stream s.
+// Enqueue one outer iteration on stream s: per block a Hadamard kernel (also resetting the
+// A-HALS wait slots), the MTTKRP (and the fixed-order sum of its split partials), and the
+// fused A-HALS kernel (sweeps, extrapolation, Gram partials, F-hat share); then decide
+// and select.
 hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* const* A,
                              const ntf_her_params& p, const SolveBufs& b,
                              const MttkrpPlan* plans, const ntf_trace& trace, hipStream_t s) {
@@ -117,19 +119,24 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
     for (int l = 0; l < N; ++l) {
       if (l == n) continue;
       hj.part[hj.nfac] = l < n ? b.gp_hat[l] : b.gp_cur[l];
-      hj.nchunks[hj.nfac] = gram_chunks(T.dims[l]);
+      hj.nchunks[hj.nfac] = gram_chunks(T.dims[l], r);
       hj.nfac++;
     }
-    if ((e = launch_hadamard(hj, r, b.G32, b.G64, s)) != hipSuccess) return e;
     const int64_t nslots = hals_slot_count(I, r, p.max_inner);
-    if ((e = launch_mttkrp(plans[n], T.data, factors_for(n, N, A, b), b.P, b.mt_part, b.slots,
-                           nslots, s)) != hipSuccess)
+    if ((e = launch_hadamard(hj, r, b.G32, b.G64, b.slots, nslots, s)) != hipSuccess) return e;
+    // split partials are summed by the wide reduction kernel: the A-HALS grid is too
+    // narrow (one workgroup per row chunk) to stream them quickly
+    if ((e = launch_mttkrp(plans[n], T.data, factors_for(n, N, A, b), b.P, b.mt_part, true,
+                           s)) != hipSuccess)
       return e;
     HalsArgs ha{};
     ha.W0 = A[n];
     ha.W = b.A_new[n];
     ha.P = b.P;
+    ha.Ppart = nullptr;
+    ha.nsplit = 1;
     ha.G = b.G32;
+    ha.G64 = b.G64;
     ha.rows = I;
     ha.r = r;
     ha.max_sweeps = p.max_inner;
@@ -139,27 +146,18 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
     ha.flags = h->dev_flags;
     ha.A_hat = b.A_hat[n];
     ha.beta_src = &b.state->beta;
+    ha.gp_new = b.gp_new[n];
+    ha.gp_hat = b.gp_hat[n];
+    ha.err_part = n == N - 1 ? b.err_part : nullptr;
     if ((e = launch_hals(ha, h->num_cus, s)) != hipSuccess) return e;
-    GramJob gj{};
-    gj.nfac = 2;
-    gj.A[0] = b.A_new[n];
-    gj.out[0] = b.gp_new[n];
-    gj.rows[0] = I;
-    gj.A[1] = b.A_hat[n];
-    gj.out[1] = b.gp_hat[n];
-    gj.rows[1] = I;
-    if ((e = launch_gram_partials(gj, r, s)) != hipSuccess) return e;
   }
   const int64_t IN = T.dims[N - 1];
-  if ((e = launch_error_partials(b.P, b.A_new[N - 1], b.G64, IN, r, b.err_part, s)) !=
-      hipSuccess)
-    return e;
   DecideArgs d{};
   d.st = b.state;
   d.p = p;
   d.normT2 = b.normT2;
   d.partials = b.err_part;
-  d.nparts = error_partial_count(IN, r);
+  d.nparts = hals_wgs(IN, r);
   d.trace = trace;
   d.order = N;
   d.sweeps_src = b.sweeps;
@@ -175,7 +173,7 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
     sj.ddst[l] = b.gp_cur[l];
     sj.dnew[l] = b.gp_new[l];
     sj.dhat[l] = b.gp_hat[l];
-    sj.dn[l] = gram_chunks(T.dims[l]) * int64_t(r) * r;
+    sj.dn[l] = gram_chunks(T.dims[l], r) * int64_t(r) * r;
   }
   return launch_select(sj, b.state, s);
 }
@@ -257,13 +255,13 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
     HadamardJob hj{};
     for (int l = 0; l < N - 1; ++l) {
       hj.part[hj.nfac] = b.gp_cur[l];
-      hj.nchunks[hj.nfac] = gram_chunks(T->dims[l]);
+      hj.nchunks[hj.nfac] = gram_chunks(T->dims[l], r);
       hj.nfac++;
     }
-    NTF_HIP(launch_hadamard(hj, r, b.G32, b.G64, s));
+    NTF_HIP(launch_hadamard(hj, r, b.G32, b.G64, nullptr, 0, s));
     FactorPtrs fp{};
     for (int l = 0; l < N; ++l) fp.p[l] = A[l];
-    NTF_HIP(launch_mttkrp(plans[N - 1], T->data, fp, b.P, b.mt_part, nullptr, 0, s));
+    NTF_HIP(launch_mttkrp(plans[N - 1], T->data, fp, b.P, b.mt_part, true, s));
     const int64_t IN = T->dims[N - 1];
     NTF_HIP(launch_error_partials(b.P, A[N - 1], b.G64, IN, r, b.err_part, s));
     NTF_HIP(launch_error_finalize(b.normT2, b.err_part, error_partial_count(IN, r), b.fhat0,
