@@ -7,17 +7,17 @@
 
 namespace ntf {
 
-// Row layout of the A-HALS kernel: a row group of 16 lanes (r <= 16) or of a whole wave
+// Row layout of the A-HALS kernel: a row group of 16 lanes (r <= 32) or of a whole wave
 // (r <= 128); NR rows per group are processed together, NR as small as keeps the grid
 // within 256 workgroups of 4 waves. The rows of one workgroup are also one Gram chunk.
 __host__ __device__ inline int hals_rows_interleaved(int r, int64_t rows) {
-  const int64_t per_nr = 4 * (r <= 16 ? 4 : 1);  // rows per workgroup with NR = 1
+  const int64_t per_nr = 4 * (r <= 32 ? 4 : 1);  // rows per workgroup with NR = 1
   for (int nr = 1; nr < 4; nr *= 2)
     if ((rows + per_nr * nr - 1) / (per_nr * nr) <= 256) return nr;
   return 4;
 }
 __host__ __device__ inline int gram_chunk_rows(int r, int64_t rows) {
-  return 4 * (r <= 16 ? 4 : 1) * hals_rows_interleaved(r, rows);
+  return 4 * (r <= 32 ? 4 : 1) * hals_rows_interleaved(r, rows);
 }
 
 // out[p * r + q] = sum_{i < nrows} rows[i * r + p] * rows[i * r + q] in float64, rows taken

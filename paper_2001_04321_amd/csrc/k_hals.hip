@@ -2,24 +2,23 @@
 // with what surrounds it in an outer iteration of Algorithm 2.
 //
 // Rows of the block are independent NNLS problems coupled only through the stopping rule.
-// A group of L lanes owns one row and C columns per lane (lane g holds columns g*C ..
-// g*C+C-1); W and P of the row live in registers, G in LDS. Column j of a sweep: each
-// lane forms its share of sum_{l != j} W[l] G[l, j] (the term of the column updated just
-// before is added last, so the rest of the sum is off the dependency chain), a DPP
-// butterfly sums the group (every lane ends with the same bits), and the owner lane sets
-//   W[j] = max(0, P[j] - sum) / G[j, j]     (0 if G[j, j] = 0: a dead component).
+// A group of RPAD lanes (16 or 64) owns one row; lane g holds columns g, g + RPAD, ... The
+// column update W_j = max(0, P_j - sum_{l != j} W_l G_lj) / G_jj is computed as
+//   q_k = P_k / G_kk - sum_{l != k} W_l (G_lk / G_kk),   W_j <- max(0, q_j),
+// with q formed exactly at the start of each sweep and kept current by rank-one updates
+// (after W_j changes by delta, q_k -= delta G_jk / G_kk for every k != j). A dead component
+// (G_jj = 0) has q_j = 0, so it is 0 after its first update, as the method prescribes. The
+// rank is padded to a compile-time multiple of 8 with zero columns, whose updates are 0.
 //
 // Stopping rule: after sweep s every workgroup publishes its share of ||W_s - W_{s-1}||^2
-// (float64) in slot (s, wg) and counts itself in; the last workgroup to arrive sums the
-// slots in workgroup order and publishes the total, so every workgroup sees the same value
-// and takes the same decision. The rule for sweep s - K + 1 is evaluated after sweep s,
-// with the load of its total issued before the sweep, so the wait overlaps K - 1 sweeps of
-// work; a ring of the last K iterates (in LDS) restores the iterate the rule stops at.
-// Waits are bounded by a wall-clock deadline (timeout: NTF_FLAG_WAIT_TIMEOUT). The grid
-// never exceeds the CU count, so all workgroups are resident together.
+// (float64); one workgroup sums the shares in workgroup order and publishes the total, so
+// every workgroup sees the same value and takes the same decision. The rule for sweep
+// s - K + 1 is evaluated after sweep s, with the load of its total issued before the sweep;
+// a ring of the last K iterates (in LDS) restores the iterate the rule stops at. Waits are
+// bounded by a wall-clock deadline (timeout: NTF_FLAG_WAIT_TIMEOUT). The grid never
+// exceeds the CU count, so all workgroups are resident together.
 //
 // Fused around the sweeps (each optional):
-//  - prologue: P rows as the fixed-order sum of the MTTKRP's split partials;
 //  - epilogue: extrapolation A_hat = max(0, W + beta (W - W_0)) (eq. extproj_her), the
 //    float64 partial Grams of the new and extrapolated rows (Gram cache of the solver), and
 //    the workgroup's share of 2 <P, W> - <G, W^T W> for the restart surrogate F-hat.
@@ -36,9 +35,7 @@ constexpr uint64_t kSentinel = ~uint64_t(0);
 struct HKArgs {
   const float* W0;
   float* W;
-  const float* P;        // rows x r, or null when Ppart is used
-  const float* Ppart;    // [nsplit][rows][r] partial MTTKRP sums
-  int64_t nsplit;
+  const float* P;        // rows x r
   const float* G;        // r x r float32
   const double* G64;     // r x r float64 (for the F-hat share)
   int64_t rows;
@@ -104,7 +101,7 @@ __device__ __forceinline__ float bcast(float x, int o) {
     int v = 0;
     switch (o) {
 #define NTF_BC(n) \
-  case n: v = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x150 + n, 0xF, 0xF, false); break;
+  case n: v = __builtin_amdgcn_mov_dpp(__float_as_int(x), 0x150 + n, 0xF, 0xF, true); break;
       NTF_BC(0) NTF_BC(1) NTF_BC(2) NTF_BC(3) NTF_BC(4) NTF_BC(5) NTF_BC(6) NTF_BC(7)
       NTF_BC(8) NTF_BC(9) NTF_BC(10) NTF_BC(11) NTF_BC(12) NTF_BC(13) NTF_BC(14) NTF_BC(15)
 #undef NTF_BC
@@ -115,22 +112,26 @@ __device__ __forceinline__ float bcast(float x, int o) {
 }
 
 // RPAD lanes per row group (16: four groups per wave; 64: one per wave), C columns per
-// lane (lane g owns columns g, g + RPAD, ...), NR rows per group processed in lockstep.
-template <int RPAD, int C, int NR>
+// lane, NR rows per group processed in lockstep, NB blocks of 8 columns swept (8 NB >= r).
+template <int RPAD, int C, int NR, int NB>
 __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   constexpr int GPW = 64 / RPAD;        // row groups per wave
   constexpr int RPWV = GPW * NR;        // rows per wave
   constexpr int WPG = kThreads / 64;    // waves per workgroup
   constexpr int RPW = WPG * RPWV;       // rows per workgroup
-  constexpr int RMAX = RPAD * C;        // largest rank handled
+  constexpr int RMAX = RPAD * C;        // columns held per row group
+  constexpr int RB = NB * 8;            // columns swept
+  static_assert(RB <= RMAX, "column blocks exceed the row group");
+  // scaled G in registers when it fits, else read from LDS in blocks of 8 columns
+  constexpr bool GREG = RB * C <= 64;
   extern __shared__ __attribute__((aligned(16))) float smem[];
   // per-sweep LDS words alternate between two copies by sweep parity: a wave can reach the
   // next sweep's write only after a barrier that every reader of the current copy has passed
   __shared__ double s_part[2][WPG];
 
   const int r = a.r;
-  float* s_g = smem;               // G, r x RMAX (row j: G[j][0..RMAX), zero padded)
-  float* s_rows = s_g + r * RMAX;  // RPW x r: P block, then new rows
+  float* s_g = smem;               // scaled G, RB x RMAX: s_g[j][k] = G_jk / G_kk, 0 if j == k
+  float* s_rows = s_g + RB * RMAX;    // RPW x r: P block, then new rows
   float* s_rows2 = s_rows + RPW * r;  // RPW x r: extrapolated rows (ring follows)
 
   const int tid = threadIdx.x;
@@ -141,25 +142,21 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   const int64_t row0 = int64_t(blockIdx.x) * RPW;
   const int nrows = int(std::min<int64_t>(RPW, a.rows - row0));
 
-  for (int e = tid; e < r * RMAX; e += kThreads) {
+  for (int e = tid; e < RB * RMAX; e += kThreads) {
     const int j = e / RMAX;
-    const int l = e - j * RMAX;
-    s_g[e] = l < r ? a.G[j * r + l] : 0.f;
+    const int k = e - j * RMAX;
+    float v = 0.f;
+    if (j < r && k < r && j != k) {
+      const float gkk = a.G[k * r + k];
+      v = gkk != 0.f ? a.G[j * r + k] * (1.f / gkk) : 0.f;
+    }
+    s_g[e] = v;
   }
   // P block of this workgroup: rows row0 .. row0+nrows-1 are contiguous in memory
   {
-    const int64_t n = int64_t(nrows) * r;
-    const int64_t g0 = row0 * r;
-    const int64_t stride = a.rows * r;
-    for (int64_t e = tid; e < n; e += kThreads) {
-      if (a.Ppart) {
-        double acc = 0.0;
-        for (int64_t q = 0; q < a.nsplit; ++q) acc += double(a.Ppart[q * stride + g0 + e]);
-        s_rows[e] = float(acc);
-      } else {
-        s_rows[e] = a.P[g0 + e];
-      }
-    }
+    const int n = nrows * r;
+    const float* Pb = a.P + row0 * r;
+    for (int e = tid; e < n; e += kThreads) s_rows[e] = Pb[e];
   }
   __syncthreads();
 
@@ -171,80 +168,85 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
     lrow[q] = wave * RPWV + q * GPW + gi;
     rok[q] = lrow[q] < nrows;
   }
-  float w[NR][C], p[NR][C], w0[NR][C], d[NR][C], inv[C];
+  float w[NR][C], pinv[NR][C], w0[NR][C], qv[NR][C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const int j = c * RPAD + gl;
-    const float gjj = j < r ? s_g[j * RMAX + j] : 0.f;
-    inv[c] = gjj != 0.f ? 1.f / gjj : 0.f;
+    const int k = c * RPAD + gl;
+    const float gkk = k < r ? a.G[k * r + k] : 0.f;
+    const float inv = gkk != 0.f ? 1.f / gkk : 0.f;
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      const bool ok = rok[q] && j < r;
-      w0[q][c] = ok ? a.W0[(row0 + lrow[q]) * r + j] : 0.f;
-      p[q][c] = ok ? s_rows[lrow[q] * r + j] : 0.f;
-      // a dead component (G[j][j] = 0) is 0 after its first update and stays 0
-      w[q][c] = (ok && gjj != 0.f) ? w0[q][c] : 0.f;
+      const bool ok = rok[q] && k < r;
+      w0[q][c] = ok ? a.W0[(row0 + lrow[q]) * r + k] : 0.f;
+      pinv[q][c] = ok ? s_rows[lrow[q] * r + k] * inv : 0.f;
+      // a dead component (G_kk = 0) is 0 after its first update and stays 0
+      w[q][c] = (ok && gkk != 0.f) ? w0[q][c] : 0.f;
     }
+  }
+  float greg[GREG ? RB : 1][C];
+  if constexpr (GREG) {
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+#pragma unroll
+      for (int c = 0; c < C; ++c) greg[j][c] = s_g[j * RMAX + c * RPAD + gl];
   }
 
   const uint64_t t_start = wall_clock64();
 
-  // one Gauss-Seidel sweep over the columns. d = W G is formed exactly at the start of the
-  // sweep and kept current by rank-one updates: after column j changes by delta,
-  // d += delta * G[j, :]. The owner of column j then has d_j = sum_l W_l G_lj and
-  //   W_j <- max(0, W_j + (P_j - d_j) / G_jj) = max(0, P_j - sum_{l != j} W_l G_lj) / G_jj.
-  // Columns go in blocks of 8 (one branch per block); columns r .. (block end) are zero
-  // padding whose update is exactly 0. The G values of the next block are read from LDS
-  // while the current block is computed.
-  constexpr int NB = (RMAX + 7) / 8;
   auto load_gblk = [&](int jb, float (&gb)[8][C]) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int j = jb * 8 + t;
+    for (int t = 0; t < 8; ++t)
 #pragma unroll
-      for (int c = 0; c < C; ++c) gb[t][c] = j < r ? s_g[j * RMAX + c * RPAD + gl] : 0.f;
-    }
+      for (int c = 0; c < C; ++c)
+        gb[t][c] = GREG ? greg[GREG ? jb * 8 + t : 0][c] : s_g[(jb * 8 + t) * RMAX + c * RPAD + gl];
   };
+  // lanes owning column offset o of their group, as a wave-wide constant mask
   auto is_owner = [&](int o) {
-    int g = gl;
-    asm volatile("" : "+v"(g));  // keep the compare next to its use (no hoisted masks)
-    return g == o;
+    uint64_t m = 0;
+#pragma unroll
+    for (int g = 0; g < GPW; ++g) m |= uint64_t(1) << (g * RPAD + o);
+    return __builtin_amdgcn_inverse_ballot_w64(m);
   };
+  // one Gauss-Seidel sweep over the columns
   auto sweep = [&]() {
     float gb0[8][C], gb1[8][C];
+    // q = P / diag(G) - W G' with two interleaved accumulators (fixed order)
+    float acc[2][NR][C];
 #pragma unroll
     for (int q = 0; q < NR; ++q)
 #pragma unroll
-      for (int c = 0; c < C; ++c) d[q][c] = 0.f;
-    // d = W G
+      for (int c = 0; c < C; ++c) {
+        acc[0][q][c] = pinv[q][c];
+        acc[1][q][c] = 0.f;
+      }
     load_gblk(0, gb0);
 #pragma unroll
     for (int jb = 0; jb < NB; ++jb) {
-      if (jb * 8 >= r) break;
       float (&cur)[8][C] = (jb & 1) ? gb1 : gb0;
       float (&nxt)[8][C] = (jb & 1) ? gb0 : gb1;
-      if (jb + 1 < NB && (jb + 1) * 8 < r) load_gblk(jb + 1, nxt);
+      if (jb + 1 < NB) load_gblk(jb + 1, nxt);
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const int l = jb * 8 + t;
-        const int cs = l / RPAD;
-        const int o = l % RPAD;
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
-          const float wl = bcast<RPAD>(w[q][cs], o);
+          const float wl = bcast<RPAD>(w[q][l / RPAD], l % RPAD);
 #pragma unroll
-          for (int c = 0; c < C; ++c) d[q][c] = fmaf(wl, cur[t][c], d[q][c]);
+          for (int c = 0; c < C; ++c) acc[t & 1][q][c] = fmaf(-wl, cur[t][c], acc[t & 1][q][c]);
         }
       }
     }
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+#pragma unroll
+      for (int c = 0; c < C; ++c) qv[q][c] = acc[0][q][c] + acc[1][q][c];
     // column updates
     load_gblk(0, gb0);
 #pragma unroll
     for (int jb = 0; jb < NB; ++jb) {
-      if (jb * 8 >= r) break;
       float (&cur)[8][C] = (jb & 1) ? gb1 : gb0;
       float (&nxt)[8][C] = (jb & 1) ? gb0 : gb1;
-      if (jb + 1 < NB && (jb + 1) * 8 < r) load_gblk(jb + 1, nxt);
+      if (jb + 1 < NB) load_gblk(jb + 1, nxt);
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const int j = jb * 8 + t;
@@ -252,11 +254,11 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
         const int o = j % RPAD;
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
-          const float wn = fmaxf(fmaf(p[q][cs] - d[q][cs], inv[cs], w[q][cs]), 0.f);
+          const float wn = fmaxf(qv[q][cs], 0.f);
           const float delta = bcast<RPAD>(wn - w[q][cs], o);
           if (is_owner(o)) w[q][cs] = wn;
 #pragma unroll
-          for (int c = 0; c < C; ++c) d[q][c] = fmaf(delta, cur[t][c], d[q][c]);
+          for (int c = 0; c < C; ++c) qv[q][c] = fmaf(-delta, cur[t][c], qv[q][c]);
         }
       }
     }
@@ -435,7 +437,12 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
 
   // ---- epilogue: write W (and A_hat); stage rows for the Gram partials ----
   const double beta = a.A_hat ? *a.beta_src : 0.0;
-  __syncthreads();  // s_rows (P block) is no longer read
+  float pv_keep[NR][C];  // P entries of this lane's columns, read before the rows are replaced
+#pragma unroll
+  for (int q = 0; q < NR; ++q)
+#pragma unroll
+    for (int c = 0; c < C; ++c) pv_keep[q][c] = 0.f;
+  __syncthreads();  // every lane has its P entries in registers (pinv) by now
 #pragma unroll
   for (int q = 0; q < NR; ++q)
 #pragma unroll
@@ -444,6 +451,7 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
       if (rok[q] && j < r) {
         const int64_t gidx = (row0 + lrow[q]) * r + j;
         a.W[gidx] = w[q][c];
+        pv_keep[q][c] = s_rows[lrow[q] * r + j];
         s_rows[lrow[q] * r + j] = w[q][c];
         if (a.A_hat) {
           const double x = w[q][c];
@@ -470,7 +478,7 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
           double gw = 0.0;
           for (int l = 0; l < r; ++l)
             gw += a.G64[int64_t(j) * r + l] * double(s_rows[lrow[q] * r + l]);
-          t += double(w[q][c]) * (2.0 * double(p[q][c]) - gw);
+          t += double(w[q][c]) * (2.0 * double(pv_keep[q][c]) - gw);
         }
       }
     const double ws = wave_sum64(t);
@@ -487,26 +495,45 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
 
 using HFn = void (*)(HKArgs);
 
-template <int RPAD, int C>
+// number of 8-column blocks swept for rank r (r <= 128)
+int hals_nb(int r) {
+  if (r <= 32) return (r + 7) / 8;
+  if (r <= 64) return (r + 7) / 8;
+  return 2 * ((r + 15) / 16);
+}
+
+template <int RPAD, int C, int NB>
 HFn pick_nr(int nr) {
-  if (nr == 1) return hals_kernel<RPAD, C, 1>;
-  if (nr == 2) return hals_kernel<RPAD, C, 2>;
-  return hals_kernel<RPAD, C, 4>;
+  if (nr == 1) return hals_kernel<RPAD, C, 1, NB>;
+  if (nr == 2) return hals_kernel<RPAD, C, 2, NB>;
+  return hals_kernel<RPAD, C, 4, NB>;
 }
 
 HFn hals_fn(int r, int nr) {
-  if (r <= 16) return pick_nr<16, 1>(nr);
-  if (r <= 64) return pick_nr<64, 1>(nr);
-  return pick_nr<64, 2>(nr);
+  switch (hals_nb(r)) {
+    case 1: return pick_nr<16, 1, 1>(nr);
+    case 2: return pick_nr<16, 1, 2>(nr);
+    case 3: return pick_nr<16, 2, 3>(nr);
+    case 4: return pick_nr<16, 2, 4>(nr);
+    case 5: return pick_nr<64, 1, 5>(nr);
+    case 6: return pick_nr<64, 1, 6>(nr);
+    case 7: return pick_nr<64, 1, 7>(nr);
+    case 8: return pick_nr<64, 1, 8>(nr);
+    case 10: return pick_nr<64, 2, 10>(nr);
+    case 12: return pick_nr<64, 2, 12>(nr);
+    case 14: return pick_nr<64, 2, 14>(nr);
+    default: return pick_nr<64, 2, 16>(nr);
+  }
 }
 
 size_t hals_lds(int r, int64_t rows) {
-  const int rmax = r <= 16 ? 16 : (r <= 64 ? 64 : 128);
-  const int c = r <= 64 ? 1 : 2;
+  const int rpad = r <= 32 ? 16 : 64;
+  const int c = r <= 16 ? 1 : (r <= 32 ? 2 : (r <= 64 ? 1 : 2));
+  const int rb = 8 * hals_nb(r);
   const int nr = hals_rows_interleaved(r, rows);
   const int rpw = gram_chunk_rows(r, rows);
   const size_t ring = size_t(kWindow) * nr * c * kThreads;
-  return (size_t(r) * rmax + 2 * size_t(rpw) * r + ring) * sizeof(float);
+  return (size_t(rb) * rpad * c + 2 * size_t(rpw) * r + ring) * sizeof(float);
 }
 
 }  // namespace
@@ -528,8 +555,6 @@ hipError_t launch_hals(const HalsArgs& h, int num_cus, hipStream_t s) {
   a.W0 = h.W0;
   a.W = h.W;
   a.P = h.P;
-  a.Ppart = h.Ppart;
-  a.nsplit = h.nsplit;
   a.G = h.G;
   a.G64 = h.G64;
   a.rows = h.rows;
@@ -559,7 +584,7 @@ hipError_t launch_hals(const HalsArgs& h, int num_cus, hipStream_t s) {
   const size_t lds = hals_lds(h.r, h.rows);
   static bool attr_done = false;
   if (!attr_done) {
-    for (int rr : {16, 64, 128})
+    for (int rr : {8, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128})
       for (int nr : {1, 2, 4}) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(hals_fn(rr, nr)),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,

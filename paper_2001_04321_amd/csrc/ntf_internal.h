@@ -175,9 +175,7 @@ hipError_t launch_fill_sentinel(double* slots, int64_t n, hipStream_t s);
 struct HalsArgs {
   const float* W0;       // warm start (may equal W)
   float* W;              // result
-  const float* P;        // MTTKRP rows x r (when Ppart is null)
-  const float* Ppart;    // or split partials [nsplit][rows][r]
-  int64_t nsplit;
+  const float* P;        // MTTKRP rows x r
   const float* G;        // r x r float32
   const double* G64;     // r x r float64, needed with err_part
   int64_t rows;

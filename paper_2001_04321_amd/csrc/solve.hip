@@ -133,8 +133,6 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
     ha.W0 = A[n];
     ha.W = b.A_new[n];
     ha.P = b.P;
-    ha.Ppart = nullptr;
-    ha.nsplit = 1;
     ha.G = b.G32;
     ha.G64 = b.G64;
     ha.rows = I;
