@@ -5,8 +5,8 @@
 // A group of RPAD lanes (16 or 64) owns one row; lane g holds columns g, g + RPAD, ... The
 // column update W_j = max(0, P_j - sum_{l != j} W_l G_lj) / G_jj is computed as
 //   q_k = P_k / G_kk - sum_{l != k} W_l (G_lk / G_kk),   W_j <- max(0, q_j),
-// with q formed exactly at the start of each sweep and kept current by rank-one updates
-// (after W_j changes by delta, q_k -= delta G_jk / G_kk for every k != j). A dead component
+// with q kept current by rank-one updates (after W_j changes by delta, q_k -= delta G_jk /
+// G_kk for every k != j) and formed from scratch every kRefresh sweeps. A dead component
 // (G_jj = 0) has q_j = 0, so it is 0 after its first update, as the method prescribes. The
 // rank is padded to a compile-time multiple of 8 with zero columns, whose updates are 0.
 //
@@ -29,7 +29,9 @@ namespace ntf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kWindow = 6;  // sweeps between publishing a slot and waiting on it
+constexpr int kBatch = 4;    // sweeps per stopping-rule exchange
+constexpr int kRing = 3 * kBatch;  // iterates kept: a decision lags at most 3 batches - 1
+constexpr int kRefresh = 4;  // sweeps between exact recomputations of q
 constexpr uint64_t kSentinel = ~uint64_t(0);
 
 struct HKArgs {
@@ -127,7 +129,8 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   extern __shared__ __attribute__((aligned(16))) float smem[];
   // per-sweep LDS words alternate between two copies by sweep parity: a wave can reach the
   // next sweep's write only after a barrier that every reader of the current copy has passed
-  __shared__ double s_part[2][WPG];
+  __shared__ double s_part[2][WPG][kBatch];
+  __shared__ int s_dec[3];  // [b & 1]: decision at exchange b; [2]: after the last sweep
 
   const int r = a.r;
   float* s_g = smem;               // scaled G, RB x RMAX: s_g[j][k] = G_jk / G_kk, 0 if j == k
@@ -207,10 +210,9 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
     for (int g = 0; g < GPW; ++g) m |= uint64_t(1) << (g * RPAD + o);
     return __builtin_amdgcn_inverse_ballot_w64(m);
   };
-  // one Gauss-Seidel sweep over the columns
-  auto sweep = [&]() {
+  // q = P / diag(G) - W G' from scratch, two interleaved accumulators (fixed order)
+  auto refresh = [&]() {
     float gb0[8][C], gb1[8][C];
-    // q = P / diag(G) - W G' with two interleaved accumulators (fixed order)
     float acc[2][NR][C];
 #pragma unroll
     for (int q = 0; q < NR; ++q)
@@ -240,7 +242,12 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
     for (int q = 0; q < NR; ++q)
 #pragma unroll
       for (int c = 0; c < C; ++c) qv[q][c] = acc[0][q][c] + acc[1][q][c];
-    // column updates
+  };
+  // one Gauss-Seidel sweep over the columns; every q_k (also k < j) follows each update, so
+  // q stays current across sweeps and is refreshed from scratch only every kRefresh sweeps
+  // to bound the drift of the rank-one updates
+  auto sweep = [&]() {
+    float gb0[8][C], gb1[8][C];
     load_gblk(0, gb0);
 #pragma unroll
     for (int jb = 0; jb < NB; ++jb) {
@@ -264,11 +271,15 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
     }
   };
 
-  // Per sweep s (1-based) the sync area holds nwg workgroup slots, one arrival counter and
-  // one total, all starting at the sentinel (all ones; the counter then counts from -1).
-  uint64_t* const slots = a.slots;
-  uint64_t* const counters = a.slots + int64_t(a.max_sweeps) * a.nwg;
-  uint64_t* const totals = counters + a.max_sweeps;
+  // Stopping-rule exchange, every kBatch sweeps (batch b = sweeps (b-1)M+1 .. bM, M =
+  // kBatch). At exchange b every workgroup stores its shares of ||W_t - W_{t-1}||^2 for the
+  // sweeps of batch b in slot (b, wg) and issues the loads of all slots of batch b - 1; the
+  // values arrive while the next batch is computed and are summed, in workgroup order, at
+  // exchange b + 1, which decides the sweeps of batch b - 1. Every workgroup sums the same
+  // values in the same order, so all take the same decision. A slot still at the sentinel
+  // (its owner is behind) is re-read until it lands. Iterates are kept in an LDS ring long
+  // enough to restore the sweep the rule stops at.
+  uint64_t* const slots = a.slots;  // [batch][wg][kBatch]
   auto spin_load = [&](const uint64_t* addr, bool& timeout) -> uint64_t {
     uint64_t v = __hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     while (v == kSentinel) {
@@ -281,90 +292,55 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
     }
     return v;
   };
-  // Publishing this workgroup's share of ||W_s - W_{s-1}||^2 (publish(s)): the share goes
-  // to its slot and the sweep's arrival counter is incremented. Everything after the
-  // barrier runs in wave 0 and never waits for memory issued in the same call: the
-  // counter's previous value is read at publish(s + 1), where the workgroup that arrived
-  // last for sweep s issues the loads of all shares of sweep s; at publish(s + 2) it sums
-  // them in workgroup order and stores the total. The total of sweep s is first needed
-  // kWindow - 1 sweeps after sweep s.
-  uint64_t pending_old = 0;  // lane 0 of wave 0: counter value before this workgroup's add
-  uint64_t u[4];             // wave 0: shares loaded for sweep `agg` (nwg <= 256)
-  int agg = 0;               // sweep whose total this workgroup owes, 0 for none
-  bool pub_to = false;       // wave 0: a share never appeared
-  auto agg_finish = [&]() {
-    const uint64_t* sl = slots + int64_t(agg - 1) * a.nwg;
+  uint64_t u[4][kBatch];  // wave 0: slots of batch `lb` (workgroups lane, lane + 64, ...)
+  int lb = 0;             // batch whose slots are in flight in u, 0 for none
+  auto issue_loads = [&](int bb) {
+    const uint64_t* sl = slots + int64_t(bb - 1) * a.nwg * kBatch;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int m = 0; m < kBatch; ++m)
+        u[k][m] = lane + 64 * k < a.nwg
+                      ? __hip_atomic_load(&sl[int64_t(lane + 64 * k) * kBatch + m],
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                      : 0;
+    lb = bb;
+  };
+  // wave 0: totals of batch lb; false if a wait timed out
+  auto totals_of = [&](double (&D)[kBatch]) -> bool {
+    const uint64_t* sl = slots + int64_t(lb - 1) * a.nwg * kBatch;
     bool to = false;
-    double v = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      // a share whose store is not visible yet still reads as the sentinel
-      if (lane + 64 * k < a.nwg && u[k] == kSentinel) u[k] = spin_load(&sl[lane + 64 * k], to);
-      v += __longlong_as_double(int64_t(u[k]));
+    for (int m = 0; m < kBatch; ++m) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (lane + 64 * k < a.nwg && u[k][m] == kSentinel)
+          u[k][m] = spin_load(&sl[int64_t(lane + 64 * k) * kBatch + m], to);
+        v += __longlong_as_double(int64_t(u[k][m]));
+      }
+      D[m] = wave_sum64(v);
     }
-    const double D = wave_sum64(v);
-    pub_to = pub_to || __any(to);
-    if (lane == 0)
-      __hip_atomic_store(&totals[agg - 1], uint64_t(__double_as_longlong(D)), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    agg = 0;
+    return !__any(to);
   };
-  auto publish = [&](int s, const float (&prev)[NR][C]) {
-    double d2 = 0.0;
+  // stopping rule over the sweeps t of batch lb (t <= last): first t with
+  // ||dW_t||^2 <= tol^2 ||dW_1||^2; returns t, 0 for none, -1 on a timeout
+  double lim = 0.0;
+  const double tol2 = a.tol * a.tol;
+  auto rule = [&](int last) -> int {
+    double D[kBatch];
+    if (!totals_of(D)) return -1;
 #pragma unroll
-    for (int q = 0; q < NR; ++q)
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const double df = double(w[q][c]) - double(prev[q][c]);
-        d2 += df * df;
-      }
-    const double ws = wave_sum64(d2);
-    if (lane == 0) s_part[s & 1][wave] = ws;
-    __syncthreads();
-    if (wave == 0) {
-      // order: consume what arrived during the sweep, then issue the new memory operations,
-      // so that no wait here covers an operation issued in the same call
-      const uint64_t old =
-          (uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(pending_old >> 32)))) << 32) |
-          uint32_t(__builtin_amdgcn_readfirstlane(int(pending_old)));
-      if (agg > 0) agg_finish();
-      if (lane == 0) {
-        double t = 0.0;
-        for (int k = 0; k < WPG; ++k) t += s_part[s & 1][k];
-        __hip_atomic_store(&slots[int64_t(s - 1) * a.nwg + blockIdx.x],
-                           uint64_t(__double_as_longlong(t)), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        pending_old = __hip_atomic_fetch_add(&counters[s - 1], uint64_t(1), __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (s > 1 && int64_t(old) == int64_t(a.nwg) - 2) {  // last for sweep s-1 (counts from -1)
-        agg = s - 1;
-        const uint64_t* sl = slots + int64_t(agg - 1) * a.nwg;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          u[k] = lane + 64 * k < a.nwg ? __hip_atomic_load(&sl[lane + 64 * k], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT)
-                                       : 0;
-      }
+    for (int m = 0; m < kBatch; ++m) {
+      const int t = (lb - 1) * kBatch + m + 1;
+      if (t > last) break;
+      if (t == 1) lim = tol2 * D[m];
+      if (D[m] <= lim) return t;
     }
-  };
-  // total of sweep sp, loaded a window ahead of use
-  uint64_t pv = 0;
-  auto issue_poll = [&](int sp) {
-    pv = __hip_atomic_load(&totals[sp - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  };
-  // stopping rule for sweep sp: 0 continue, 1 stop, 2 timed out
-  double d1 = 0.0;
-  auto decide = [&](int sp) -> int {
-    bool to = false;
-    if (pv == kSentinel) pv = spin_load(&totals[sp - 1], to);
-    if (to) return 2;
-    const double delta = sqrt(__longlong_as_double(int64_t(pv)));
-    if (sp == 1) d1 = delta;
-    return delta <= a.tol * d1 ? 1 : 0;
+    return 0;
   };
 
-  // ring of the last kWindow iterates in LDS: [slot][q * C + c][thread]
+  // ring of the last kRing iterates in LDS: [slot][q * C + c][thread]
   float* s_ring = s_rows2 + RPW * r;
   auto ring_put = [&](int slot) {
 #pragma unroll
@@ -378,60 +354,103 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
 #pragma unroll
       for (int c = 0; c < C; ++c) w[q][c] = s_ring[(slot * NR * C + q * C + c) * kThreads + tid];
   };
+
+  double sh[kBatch];  // this thread's shares of the current batch
+#pragma unroll
+  for (int m = 0; m < kBatch; ++m) sh[m] = 0.0;
   int done = a.max_sweeps;
   bool timed_out = false;
-  bool finished = false;
-  for (int s = 1; s <= a.max_sweeps; ++s) {
-    const int sp = s - kWindow + 1;  // rule evaluated after this sweep
-    if (sp >= 1) issue_poll(sp);
+  bool stopped = false;
+  const int S = a.max_sweeps;
+  for (int s = 1; s <= S; ++s) {
     float prev[NR][C];
 #pragma unroll
     for (int q = 0; q < NR; ++q)
 #pragma unroll
       for (int c = 0; c < C; ++c) prev[q][c] = s == 1 ? w0[q][c] : w[q][c];
+    if ((s - 1) % kRefresh == 0) refresh();
     sweep();
-    ring_put(s % kWindow);
-    // the rule is checked before this sweep's share goes out, so that the wait for the
-    // total does not also wait for this sweep's counter update; on a stop every workgroup
-    // stops at the same sweep (they read the same total), so none needs the skipped share
-    if (sp >= 1) {
-      const int st = decide(sp);
-      if (st == 1) {
-        ring_get(sp % kWindow);
-        done = sp;
-        finished = true;
-        break;
-      }
-      if (st == 2) {
-        done = s;
-        timed_out = true;
-        finished = true;
-        break;
-      }
+    ring_put(s % kRing);
+    {
+      double d2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const double df = double(w[q][c]) - double(prev[q][c]);
+          d2 = fma(df, df, d2);
+        }
+      const int m0 = (s - 1) % kBatch;
+#pragma unroll
+      for (int m = 0; m < kBatch; ++m)
+        if (m == m0) sh[m] = d2;
     }
-    publish(s, prev);
-  }
-  if (!finished) {
-    // The total of sweep S-1 may still be owed (its loads were issued at publish(S)); the
-    // total of sweep S itself is never needed.
-    const int S = a.max_sweeps;
-    if (wave == 0 && agg > 0) agg_finish();
-    // rules not evaluated yet: sweeps max(1, S-K+2) .. S-1, in order
-    for (int sp = std::max(1, S - kWindow + 2); sp <= S - 1; ++sp) {
-      issue_poll(sp);
-      const int st = decide(sp);
-      if (st == 1) {
-        ring_get(sp % kWindow);
-        done = sp;
-        break;
+    if (s % kBatch != 0 && s != S) continue;
+
+    // ---- exchange b ----
+    const int b = (s + kBatch - 1) / kBatch;
+#pragma unroll
+    for (int m = 0; m < kBatch; ++m) {
+      const double ws = wave_sum64(sh[m]);
+      if (lane == 0) s_part[b & 1][wave][m] = ws;
+      sh[m] = 0.0;
+    }
+    // wave 0 decides batch b - 2 (loads issued at exchange b - 1) before the barrier
+    if (wave == 0) {
+      int st = 0;
+      if (lb > 0) st = rule(S);
+      if (lane == 0) s_dec[b & 1] = st;
+    }
+    __syncthreads();
+    const int st = s_dec[b & 1];
+    if (wave == 0) {
+      if (lane == 0) {
+        uint64_t* sl = slots + (int64_t(b - 1) * a.nwg + blockIdx.x) * kBatch;
+#pragma unroll
+        for (int m = 0; m < kBatch; ++m) {
+          double t = 0.0;
+          for (int k = 0; k < WPG; ++k) t += s_part[b & 1][k][m];
+          __hip_atomic_store(&sl[m], uint64_t(__double_as_longlong(t)), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
-      if (st == 2) {
-        timed_out = true;
-        break;
-      }
+      if (st == 0 && b >= 2) issue_loads(b - 1);
+    }
+    if (st > 0) {
+      ring_get(st % kRing);
+      done = st;
+      stopped = true;
+      break;
+    }
+    if (st < 0) {
+      done = s;
+      timed_out = true;
+      stopped = true;
+      break;
     }
   }
-  if ((timed_out || pub_to) && lane == 0)
+  if (!stopped) {
+    // all S sweeps ran: decide batches B - 1 (loads in flight) and B, sweeps t <= S - 1
+    const int B = (S + kBatch - 1) / kBatch;
+    if (wave == 0) {
+      int st = 0;
+      if (lb > 0) st = rule(S - 1);
+      if (st == 0) {
+        issue_loads(B);
+        st = rule(S - 1);
+      }
+      if (lane == 0) s_dec[2] = st;
+    }
+    __syncthreads();
+    const int st = s_dec[2];
+    if (st > 0) {
+      ring_get(st % kRing);
+      done = st;
+    } else if (st < 0) {
+      timed_out = true;
+    }
+  }
+  if (timed_out && lane == 0)
     __hip_atomic_fetch_or(a.flags, NTF_FLAG_WAIT_TIMEOUT, __ATOMIC_RELAXED,
                           __HIP_MEMORY_SCOPE_AGENT);
 
@@ -482,11 +501,11 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
         }
       }
     const double ws = wave_sum64(t);
-    if (lane == 0) s_part[0][wave] = ws;
+    if (lane == 0) s_part[0][wave][0] = ws;
     __syncthreads();
     if (tid == 0) {
       double e = 0.0;
-      for (int k = 0; k < WPG; ++k) e += s_part[0][k];
+      for (int k = 0; k < WPG; ++k) e += s_part[0][k][0];
       a.err_part[blockIdx.x] = e;
     }
   }
@@ -532,7 +551,7 @@ size_t hals_lds(int r, int64_t rows) {
   const int rb = 8 * hals_nb(r);
   const int nr = hals_rows_interleaved(r, rows);
   const int rpw = gram_chunk_rows(r, rows);
-  const size_t ring = size_t(kWindow) * nr * c * kThreads;
+  const size_t ring = size_t(kRing) * nr * c * kThreads;
   return (size_t(rb) * rpad * c + 2 * size_t(rpw) * r + ring) * sizeof(float);
 }
 
@@ -546,8 +565,8 @@ bool hals_supported(int64_t rows, int r, int num_cus) {
 }
 
 int64_t hals_slot_count(int64_t rows, int r, int max_sweeps) {
-  // per sweep: one slot per workgroup, an arrival counter and the total
-  return (hals_wgs(rows, r) + 2) * int64_t(max_sweeps);
+  // per batch of kBatch sweeps: kBatch shares per workgroup
+  return ceil_div(int64_t(max_sweeps), int64_t(kBatch)) * hals_wgs(rows, r) * kBatch;
 }
 
 hipError_t launch_hals(const HalsArgs& h, int num_cus, hipStream_t s) {
