@@ -161,7 +161,8 @@ ntf_status ntf_gram(ntf_handle* h, const float* const* A, const int64_t* rows, i
  * ||W_1 - W_0||_F (Sec. 4.1; norms in float64). tol = 0 runs until a sweep changes
  * nothing or max_sweeps is reached. A column with G[j, j] = 0 is set to 0.
  * W: rows x r, in place (input = warm start). P: rows x r. G: r x r float32, symmetric.
- * sweeps_done: device int32 or NULL. rows <= 8192 for r <= 32, <= 4096 otherwise. */
+ * sweeps_done: device int32 or NULL. rows <= 16384 for r <= 32, <= 4096 for r <= 128;
+ * r > 128 or more rows return NTF_EUNSUPPORTED. */
 ntf_status ntf_hals_update(ntf_handle* h, float* W, const float* P, const float* G,
                            int64_t rows, int32_t r, int32_t max_sweeps, double tol,
                            int32_t* sweeps_done, void* stream);
@@ -199,6 +200,24 @@ ntf_status ntf_error(ntf_handle* h, const double* normT2, const float* P, const 
 ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, float* const* A,
                      const ntf_her_params* params, int32_t iters, ntf_her_state* state,
                      int32_t resume, const ntf_trace* trace, void* stream);
+
+/* Squared-error loss L = ||T - [[A_1..A_N]]||_F^2 (the objective of eq. objFun without
+ * its 1/2) by the Gram trick of Sec. 3.1.3, all in float64:
+ * L = ||T||^2 - 2 <P, A> + <G, A^T A>, with A the factor of some mode n, P its MTTKRP and
+ * G the float64 Hadamard product of the other factors' Grams (ntf_gram with exclude = n).
+ * normT2, loss: device doubles (loss overwritten). P, A: rows x r float32. */
+ntf_status ntf_cp_loss(ntf_handle* h, const double* normT2, const float* P, const float* A,
+                       const double* G, int64_t rows, int32_t r, double* loss, void* stream);
+
+/* Gradient of the loss with respect to factor n (Sec. 2, eq. def:grad):
+ * grad = alpha * s * (A G - P), s = *scale (a device double, e.g. the incoming gradient of
+ * the loss in reverse-mode differentiation) or 1 when scale is NULL. alpha = 2 gives the
+ * gradient of L above, alpha = 1 that of the paper's F. A, P, grad: rows x r float32 (grad
+ * overwritten; it may not alias A or P); G: r x r float64 from ntf_gram(exclude = n).
+ * Accumulation in float64. */
+ntf_status ntf_cp_grad(ntf_handle* h, const float* A, const float* P, const double* G,
+                       int64_t rows, int32_t r, const double* scale, float alpha, float* grad,
+                       void* stream);
 
 /* || T - [[A_1..A_N]] ||_F^2 from the explicit residual, float64 accumulation (the data
  * fitting error of Sec. 4.1, eq. err_true_def, times 2). out: device double. */

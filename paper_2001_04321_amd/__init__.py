@@ -5,8 +5,8 @@ declared in include/ntf.h and calls it; all arithmetic runs in the library's HIP
 There is no CPU fallback: if libntf.so is missing the import of a call raises.
 
 Functions carry the C names: ntf_norm2, ntf_cast_bf16, ntf_mttkrp, ntf_gram,
-ntf_hals_update, ntf_her_step, ntf_error, ntf_solve, ntf_residual_norm2, plus the
-autograd loss in `paper_2001_04321_amd.autograd`.
+ntf_hals_update, ntf_her_step, ntf_error, ntf_solve, ntf_residual_norm2, ntf_cp_loss,
+ntf_cp_grad, plus the autograd loss `NTFLoss` / `ntf_loss` (module `autograd`).
 """
 from __future__ import annotations
 
@@ -21,7 +21,8 @@ from ._abi import NtfError, check, i64_array, lib, ptr_array
 __all__ = [
     "Handle", "HerParams", "NtfError", "handle", "ntf_norm2", "ntf_cast_bf16", "ntf_mttkrp",
     "ntf_gram", "ntf_hals_update", "ntf_her_step", "ntf_error", "ntf_solve",
-    "ntf_residual_norm2", "ntf_device_flags", "new_state", "state_dict",
+    "ntf_residual_norm2", "ntf_device_flags", "new_state", "state_dict", "ntf_cp_loss",
+    "ntf_cp_grad", "NTFLoss", "ntf_loss",
 ]
 
 _DTYPES = {torch.float32: _abi.NTF_F32, torch.bfloat16: _abi.NTF_BF16}
@@ -197,6 +198,31 @@ def ntf_error(normT2: torch.Tensor, P: torch.Tensor, A: torch.Tensor, G64: torch
     return out
 
 
+def ntf_cp_loss(normT2: torch.Tensor, P: torch.Tensor, A: torch.Tensor, G64: torch.Tensor,
+                out: torch.Tensor | None = None, h=None, stream=None) -> torch.Tensor:
+    """||T - [[A]]||^2 by the float64 Gram trick from one mode's P, A and G (no 1/2)."""
+    out = torch.empty((), dtype=torch.float64, device=P.device) if out is None else out
+    rows, r = A.shape
+    check(lib().ntf_cp_loss(_h(h), _dev(normT2, "normT2", torch.float64),
+                            _dev(P, "P", torch.float32), _dev(A, "A", torch.float32),
+                            _dev(G64, "G", torch.float64), rows, r,
+                            _dev(out, "loss", torch.float64), _stream(stream)))
+    return out
+
+
+def ntf_cp_grad(A: torch.Tensor, P: torch.Tensor, G64: torch.Tensor,
+                scale: torch.Tensor | None = None, alpha: float = 2.0,
+                out: torch.Tensor | None = None, h=None, stream=None) -> torch.Tensor:
+    """alpha * scale * (A G - P): the loss gradient for one factor (scale: device double)."""
+    out = torch.empty_like(A) if out is None else out
+    rows, r = A.shape
+    check(lib().ntf_cp_grad(_h(h), _dev(A, "A", torch.float32), _dev(P, "P", torch.float32),
+                            _dev(G64, "G", torch.float64), rows, r,
+                            _dev(scale, "scale", torch.float64) if scale is not None else None,
+                            float(alpha), _dev(out, "grad", torch.float32), _stream(stream)))
+    return out
+
+
 def ntf_residual_norm2(T: torch.Tensor, factors, h=None, stream=None) -> torch.Tensor:
     out = torch.empty((), dtype=torch.float64, device=T.device)
     d = _tensor_desc(T)
@@ -242,3 +268,6 @@ def ntf_device_flags(h=None, stream=None) -> int:
     v = C.c_uint32()
     check(lib().ntf_device_flags(_h(h), _stream(stream), C.byref(v)))
     return int(v.value)
+
+
+from .autograd import NTFLoss, ntf_loss  # noqa: E402

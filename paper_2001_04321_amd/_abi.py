@@ -63,6 +63,9 @@ SIGNATURES = {
     "ntf_solve": (C.c_int, [PTR, C.POINTER(NtfTensor), C.c_int32, PTRS,
                             C.POINTER(NtfHerParams), C.c_int32, PTR, C.c_int32,
                             C.POINTER(NtfTrace), PTR]),
+    "ntf_cp_loss": (C.c_int, [PTR, PTR, PTR, PTR, PTR, C.c_int64, C.c_int32, PTR, PTR]),
+    "ntf_cp_grad": (C.c_int, [PTR, PTR, PTR, PTR, C.c_int64, C.c_int32, PTR, C.c_float, PTR,
+                              PTR]),
     "ntf_residual_norm2": (C.c_int, [PTR, C.POINTER(NtfTensor), PTRS, C.c_int32, PTR, PTR]),
 }
 

@@ -5,6 +5,8 @@
 #include <cstdio>
 #include <cstring>
 
+#include <cmath>
+
 #include "ntf_internal.h"
 
 namespace ntf {
@@ -390,6 +392,38 @@ ntf_status ntf_error(ntf_handle* h, const double* normT2, const float* P, const 
   double* part = reinterpret_cast<double*>(h->ws);
   NTF_HIP(launch_error_partials(P, A, G, rows, r, part, s));
   NTF_HIP(launch_error_finalize(normT2, part, np, fhat, h->dev_flags, s));
+  return NTF_OK;
+}
+
+ntf_status ntf_cp_loss(ntf_handle* h, const double* normT2, const float* P, const float* A,
+                       const double* G, int64_t rows, int32_t r, double* loss, void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_rank(r);
+  if (st) return st;
+  NTF_RETURN_IF(!normT2 || !P || !A || !G || !loss, NTF_EINVAL, "NULL argument");
+  NTF_RETURN_IF(rows < 1, NTF_EINVAL, "rows < 1");
+  const int64_t np = error_partial_count(rows, r);
+  st = ensure_workspace(h, size_t(np) * sizeof(double) + 256);
+  if (st) return st;
+  hipStream_t s = as_stream(stream);
+  double* part = reinterpret_cast<double*>(h->ws);
+  NTF_HIP(launch_error_partials(P, A, G, rows, r, part, s));
+  NTF_HIP(launch_error_finalize(normT2, part, np, loss, h->dev_flags, s, 1.0));
+  return NTF_OK;
+}
+
+ntf_status ntf_cp_grad(ntf_handle* h, const float* A, const float* P, const double* G,
+                       int64_t rows, int32_t r, const double* scale, float alpha, float* grad,
+                       void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_rank(r);
+  if (st) return st;
+  NTF_RETURN_IF(!A || !P || !G || !grad, NTF_EINVAL, "NULL argument");
+  NTF_RETURN_IF(rows < 1, NTF_EINVAL, "rows < 1");
+  NTF_RETURN_IF(!std::isfinite(alpha), NTF_EINVAL, "alpha is not finite");
+  NTF_HIP(launch_cp_grad(A, P, G, rows, r, scale, alpha, grad, as_stream(stream)));
   return NTF_OK;
 }
 

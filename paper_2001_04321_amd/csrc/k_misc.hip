@@ -161,13 +161,33 @@ __device__ void flag_set(uint32_t* flags, uint32_t bit) {
 __global__ __launch_bounds__(256) void error_finalize_kernel(const double* normT2,
                                                              const double* partials,
                                                              int64_t nparts, double* fhat,
-                                                             uint32_t* flags) {
+                                                             uint32_t* flags, double scale) {
   const double s = ordered_sum(partials, nparts);
   if (threadIdx.x == 0) {
-    const double f = 0.5 * (*normT2 - s);
+    const double f = scale * (*normT2 - s);
     if (!isfinite(f)) flag_set(flags, NTF_FLAG_NONFINITE);
     *fhat = f;
   }
+}
+
+// Gradient of the squared-error loss with respect to one factor (Sec. 2, eq. def:grad):
+// out[i, p] = alpha * scale * (sum_l A[i, l] G[l, p] - P[i, p]), with G the Hadamard product
+// of the other factors' Grams and P the MTTKRP of the factor's mode; float64 accumulation.
+__global__ __launch_bounds__(256) void cp_grad_kernel(const float* __restrict__ A,
+                                                      const float* __restrict__ P,
+                                                      const double* __restrict__ G,
+                                                      int64_t rows, int r,
+                                                      const double* __restrict__ scale,
+                                                      float alpha, float* __restrict__ out) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= rows * r) return;
+  const int64_t i = e / r;
+  const int p = int(e - i * r);
+  const float* ai = A + i * r;
+  double g = 0.0;
+  for (int l = 0; l < r; ++l) g += double(ai[l]) * G[int64_t(l) * r + p];
+  const double f = double(alpha) * (scale ? *scale : 1.0);
+  out[e] = float(f * (g - double(P[e])));
 }
 
 __global__ void her_init_kernel(ntf_her_state* st, double beta0, const double* fhat0) {
@@ -343,9 +363,17 @@ hipError_t launch_error_partials(const float* P, const float* A, const double* G
 }
 
 hipError_t launch_error_finalize(const double* normT2, const double* partials, int64_t nparts,
-                                 double* fhat, uint32_t* flags, hipStream_t s) {
+                                 double* fhat, uint32_t* flags, hipStream_t s, double scale) {
   hipLaunchKernelGGL(error_finalize_kernel, dim3(1), dim3(256), 0, s, normT2, partials, nparts,
-                     fhat, flags);
+                     fhat, flags, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_cp_grad(const float* A, const float* P, const double* G, int64_t rows, int r,
+                          const double* scale, float alpha, float* out, hipStream_t s) {
+  const int64_t n = rows * r;
+  hipLaunchKernelGGL(cp_grad_kernel, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s, A, P, G,
+                     rows, r, scale, alpha, out);
   return hipGetLastError();
 }
 

@@ -202,9 +202,13 @@ hipError_t launch_extrapolate(const float* a_new, const float* a_old, float* out
 int64_t error_partial_count(int64_t rows, int r);
 hipError_t launch_error_partials(const float* P, const float* A, const double* G, int64_t rows,
                                  int r, double* partials, hipStream_t s);
-// F-hat = 1/2 (normT2 - sum partials) into *fhat.
+// scale * (normT2 - sum partials) into *out (scale 1/2: F-hat; 1: the squared-error loss).
 hipError_t launch_error_finalize(const double* normT2, const double* partials, int64_t nparts,
-                                 double* fhat, uint32_t* flags, hipStream_t s);
+                                 double* out, uint32_t* flags, hipStream_t s,
+                                 double scale = 0.5);
+// out = alpha * (*scale or 1) * (A G - P), rows x r (loss gradient of one factor).
+hipError_t launch_cp_grad(const float* A, const float* P, const double* G, int64_t rows, int r,
+                          const double* scale, float alpha, float* out, hipStream_t s);
 
 // HER state kernels.
 hipError_t launch_her_init(ntf_her_state* st, const ntf_her_params& p, const double* fhat0,
