@@ -219,6 +219,33 @@ ntf_status ntf_cp_grad(ntf_handle* h, const float* A, const float* P, const doub
                        int64_t rows, int32_t r, const double* scale, float alpha, float* grad,
                        void* stream);
 
+/* One problem of a batch (see ntf_solve_batched). */
+typedef struct ntf_problem {
+  ntf_tensor T;                /* order 3, NTF_F32, each dim in [1, 256] */
+  int32_t r;                   /* rank, 1..32 */
+  int32_t reserved;            /* must be 0 */
+  float* A[3];                 /* device factors I_n x r, row-major: A_0 in, result out */
+  ntf_her_state* state;        /* device; output state, and input state when resuming;
+                                  may be NULL when not resuming */
+  double* trace_fhat;          /* device [iters]: F-hat_k, or NULL */
+  int32_t* trace_restart;      /* device [iters]: 1 if iteration k restarted, or NULL */
+  int32_t* trace_sweeps;       /* device [iters * 3]: A-HALS sweeps per block, or NULL */
+} ntf_problem;
+
+/* Algorithm 2 (HER with A-HALS blocks, Sec. 3.1) for `nprob` independent 3-way float32
+ * problems of any shapes and ranks, `iters` outer iterations each, in ONE persistent
+ * launch: a workgroup owns a problem for all iterations (problems larger in I_1 I_2 I_3 r
+ * start first). Per problem the results equal those of ntf_solve up to rounding order
+ * (same method, parameters and F-hat_0 = F(A_0)); restart decisions may differ where
+ * rounding decides them. probs: host array; all pointers inside are device pointers.
+ * resume != 0 continues from each problem's state and factors. The launch is captured
+ * into a HIP graph and replayed while the problem set and parameters are unchanged. The
+ * host descriptors are copied from pinned staging: the call waits until the previous
+ * call's copy has completed. */
+ntf_status ntf_solve_batched(ntf_handle* h, int32_t nprob, const ntf_problem* probs,
+                             const ntf_her_params* params, int32_t iters, int32_t resume,
+                             void* stream);
+
 /* || T - [[A_1..A_N]] ||_F^2 from the explicit residual, float64 accumulation (the data
  * fitting error of Sec. 4.1, eq. err_true_def, times 2). out: device double. */
 ntf_status ntf_residual_norm2(ntf_handle* h, const ntf_tensor* T, const float* const* A,

@@ -6,7 +6,8 @@ There is no CPU fallback: if libntf.so is missing the import of a call raises.
 
 Functions carry the C names: ntf_norm2, ntf_cast_bf16, ntf_mttkrp, ntf_gram,
 ntf_hals_update, ntf_her_step, ntf_error, ntf_solve, ntf_residual_norm2, ntf_cp_loss,
-ntf_cp_grad, plus the autograd loss `NTFLoss` / `ntf_loss` (module `autograd`).
+ntf_cp_grad, ntf_solve_batched, plus the autograd loss `NTFLoss` / `ntf_loss` (module
+`autograd`).
 """
 from __future__ import annotations
 
@@ -22,7 +23,7 @@ __all__ = [
     "Handle", "HerParams", "NtfError", "handle", "ntf_norm2", "ntf_cast_bf16", "ntf_mttkrp",
     "ntf_gram", "ntf_hals_update", "ntf_her_step", "ntf_error", "ntf_solve",
     "ntf_residual_norm2", "ntf_device_flags", "new_state", "state_dict", "ntf_cp_loss",
-    "ntf_cp_grad", "NTFLoss", "ntf_loss",
+    "ntf_cp_grad", "NTFLoss", "ntf_loss", "ntf_solve_batched",
 ]
 
 _DTYPES = {torch.float32: _abi.NTF_F32, torch.bfloat16: _abi.NTF_BF16}
@@ -262,6 +263,53 @@ def ntf_solve(T: torch.Tensor, factors, iters: int, params: HerParams | None = N
                           _dev(state, "state"), 1 if resume else 0,
                           C.byref(ctr) if ctr is not None else None, _stream(stream)))
     return state, tr
+
+
+def ntf_solve_batched(tensors, factors, iters: int, params: HerParams | None = None,
+                      states: torch.Tensor | None = None, resume: bool = False,
+                      trace: bool = True, h=None, stream=None):
+    """Algorithm 2 on many independent 3-way float32 problems in one persistent launch.
+
+    tensors: list of float32 device tensors (I1, I2, I3); factors: list of [A1, A2, A3]
+    (float32, I_n x r) updated in place. states: device uint8 tensor of
+    len(tensors) * sizeof(ntf_her_state) bytes (allocated when None). Returns
+    (states, trace) with trace = dict(fhat [B, iters], restart [B, iters],
+    sweeps [B, iters, 3]) of device tensors, or None.
+    """
+    p = (params or HerParams()).to_c()
+    B = len(tensors)
+    if len(factors) != B:
+        raise ValueError("one factor list per tensor")
+    dev = tensors[0].device
+    ss = C.sizeof(_abi.NtfHerState)
+    if states is None:
+        states = torch.zeros(B * ss, dtype=torch.uint8, device=dev)
+    tr = None
+    if trace and iters > 0:
+        tr = dict(fhat=torch.zeros((B, iters), dtype=torch.float64, device=dev),
+                  restart=torch.zeros((B, iters), dtype=torch.int32, device=dev),
+                  sweeps=torch.zeros((B, iters, 3), dtype=torch.int32, device=dev))
+    arr = (_abi.NtfProblem * B)()
+    for b, (T, A) in enumerate(zip(tensors, factors)):
+        q = arr[b]
+        q.T = _tensor_desc(T)
+        q.r = int(A[0].shape[1])
+        q.reserved = 0
+        for n in range(3):
+            q.A[n] = _dev(A[n], f"A[{b}][{n}]", torch.float32)
+        q.state = states.data_ptr() + b * ss
+        if tr is not None:
+            q.trace_fhat = tr["fhat"][b].data_ptr()
+            q.trace_restart = tr["restart"][b].data_ptr()
+            q.trace_sweeps = tr["sweeps"][b].data_ptr()
+    check(lib().ntf_solve_batched(_h(h), B, arr, C.byref(p), int(iters), 1 if resume else 0,
+                                  _stream(stream)))
+    return states, tr
+
+
+def batched_state_dict(states: torch.Tensor, b: int) -> dict:
+    ss = C.sizeof(_abi.NtfHerState)
+    return state_dict(states[b * ss:(b + 1) * ss])
 
 
 def ntf_device_flags(h=None, stream=None) -> int:

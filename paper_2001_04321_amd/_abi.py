@@ -39,6 +39,12 @@ class NtfTrace(C.Structure):
                 ("restart", C.c_void_p), ("sweeps", C.c_void_p)]
 
 
+class NtfProblem(C.Structure):
+    _fields_ = [("T", NtfTensor), ("r", C.c_int32), ("reserved", C.c_int32),
+                ("A", C.c_void_p * 3), ("state", C.c_void_p), ("trace_fhat", C.c_void_p),
+                ("trace_restart", C.c_void_p), ("trace_sweeps", C.c_void_p)]
+
+
 PTR = C.c_void_p
 PTRS = C.POINTER(C.c_void_p)
 I64S = C.POINTER(C.c_int64)
@@ -66,6 +72,8 @@ SIGNATURES = {
     "ntf_cp_loss": (C.c_int, [PTR, PTR, PTR, PTR, PTR, C.c_int64, C.c_int32, PTR, PTR]),
     "ntf_cp_grad": (C.c_int, [PTR, PTR, PTR, PTR, C.c_int64, C.c_int32, PTR, C.c_float, PTR,
                               PTR]),
+    "ntf_solve_batched": (C.c_int, [PTR, C.c_int32, C.POINTER(NtfProblem),
+                                    C.POINTER(NtfHerParams), C.c_int32, C.c_int32, PTR]),
     "ntf_residual_norm2": (C.c_int, [PTR, C.POINTER(NtfTensor), PTRS, C.c_int32, PTR, PTR]),
 }
 

@@ -6,6 +6,9 @@
 #include <cstring>
 
 #include <cmath>
+#include <algorithm>
+#include <new>
+#include <vector>
 
 #include "ntf_internal.h"
 
@@ -174,6 +177,10 @@ void ntf_handle_destroy(ntf_handle* h) {
   DeviceGuard guard(h->device);
   (void)hipDeviceSynchronize();
   release_solve_graph(h);
+  if (h->bgraph) (void)hipGraphExecDestroy(h->bgraph);
+  if (h->bstage_done) (void)hipEventDestroy(h->bstage_done);
+  if (h->bstage) (void)hipHostFree(h->bstage);
+  if (h->bws) (void)hipFree(h->bws);
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   if (h->ws) (void)hipFree(h->ws);
   if (h->dev_flags) (void)hipFree(h->dev_flags);
@@ -425,6 +432,164 @@ ntf_status ntf_cp_grad(ntf_handle* h, const float* A, const float* P, const doub
   NTF_RETURN_IF(!std::isfinite(alpha), NTF_EINVAL, "alpha is not finite");
   NTF_HIP(launch_cp_grad(A, P, G, rows, r, scale, alpha, grad, as_stream(stream)));
   return NTF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+ntf_status solve_batched_impl(ntf_handle* h, int32_t nprob, const ntf_problem* probs,
+                              const ntf_her_params* params, int32_t iters, int32_t resume,
+                              void* stream) {
+  NTF_GUARD(h);
+  NTF_RETURN_IF(nprob < 1 || nprob > 65535, NTF_EINVAL, "nprob %d outside [1, 65535]", nprob);
+  NTF_RETURN_IF(!probs, NTF_EINVAL, "probs is NULL");
+  NTF_RETURN_IF(iters < 0, NTF_EINVAL, "iters < 0");
+  ntf_status st = check_params(params);
+  if (st) return st;
+  std::vector<BatchedProblem> bp(static_cast<size_t>(nprob));
+  std::vector<int64_t> cost(static_cast<size_t>(nprob));
+  size_t ws_bytes = 0;
+  for (int b = 0; b < nprob; ++b) {
+    const ntf_problem& q = probs[b];
+    NTF_RETURN_IF(q.T.order != 3, NTF_EUNSUPPORTED, "problem %d: order %d (batched: 3-way)", b,
+                  q.T.order);
+    NTF_RETURN_IF(q.T.dtype != NTF_F32, NTF_EUNSUPPORTED, "problem %d: tensor must be float32",
+                  b);
+    NTF_RETURN_IF(!q.T.data, NTF_EINVAL, "problem %d: tensor data is NULL", b);
+    NTF_RETURN_IF(q.r < 1 || q.r > kBatchedMaxRank, NTF_EUNSUPPORTED,
+                  "problem %d: rank %d outside [1, %d]", b, q.r, kBatchedMaxRank);
+    NTF_RETURN_IF(q.reserved != 0, NTF_EINVAL, "problem %d: reserved must be 0", b);
+    NTF_RETURN_IF(resume && !q.state, NTF_EINVAL, "problem %d: resume needs a state", b);
+    BatchedProblem& d = bp[size_t(b)];
+    d.T = static_cast<const float*>(q.T.data);
+    for (int n = 0; n < 3; ++n) {
+      NTF_RETURN_IF(q.T.dims[n] < 1 || q.T.dims[n] > kBatchedMaxDim, NTF_EUNSUPPORTED,
+                    "problem %d: dim %d = %lld outside [1, %d]", b, n,
+                    static_cast<long long>(q.T.dims[n]), kBatchedMaxDim);
+      NTF_RETURN_IF(!q.A[n], NTF_EINVAL, "problem %d: factor %d is NULL", b, n);
+      d.I[n] = int(q.T.dims[n]);
+      d.A[n] = q.A[n];
+    }
+    d.r = q.r;
+    d.rb = (q.r + 7) / 8 * 8;
+    d.state = q.state;
+    d.tr_fhat = q.trace_fhat;
+    d.tr_restart = q.trace_restart;
+    d.tr_sweeps = q.trace_sweeps;
+    ws_bytes = align_up(ws_bytes, 256) + batched_problem_bytes(d.I, d.rb);
+    cost[size_t(b)] = int64_t(d.I[0]) * d.I[1] * d.I[2] * d.rb;
+  }
+  const size_t desc_bytes = batched_desc_bytes(nprob);
+  const size_t need = align_up(desc_bytes, 256) + ws_bytes;
+  hipStream_t s = as_stream(stream);
+  if (need > h->bws_size) {
+    NTF_HIP(hipDeviceSynchronize());
+    if (h->bgraph) {
+      (void)hipGraphExecDestroy(h->bgraph);
+      h->bgraph = nullptr;
+    }
+    if (h->bws) (void)hipFree(h->bws);
+    h->bws = nullptr;
+    h->bws_size = 0;
+    const size_t want = align_up(need + need / 4, size_t(1) << 20);
+    if (hipMalloc(&h->bws, want) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("batched workspace allocation of %zu bytes failed", want);
+      return NTF_ENOMEM;
+    }
+    h->bws_size = want;
+  }
+  if (!h->bstage_done) NTF_HIP(hipEventCreateWithFlags(&h->bstage_done, hipEventDisableTiming));
+  // the staging area is rewritten only after its previous upload has completed
+  NTF_HIP(hipEventSynchronize(h->bstage_done));
+  if (desc_bytes > h->bstage_size) {
+    if (h->bstage) (void)hipHostFree(h->bstage);
+    h->bstage = nullptr;
+    h->bstage_size = 0;
+    NTF_HIP(hipHostMalloc(&h->bstage, desc_bytes, hipHostMallocDefault));
+    h->bstage_size = desc_bytes;
+  }
+  size_t off = align_up(desc_bytes, 256);
+  for (int b = 0; b < nprob; ++b) {
+    off = align_up(off, 256);
+    bp[size_t(b)].ws = h->bws + off;
+    off += batched_problem_bytes(bp[size_t(b)].I, bp[size_t(b)].rb);
+  }
+  // largest problems first, so a grid wider than the device starts the long ones early
+  std::vector<int32_t> order(static_cast<size_t>(nprob));
+  for (int b = 0; b < nprob; ++b) order[size_t(b)] = b;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return cost[size_t(x)] > cost[size_t(y)]; });
+  BatchedJob job{};
+  job.probs = bp.data();
+  job.order = order.data();
+  job.nprob = nprob;
+  job.iters = iters;
+  job.resume = resume ? 1 : 0;
+  job.params = *params;
+  job.host_desc = h->bstage;
+  job.dev_desc = h->bws;
+  job.flags = h->dev_flags;
+  size_t lds = 0;
+  NTF_HIP(batched_upload(job, &lds, s));
+  NTF_HIP(hipEventRecord(h->bstage_done, s));
+  NTF_RETURN_IF(lds > 150 * 1024, NTF_EUNSUPPORTED, "problem set needs %zu bytes of LDS", lds);
+  // the persistent launch is captured once into a graph and replayed while its
+  // arguments are unchanged
+  unsigned char key[sizeof(h->bgraph_key)] = {};
+  {
+    struct K {
+      void* ws;
+      int nprob, iters, resume, pad;
+      ntf_her_params p;
+      size_t lds;
+      uint32_t* flags;
+    } k{};
+    k.ws = h->bws;
+    k.nprob = nprob;
+    k.iters = iters;
+    k.resume = job.resume;
+    k.p = *params;
+    k.lds = lds;
+    k.flags = h->dev_flags;
+    static_assert(sizeof(K) <= sizeof(key), "graph key too small");
+    std::memcpy(key, &k, sizeof(K));
+  }
+  if (!h->bgraph || std::memcmp(key, h->bgraph_key, sizeof(key)) != 0) {
+    if (h->bgraph) {
+      NTF_HIP(hipStreamSynchronize(s));
+      (void)hipGraphExecDestroy(h->bgraph);
+      h->bgraph = nullptr;
+    }
+    if (!h->capture_stream) NTF_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    NTF_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed));
+    const hipError_t le = batched_launch(job, lds, h->capture_stream);
+    const hipError_t ce = hipStreamEndCapture(h->capture_stream, &g);
+    NTF_HIP(le);
+    NTF_HIP(ce);
+    const hipError_t ie = hipGraphInstantiate(&h->bgraph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    NTF_HIP(ie);
+    std::memcpy(h->bgraph_key, key, sizeof(key));
+  }
+  NTF_HIP(hipGraphLaunch(h->bgraph, s));
+  return NTF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ntf_status ntf_solve_batched(ntf_handle* h, int32_t nprob, const ntf_problem* probs,
+                             const ntf_her_params* params, int32_t iters, int32_t resume,
+                             void* stream) {
+  clear_error();
+  try {
+    return solve_batched_impl(h, nprob, probs, params, iters, resume, stream);
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return NTF_ENOMEM;
+  }
 }
 
 ntf_status ntf_residual_norm2(ntf_handle* h, const ntf_tensor* T, const float* const* A,

@@ -91,6 +91,14 @@ struct ntf_handle {
   uint32_t* dev_flags = nullptr;
   hipStream_t capture_stream = nullptr;
   ntf::SolveGraph* graph = nullptr;
+  // batched solver: its own workspace, pinned descriptor staging, cached graph
+  char* bws = nullptr;
+  size_t bws_size = 0;
+  void* bstage = nullptr;      // pinned host
+  size_t bstage_size = 0;
+  hipEvent_t bstage_done = nullptr;
+  hipGraphExec_t bgraph = nullptr;
+  unsigned char bgraph_key[160] = {};
 };
 
 namespace ntf {
@@ -245,6 +253,38 @@ struct SelectJob {
 hipError_t launch_select(const SelectJob& j, const ntf_her_state* st, hipStream_t s);
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s);
 hipError_t launch_reset_call(ntf_her_state* st, hipStream_t s);
+
+// Batched solver (one workgroup per 3-way float32 problem, all iterations in one launch).
+constexpr int kBatchedMaxDim = 256;
+constexpr int kBatchedMaxRank = 32;
+constexpr size_t kBatchedDescBytes = 512;
+struct BatchedProblem {
+  const float* T;
+  int I[3];
+  int r, rb;            // rank and its padding to a multiple of 8
+  float* A[3];
+  char* ws;             // batched_problem_bytes(I, rb) bytes of device workspace
+  ntf_her_state* state; // may be null
+  double* tr_fhat;
+  int32_t* tr_restart;
+  int32_t* tr_sweeps;
+};
+struct BatchedJob {
+  const BatchedProblem* probs;
+  const int32_t* order;  // host: processing order (largest first)
+  int nprob;
+  int iters;
+  int resume;
+  ntf_her_params params;
+  void* host_desc;       // pinned, batched_desc_bytes(nprob)
+  void* dev_desc;        // device, batched_desc_bytes(nprob)
+  uint32_t* flags;
+};
+size_t batched_problem_bytes(const int I[3], int rb);
+size_t batched_lds_bytes(int I0, int I1, int I2, int rb);
+size_t batched_desc_bytes(int nprob);
+hipError_t batched_upload(const BatchedJob& job, size_t* lds_out, hipStream_t s);
+hipError_t batched_launch(const BatchedJob& job, size_t lds, hipStream_t s);
 
 // || T - [[A]] ||^2 (explicit residual, float64).
 int residual_partials();
