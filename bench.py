@@ -12,7 +12,11 @@ float32 accumulation); the float32 form on the float32 tensor (float32 matrix co
 MTTKRP throughput, final relative errors (explicit residual against the float32 tensor)
 and the FP64 oracle's rate on the host are reported beside it.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
+                    [--no-autograd] [--copy-probe]
+
+Also reported (not the headline value): the 256-problem batched workload solved in one
+persistent launch, and the 512^3 r=50 autograd loss with its backward.
 """
 from __future__ import annotations
 
@@ -26,7 +30,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3
 WORKLOAD = "cube400_r32_corr"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cube400_r32.json")
+
+
+def _source_digest(names) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_2001_04321_amd", "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {"mttkrp": ["k_mttkrp.hip"], "hals": ["k_hals.hip", "gram_chunk.h"]}
+
+
+def traffic_for(kind: str):
+    """HBM bytes per launch from the committed counter runs, or None when they are absent
+    or were taken on a different version of the kernel's source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)[kind]
+    except (OSError, KeyError, ValueError):
+        return None
+    if t.get("source_digest") != _source_digest(KERNEL_SOURCES[kind]):
+        return None
+    return t.get("bytes_per_launch")
 
 
 def log(msg: str) -> None:
@@ -74,6 +105,160 @@ def time_mttkrp(ntf, torch, Td, A_dev, reps):
     return out
 
 
+def time_hals(ntf, torch, Td, A_dev, reps):
+    """Average duration of one ntf_hals_update call per mode at the solver's settings
+    (50 sweeps at most, tol 1e-2), warm-started from the final factors, with the P and G
+    the solver would build for that mode; returns (ms per mode, sweeps per mode)."""
+    out, sweeps = [], []
+    for n in range(Td.dim()):
+        P = ntf.ntf_mttkrp(Td, A_dev, n)
+        G32, _ = ntf.ntf_gram(A_dev, exclude=n, want64=False)
+        W = A_dev[n].clone()
+        sw = ntf.ntf_hals_update(W.clone(), P, G32, 50, 1e-2)
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch)
+        e0.record()
+        for _ in range(reps):
+            W.copy_(A_dev[n])
+            ntf.ntf_hals_update(W, P, G32, 50, 1e-2, sweeps=sw)
+        e1.record()
+        torch.cuda.synchronize()
+        e2, e3 = _events(torch)
+        e2.record()
+        for _ in range(reps):
+            W.copy_(A_dev[n])
+        e3.record()
+        torch.cuda.synchronize()
+        out.append((e0.elapsed_time(e1) - e2.elapsed_time(e3)) / reps)
+        sweeps.append(int(sw.item()))
+    return out, sweeps
+
+
+def bench_batched(ntf, torch, iters: int):
+    """The 256-problem workload (I_n ~ U{32..160}, r ~ U{5..20}, 30 dB) solved for `iters`
+    outer iterations in one persistent launch (after one warm-up call that captures it)."""
+    import numpy as np
+
+    import synth
+    specs = synth.batch_specs(256)
+    Ts, A0 = [], []
+    for b, sp in enumerate(specs):
+        pr = synth.batch_problem(sp, b)
+        Ts.append(torch.from_numpy(pr.T.astype(np.float32)).cuda())
+        A0.append([torch.from_numpy(a.astype(np.float32)).cuda() for a in pr.A0])
+    As = [[a.clone() for a in A] for A in A0]
+    ntf.ntf_solve_batched(Ts, As, iters, trace=False)  # warm-up: capture + first run
+    for A, B in zip(As, A0):
+        for a, b in zip(A, B):
+            a.copy_(b)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    ntf.ntf_solve_batched(Ts, As, iters, trace=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    elems = sum(int(np.prod(sp[:3])) for sp in specs)
+    # two passes over every tensor per outer iteration (Y = T x_3 A_3, then the mode-3 pass)
+    gbs = 2 * elems * 4 * iters / (ms / 1e3) / 1e9
+    relerr = []
+    for b in (0, 1, 2):
+        res = float(ntf.ntf_residual_norm2(Ts[b], As[b]).item()) ** 0.5
+        relerr.append(res / float(Ts[b].norm().item()))
+    return dict(problems=len(specs), iters=iters, ms=round(ms, 3),
+                problem_iters_per_s=round(len(specs) * iters / (ms / 1e3), 1),
+                tensor_gb=round(elems * 4 / 1e9, 3), stream_gbs=round(gbs, 1),
+                relerr_first3=[round(x, 6) for x in relerr])
+
+
+def bench_autograd(ntf, torch, reps: int):
+    """Loss ||T - [[A,B,C]]||^2 and its hand-written backward on 512^3, r = 50 (float32)."""
+    import numpy as np
+
+    import synth
+    pr = synth.workload("cube512_r50")
+    Td = torch.from_numpy(pr.T.astype(np.float32)).cuda()
+    A0 = [torch.from_numpy(a.astype(np.float32)).cuda() for a in pr.A0]
+    del pr
+    normT2 = ntf.ntf_norm2(Td)
+
+    def step():
+        As = [a.detach().requires_grad_(True) for a in A0]
+        L = ntf.ntf_loss(Td, As, normT2=normT2)
+        L.backward()
+        return L
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(reps):
+        L = step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n = int(Td.numel())
+    return dict(workload="cube512_r50", ms_forward_backward=round(ms, 3),
+                tensor_passes=4, pass_gbs=round(4 * n * 4 / (ms / 1e3) / 1e9, 1),
+                loss=float(L.item()))
+
+
+def copy_probe(torch, nbytes: int = 256 << 20):
+    """A plain device copy of known size (traffic counters are scaled by it)."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+
+
+def traffic_from_counters(fetch_csv: str, write_csv: str, out_path: str, command: str):
+    """Per-launch HBM traffic of the MTTKRP and A-HALS kernels from two rocprofv3 --pmc
+    runs of this script with --copy-probe (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch),
+    each scaled by what the counter reads for the 256 MB copy (bytes it must move / KiB
+    counted). Writes the JSON that `traffic_for` reads."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        vals = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+        return vals
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+
+    def pick(vals, key):
+        ks = [k for k in vals if key(k)]
+        return [v for k in ks for v in vals[k]]
+
+    nbytes = 256 << 20
+    is_copy = lambda k: "copy" in k.lower() and "ntf" not in k
+    # the probe is the copy dispatch that moves 256 MB (other copies are small staging)
+    f_copy = max(pick(fetch, is_copy))
+    w_copy = max(pick(write, is_copy))
+    f_scale, w_scale = nbytes / f_copy, nbytes / w_copy
+    out = {"copy_probe": {"bytes": nbytes, "fetch_kib": f_copy, "write_kib": w_copy,
+                          "fetch_scale": f_scale, "write_scale": w_scale},
+           "command": command}
+    for kind, key in (("mttkrp", lambda k: "mttkrp_kernel<true" in k),
+                      ("hals", lambda k: "hals_kernel" in k)):
+        fv, wv = pick(fetch, key), pick(write, key)
+        if not fv or not wv:
+            continue
+        fb, wb = statistics.mean(fv) * f_scale, statistics.mean(wv) * w_scale
+        out[kind] = {"fetch_bytes": round(fb), "write_bytes": round(wb),
+                     "bytes_per_launch": round(fb + wb), "dispatches": len(fv),
+                     "source_digest": _source_digest(KERNEL_SOURCES[kind])}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 def cpu_baseline(pr_T32, A0, budget_s: float):
     """The FP64 oracle as it stands, on a bounded number of outer iterations."""
     import numpy as np
@@ -109,7 +294,21 @@ def main(argv=None):
     ap.add_argument("--mttkrp-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--hals-reps", type=int, default=10)
+    ap.add_argument("--batched-iters", type=int, default=200)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--autograd-reps", type=int, default=5)
+    ap.add_argument("--no-autograd", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 256 MB device copy (reference for traffic counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic summary from two counter runs and exit")
+    ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
     a = ap.parse_args(argv)
+    if a.traffic_from:
+        print(json.dumps(traffic_from_counters(a.traffic_from[0], a.traffic_from[1],
+                                               TRAFFIC_FILE, a.traffic_command), indent=1))
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the batched and "
               f"single-problem paths are single-device in this build", file=sys.stderr)
@@ -157,11 +356,12 @@ def main(argv=None):
         sweeps = trace["sweeps"].float().mean().item()
         restarts = int(trace["restart"].sum().item())
         mt_ms = time_mttkrp(ntf, torch, Td, A_dev, a.mttkrp_reps)
+        hals_ms, hals_sweeps = time_hals(ntf, torch, Td, A_dev, a.hals_reps)
         flops = 2.0 * r * n_elem
         forms[form] = dict(
             iters_per_s=a.steps / (ms / 1e3), ms_per_step=ms / a.steps, wall_s=wall,
             final_relerr=relerr, restarts=restarts, mean_inner_sweeps=sweeps,
-            mttkrp_ms=mt_ms,
+            mttkrp_ms=mt_ms, hals_ms=hals_ms, hals_sweeps=hals_sweeps,
             mttkrp_tflops=[flops / (t / 1e3) / 1e12 for t in mt_ms],
             mttkrp_gbs=[n_elem * s / (t / 1e3) / 1e9 for t in mt_ms])
         log(f"[bench] {form}: {forms[form]['iters_per_s']:.1f} it/s, relerr {relerr:.6e}, "
@@ -177,9 +377,30 @@ def main(argv=None):
             golden = g["relerr"]
 
     bf = forms["bf16"]
-    # dominant kernel: the bf16 MTTKRP; algorithmic bytes = one read of the bf16 tensor
+    # MTTKRP: algorithmic bytes = one read of the bf16 tensor per launch (factors and the
+    # output are < 0.1 %); HBM roof.
     t_mt = sum(bf["mttkrp_ms"]) / len(bf["mttkrp_ms"])
     achieved = n_elem * 2 / (t_mt / 1e3) / 1e9
+    mt_roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+               "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+               "traffic": traffic_for("mttkrp"),
+               "kernel": "mttkrp_kernel + mttkrp_reduce_kernel (one ntf_mttkrp call), bf16 "
+                         "tensor, mean over the 3 modes",
+               "step_share": round(sum(bf["mttkrp_ms"]) / bf["ms_per_step"], 3)}
+    # A-HALS: algorithmic flops = 2 r^2 per row per sweep (r multiply-adds per column);
+    # fp32 vector peak (the kernel is bound by its column-to-column dependency chain)
+    hals_dims = w["dims"]
+    hflops = [2.0 * r * r * I * sw for I, sw in zip(hals_dims, bf["hals_sweeps"])]
+    t_h = sum(bf["hals_ms"]) / len(bf["hals_ms"])
+    h_ach = sum(hflops) / len(hflops) / (t_h / 1e3) / 1e12
+    hals_roof = {"bound": "alu", "achieved": round(h_ach, 4), "peak": FP32_VALU_PEAK_TFLOPS,
+                 "unit": "TFLOP/s", "frac": round(h_ach / FP32_VALU_PEAK_TFLOPS, 5),
+                 "traffic": traffic_for("hals"),
+                 "kernel": "hals_kernel (one ntf_hals_update call at 50 sweeps at most, "
+                           "tol 1e-2), mean over the 3 modes",
+                 "sweeps": bf["hals_sweeps"],
+                 "step_share": round(sum(bf["hals_ms"]) / bf["ms_per_step"], 3)}
+    roofs = sorted([mt_roof, hals_roof], key=lambda x: -x["step_share"])
     line = {
         "metric": "BCD-HER iters/s + MTTKRP TFLOP/s, BF16-MFMA vs FP32, at final rel.err <=1e-3",
         "value": round(bf["iters_per_s"], 3),
@@ -196,11 +417,8 @@ def main(argv=None):
         "config": {"workload": WORKLOAD, "dims": list(w["dims"]), "rank": r,
                    "snr_db": w["snr_db"], "factors": "pairwise column correlation 0.9",
                    "params": "beta0=0.5 gamma=1.05 gamma_bar=1.01 eta=1.5 inner<=50 tol=1e-2"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
-                     "kernel": "ntf_mttkrp, bf16 tensor, mean over the 3 modes "
-                               "(main MFMA kernel + split reduction)"},
+        "roofline": roofs[0],
+        "roofline_next": roofs[1],
         "fp32_iters_per_s": round(forms["fp32"]["iters_per_s"], 3),
         "bf16_vs_fp32": round(bf["iters_per_s"] / forms["fp32"]["iters_per_s"], 4),
         "mttkrp_tflops": {k: [round(x, 2) for x in v["mttkrp_tflops"]] for k, v in forms.items()},
@@ -213,6 +431,15 @@ def main(argv=None):
         "device_flags": flags,
         "cpu_baseline": None,
     }
+    if not a.no_batched:
+        log(f"[bench] batched: 256 problems, {a.batched_iters} iterations, one launch")
+        line["batched"] = bench_batched(ntf, torch, a.batched_iters)
+    if not a.no_autograd:
+        log("[bench] autograd: 512^3 r=50 loss + backward")
+        line["autograd"] = bench_autograd(ntf, torch, a.autograd_reps)
+    if a.copy_probe:
+        copy_probe(torch)
+    line["device_flags"] = ntf.ntf_device_flags()
     if not a.no_cpu_baseline:
         log(f"[bench] cpu baseline (oracle, ~{a.cpu_budget:.0f}s)")
         line["cpu_baseline"] = cpu_baseline(T32, A0, a.cpu_budget)

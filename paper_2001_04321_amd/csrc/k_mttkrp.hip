@@ -83,6 +83,7 @@ struct KArgs {
   FastDiv fd_Rp;               // case A: u = a * Rp + b_hi, Rp = R / I_v
   int64_t Rp;
   int64_t per_split, extra;
+  int64_t mtiles;              // row tiles (the grid is mtiles x splits workgroups)
   int r;
   int vb;                      // v-block length (multiple of the chunk)
   int ub;                      // u values per X batch
@@ -138,10 +139,19 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
   const int wk = wave / WM;
   const int col = lane & 31;
   const int half = lane >> 5;
-  const int64_t i0 = int64_t(blockIdx.x) * MT;
+  // XCD-aware numbering: workgroups are dealt to the 8 XCDs round-robin by launch index;
+  // logical workgroups are renumbered so that consecutive row tiles of a split (which
+  // share cache lines at their edges) run on the same XCD and hit the same L2
+  uint32_t lw = blockIdx.x;
+  {
+    const uint32_t per = gridDim.x / 8;
+    if (lw < per * 8) lw = (lw % 8) * per + lw / 8;
+  }
+  const int64_t tile = lw % uint32_t(k.mtiles);
+  const int64_t i0 = tile * MT;
   const int64_t row = i0 + wm * 32 + col;  // case A / f32 case B: the lane's output row
   const bool row_ok = row < k.I;
-  const int64_t split = blockIdx.y;
+  const int64_t split = lw / uint32_t(k.mtiles);
   const int64_t w_beg = split * k.per_split + (split < k.extra ? split : k.extra);
   const int64_t w_end = w_beg + k.per_split + (split < k.extra ? 1 : 0);
   const TE* __restrict__ T = static_cast<const TE*>(k.T);
@@ -490,7 +500,9 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus) {
     if (l != mode && l != pl.vmode) pl.U *= T.dims[l];
   // row tile: least padding among the instantiated shapes (ties: the taller tile)
   const int64_t I = pl.v.I;
-  const int wm_min = nt >= 4 ? 2 : 1;
+  // bf16 last mode: a wave's tile spans 32 contiguous elements (64 B); two waves side by
+  // side make whole 128-byte lines per workgroup
+  const int wm_min = (nt >= 4 || (bf16 && last)) ? 2 : 1;
   int64_t best = -1;
   pl.wm = 4;
   for (int wm : {4, 2, 1}) {
@@ -562,6 +574,7 @@ hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& 
   k.Rp = last ? 1 : pl.v.R / pl.Iv;
   k.fd_Rp = make_fastdiv(uint32_t(k.Rp));
   k.per_split = pl.chunks / pl.splits;
+  k.mtiles = pl.mtiles;
   k.extra = pl.chunks % pl.splits;
   k.r = pl.r;
   k.vb = pl.vb;
@@ -580,7 +593,7 @@ hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& 
     if (e != hipSuccess) return e;
     done = true;
   }
-  dim3 grid(unsigned(pl.mtiles), unsigned(pl.splits));
+  dim3 grid(unsigned(pl.mtiles * pl.splits));
   hipLaunchKernelGGL(fn, grid, dim3(kThreads), pl.lds, s, k);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
