@@ -84,6 +84,9 @@ struct KArgs {
   int64_t Rp;
   int64_t per_split, extra;
   int64_t mtiles;              // row tiles (the grid is mtiles x splits workgroups)
+  int av_vec;                  // A_v rows are RP floats (r == RP) and 16-byte aligned
+  float* ystore;               // case A, one wave per row tile: store Y[i][u][:] = T_u A_v
+                               // rows instead of folding them (null: fold into P)
   int r;
   int vb;                      // v-block length (multiple of the chunk)
   int ub;                      // u values per X batch
@@ -187,6 +190,12 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
         const uint4* p = reinterpret_cast<const uint4*>(T + off);
 #pragma unroll
         for (int q = 0; q < 4; ++q) reg[q] = p[q];
+      } else if (row_ok && k.vec_ok && k.Iv % (EPL / 4) == 0) {
+        // tail chunk with I_v a multiple of the 16-byte slot: whole slots or none
+        const uint4* p = reinterpret_cast<const uint4*>(T + off);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          reg[q] = v + (q + 1) * (EPL / 4) <= k.Iv ? p[q] : make_uint4(0, 0, 0, 0);
       } else {
         TE tmp[EPL];
 #pragma unroll
@@ -297,15 +306,47 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
     // ---- A_v block into LDS (zero beyond I_v and r) ----
     if (vbi != cur_vb) {
       __syncthreads();
-      for (int e = tid; e < vb * RP; e += kThreads) {
-        const int kk = e / RP;
-        const int p = e - kk * RP;
-        const int64_t v = v0 + kk;
-        const float val = (p < k.r && v < k.Iv) ? k.Av[v * k.r + p] : 0.f;
-        if (BF16)
-          reinterpret_cast<uint16_t*>(s_av)[p * ldb + kk] = f2bf(val);
-        else
-          reinterpret_cast<float*>(s_av)[kk * RP + p] = val;
+      if (k.av_vec) {
+        // r == RP and A_v 16-byte aligned: the block is contiguous; 16-byte loads, eight
+        // in flight per thread
+        const int nv = int(std::min<int64_t>(vb, k.Iv - v0));
+        const int n4 = vb * RP / 4;
+        const float4* src = reinterpret_cast<const float4*>(k.Av + v0 * RP);
+        for (int b0 = tid; b0 < n4; b0 += kThreads * 8) {
+          float4 t[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int e4 = b0 + j * kThreads;
+            t[j] = (e4 < n4 && (e4 * 4) / RP < nv) ? src[e4] : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int e4 = b0 + j * kThreads;
+            if (e4 >= n4) continue;
+            const int kk = (e4 * 4) / RP;
+            const int p = e4 * 4 - kk * RP;
+            if (BF16) {
+              uint16_t* d = reinterpret_cast<uint16_t*>(s_av);
+              d[(p + 0) * ldb + kk] = f2bf(t[j].x);
+              d[(p + 1) * ldb + kk] = f2bf(t[j].y);
+              d[(p + 2) * ldb + kk] = f2bf(t[j].z);
+              d[(p + 3) * ldb + kk] = f2bf(t[j].w);
+            } else {
+              *reinterpret_cast<float4*>(&reinterpret_cast<float*>(s_av)[kk * RP + p]) = t[j];
+            }
+          }
+        }
+      } else {
+        for (int e = tid; e < vb * RP; e += kThreads) {
+          const int kk = e / RP;
+          const int p = e - kk * RP;
+          const int64_t v = v0 + kk;
+          const float val = (p < k.r && v < k.Iv) ? k.Av[v * k.r + p] : 0.f;
+          if (BF16)
+            reinterpret_cast<uint16_t*>(s_av)[p * ldb + kk] = f2bf(val);
+          else
+            reinterpret_cast<float*>(s_av)[kk * RP + p] = val;
+        }
       }
       cur_vb = vbi;
     }
@@ -350,12 +391,26 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
           const int kc = wk + cj * WK;
           if (kc < nkc) compute_item(buf[d], kc);
           if (cj == ipu - 1) {
-            const float* xs = s_x + cu * RP;
+            if (k.ystore) {
+              // Y[i][u][p] (the wave covers every v chunk of u: WK == 1)
+              const int64_t uu = u0 + cu;
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-              const float x = xs[nt * 32 + col];
+              for (int nt = 0; nt < NT; ++nt) {
+                const int p = nt * 32 + col;
 #pragma unroll
-              for (int e = 0; e < 16; ++e) acc[nt][e] = fmaf(x, y[nt][e], acc[nt][e]);
+                for (int e = 0; e < 16; ++e) {
+                  const int64_t i = i0 + wm * 32 + 8 * (e >> 2) + half * 4 + (e & 3);
+                  if (p < k.r && i < k.I) k.ystore[(i * k.U + uu) * k.r + p] = y[nt][e];
+                }
+              }
+            } else {
+              const float* xs = s_x + cu * RP;
+#pragma unroll
+              for (int nt = 0; nt < NT; ++nt) {
+                const float x = xs[nt * 32 + col];
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[nt][e] = fmaf(x, y[nt][e], acc[nt][e]);
+              }
             }
           }
           if (++cj == ipu) {
@@ -379,7 +434,7 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
       for (int e = 0; e < 16; ++e) dst[(nt * 16 + e) * 64 + lane] = acc[nt][e];
   }
   __syncthreads();
-  if (wk == 0) {
+  if (wk == 0 && !k.ystore) {
     for (int ww = 1; ww < WK; ++ww) {
       const float* src = red + ((ww - 1) * WM + wm) * (64 * 16 * NT);
 #pragma unroll
@@ -420,6 +475,67 @@ __global__ __launch_bounds__(256) void mttkrp_reduce_kernel(const float* __restr
     if (g == 0 && e < n) P[e] = float(((s[0][o] + s[1][o]) + s[2][o]) + s[3][o]);
     __syncthreads();
   }
+}
+
+// Folds of a stored Y[I][U][r] (3-way tensors: Y = T x_3 A_3, u = mode 2):
+//   fold_u: P[i, p] = sum_u X[u, p] Y[i, u, p]   (the mode-1 MTTKRP, X = A_2)
+//   fold_i: P[u, p] = sum_i X[i, p] Y[i, u, p]   (the mode-2 MTTKRP, X = A_1), as partial
+//           sums over i ranges that mttkrp_reduce_kernel adds in order.
+// fold_u: one workgroup per i; 8 groups of u summed in fixed order.
+__global__ __launch_bounds__(256) void fold_u_kernel(const float* __restrict__ Y,
+                                                     const float* __restrict__ X, int64_t U,
+                                                     int r, float* __restrict__ P) {
+  __shared__ float s[8][256];
+  const int64_t i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const float* yi = Y + i * U * r;
+  for (int p0 = 0; p0 < r; p0 += 32) {
+    const int p = p0 + (tid & 31);
+    const int g = tid >> 5;
+    // four independent partial sums (u = g + 8 (4 t + j)), combined in a fixed order, so
+    // that several loads are in flight per thread
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    if (p < r) {
+      int64_t u = g;
+      for (; u + 24 < U; u += 32) {
+        a0 = fmaf(X[u * r + p], yi[u * r + p], a0);
+        a1 = fmaf(X[(u + 8) * r + p], yi[(u + 8) * r + p], a1);
+        a2 = fmaf(X[(u + 16) * r + p], yi[(u + 16) * r + p], a2);
+        a3 = fmaf(X[(u + 24) * r + p], yi[(u + 24) * r + p], a3);
+      }
+      for (; u < U; u += 8) a0 = fmaf(X[u * r + p], yi[u * r + p], a0);
+    }
+    s[g][tid & 31] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (tid < 32 && p0 + tid < r) {
+      float t = 0.f;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t += s[q][tid];
+      P[i * r + p0 + tid] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// fold_i: workgroup (u tile of 256 / r' outputs, i range); partial[split][u][p].
+__global__ __launch_bounds__(256) void fold_i_kernel(const float* __restrict__ Y,
+                                                     const float* __restrict__ X, int64_t I,
+                                                     int64_t U, int r, int64_t per,
+                                                     float* __restrict__ part) {
+  const int64_t n = U * r;
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;  // (u, p) flattened
+  const int64_t split = blockIdx.y;
+  const int64_t i_lo = split * per, i_hi = std::min<int64_t>(I, i_lo + per);
+  if (e >= n) return;
+  const int p = int(e % r);
+  float a0 = 0.f, a1 = 0.f;
+  int64_t i = i_lo;
+  for (; i + 1 < i_hi; i += 2) {
+    a0 = fmaf(X[i * r + p], Y[i * n + e], a0);
+    a1 = fmaf(X[(i + 1) * r + p], Y[(i + 1) * n + e], a1);
+  }
+  if (i < i_hi) a0 = fmaf(X[i * r + p], Y[i * n + e], a0);
+  part[split * n + e] = a0 + a1;
 }
 
 using KernelFn = void (*)(KArgs);
@@ -482,8 +598,9 @@ ModeView make_mode_view(const ntf_tensor& T, int mode) {
   return v;
 }
 
-MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus) {
+MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus, bool store_y) {
   MttkrpPlan pl;
+  pl.store_y = store_y;
   pl.v = make_mode_view(T, mode);
   pl.dtype = T.dtype;
   pl.r = r;
@@ -513,6 +630,7 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus) {
       pl.wm = wm;
     }
   }
+  if (store_y) pl.wm = 4;  // one wave covers all v chunks of a row tile: Y rows are whole
   pl.wk = 4 / pl.wm;
   // v-block: all of I_v when its A_v block fits 64 KB of LDS
   const int kch = bf16 ? 64 : 32;
@@ -552,13 +670,15 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus) {
 }
 
 hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& A, float* P,
-                         float* partials, bool reduce, hipStream_t s) {
+                         float* partials, bool reduce, hipStream_t s, float* ystore) {
   KArgs k{};
+  k.ystore = pl.store_y ? ystore : nullptr;
   k.T = T;
   const int N = pl.v.order;
   const int n = pl.v.mode;
   const bool last = pl.layout == 1;
   k.Av = A.p[pl.vmode];
+  k.av_vec = (pl.r == pl.rpad && (reinterpret_cast<uintptr_t>(k.Av) & 15) == 0) ? 1 : 0;
   k.n_o = 0;
   for (int l = 0; l < N; ++l) {
     if (l == n || l == pl.vmode) continue;
@@ -597,6 +717,7 @@ hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& 
   hipLaunchKernelGGL(fn, grid, dim3(kThreads), pl.lds, s, k);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (k.ystore) return e;
   if (split && reduce) {
     const int64_t nout = pl.v.I * pl.r;
     const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(ceil_div(nout, 64), 4096)));
@@ -605,6 +726,33 @@ hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& 
     e = hipGetLastError();
   }
   return e;
+}
+
+hipError_t launch_fold_u(const float* Y, const float* X, int64_t I, int64_t U, int r, float* P,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(fold_u_kernel, dim3(unsigned(I)), dim3(256), 0, s, Y, X, U, r, P);
+  return hipGetLastError();
+}
+
+int64_t fold_i_splits(int64_t I, int64_t U, int r) {
+  // enough workgroups to stream Y: about 1024 in total, at least 4 rows of i each
+  const int64_t tiles = ceil_div(U * r, 256);
+  return std::max<int64_t>(1, std::min<int64_t>(ceil_div(1024, tiles), ceil_div(I, 4)));
+}
+
+hipError_t launch_fold_i(const float* Y, const float* X, int64_t I, int64_t U, int r,
+                         float* partials, float* P, hipStream_t s) {
+  const int64_t splits = fold_i_splits(I, U, r);
+  const int64_t per = ceil_div(I, splits);
+  const int64_t n = U * r;
+  hipLaunchKernelGGL(fold_i_kernel, dim3(unsigned(ceil_div(n, 256)), unsigned(splits)),
+                     dim3(256), 0, s, Y, X, I, U, r, per, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 64), 4096)));
+  hipLaunchKernelGGL(mttkrp_reduce_kernel, dim3(blocks), dim3(256), 0, s, partials, splits, n,
+                     P);
+  return hipGetLastError();
 }
 
 }  // namespace ntf

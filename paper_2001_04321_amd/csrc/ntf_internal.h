@@ -141,15 +141,28 @@ struct MttkrpPlan {
   size_t lds;      // dynamic LDS bytes
   int64_t mtiles;  // row tiles
   int64_t chunks;  // work items (v-block, u)
+  bool store_y = false;  // store Y = T_u A_v rows instead of folding (case A, 3-way solver)
   int64_t splits;  // splits of the work items (grid.y)
   size_t partial_floats() const { return splits > 1 ? size_t(splits) * v.I * r : 0; }
 };
-MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus);
+MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus,
+                       bool store_y = false);
 // MTTKRP. With one split the kernel writes P (I x r) directly. With several it writes
 // plan.partial_floats() floats of split partials; if `reduce` is set a second kernel sums
 // them into P in a fixed order, otherwise the caller (A-HALS) consumes the partials.
+// A plan made with store_y (case A only) writes Y[i][u][:] = T_u A_v (I x U x r floats)
+// to `ystore` instead, and nothing to P.
 hipError_t launch_mttkrp(const MttkrpPlan& plan, const void* T, const FactorPtrs& A, float* P,
-                         float* partials, bool reduce, hipStream_t s);
+                         float* partials, bool reduce, hipStream_t s, float* ystore = nullptr);
+// 3-way tensors, from a stored Y (mode 0 plan with store_y, u = mode 1):
+//   P[i, p] = sum_u X[u, p] Y[i, u, p]            (mode-0 MTTKRP, X = A_1)
+//   P[u, p] = sum_i X[i, p] Y[i, u, p]            (mode-1 MTTKRP, X = A_0; `partials`
+//                                                  holds fold_i_splits(I, U, r) U r floats)
+hipError_t launch_fold_u(const float* Y, const float* X, int64_t I, int64_t U, int r, float* P,
+                         hipStream_t s);
+int64_t fold_i_splits(int64_t I, int64_t U, int r);
+hipError_t launch_fold_i(const float* Y, const float* X, int64_t I, int64_t U, int r,
+                         float* partials, float* P, hipStream_t s);
 
 // Gram partials: for factor f (rows[f] x r), out[f] gets gram_chunks(rows, r) partial
 // r x r float64 Grams (row chunks of the A-HALS workgroup size, so the A-HALS epilogue

@@ -5,7 +5,8 @@
 // HER_eq:beta_bar_update) is captured once into a HIP graph and replayed `iters` times:
 //
 //   for block n:  G^(n)   = Hadamard of cached Grams (A-hat_k for l < n, A_{k-1} for l > n)
-//                 P       = MTTKRP_n(T; A-hat_k^(l<n), A_{k-1}^(l>n))      (the hot kernel)
+//                 P       = MTTKRP_n(T; A-hat_k^(l<n), A_{k-1}^(l>n))      (the hot kernel;
+//                           3-way: modes 1 and 2 fold one shared Y = T x_3 A-hat_{k-1}^(3))
 //                 A_new   = A-HALS(warm start A_{k-1}^(n); P, G^(n)), fused with
 //                 A_hat   = max(0, A_new + beta (A_new - A_{k-1}^(n)))
 //                 Grams of A_new and A_hat (float64 partials, cached)
@@ -56,6 +57,7 @@ struct SolveBufs {
   double* G64;
   float* P;
   float* mt_part;
+  float* Y;  // 3-way: Y = T x_3 A_3 (I_1 x I_2 x r), shared by the mode-1 and mode-2 MTTKRPs
   double* slots;
   int64_t nslots;
   int32_t* sweeps;
@@ -63,8 +65,18 @@ struct SolveBufs {
   int64_t nerr;
 };
 
+// 3-way tensors: the mode-1 and mode-2 MTTKRPs share Y = T x_3 A-hat^(3) (A-hat^(3) does not
+// change before the mode-3 update), so the tensor is streamed twice per iteration instead of
+// three times. Used when Y is smaller than the tensor and A_3 fits one LDS block.
+bool use_shared_y(const ntf_tensor& T, int r, const MttkrpPlan& plan_y) {
+  if (T.order != 3 || plan_y.nvb != 1) return false;
+  const int64_t s = T.dtype == NTF_BF16 ? 2 : 4;
+  const int64_t ybytes = T.dims[0] * T.dims[1] * int64_t(r) * 4;
+  return ybytes < T.dims[0] * T.dims[1] * T.dims[2] * s;
+}
+
 void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
-           const MttkrpPlan* plans, bool own_state) {
+           const MttkrpPlan* plans, bool own_state, bool shared_y) {
   const int N = T.order;
   const size_t rr = size_t(r) * r;
   b.norm_part = ar.take<double>(norm2_partials());
@@ -89,7 +101,11 @@ void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
   b.G32 = ar.take<float>(rr);
   b.G64 = ar.take<double>(rr);
   b.P = ar.take<float>(size_t(maxI) * r);
+  if (shared_y)
+    maxpart = std::max<size_t>(
+        maxpart, size_t(fold_i_splits(T.dims[0], T.dims[1], r)) * T.dims[1] * r);
   b.mt_part = ar.take<float>(std::max<size_t>(maxpart, 1));
+  b.Y = shared_y ? ar.take<float>(size_t(T.dims[0]) * T.dims[1] * r) : nullptr;
   b.nslots = maxslots;
   b.slots = ar.take<double>(size_t(maxslots));
   b.sweeps = ar.take<int32_t>(kMaxOrder);
@@ -110,7 +126,8 @@ FactorPtrs factors_for(int n, int N, float* const* A, const SolveBufs& b) {
 // and select.
 hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* const* A,
                              const ntf_her_params& p, const SolveBufs& b,
-                             const MttkrpPlan* plans, const ntf_trace& trace, hipStream_t s) {
+                             const MttkrpPlan* plans, const MttkrpPlan* plan_y,
+                             const ntf_trace& trace, hipStream_t s) {
   const int N = T.order;
   hipError_t e;
   for (int n = 0; n < N; ++n) {
@@ -126,9 +143,20 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
     if ((e = launch_hadamard(hj, r, b.G32, b.G64, b.slots, nslots, s)) != hipSuccess) return e;
     // split partials are summed by the wide reduction kernel: the A-HALS grid is too
     // narrow (one workgroup per row chunk) to stream them quickly
-    if ((e = launch_mttkrp(plans[n], T.data, factors_for(n, N, A, b), b.P, b.mt_part, true,
-                           s)) != hipSuccess)
+    if (b.Y && n == 0) {
+      if ((e = launch_mttkrp(*plan_y, T.data, factors_for(0, N, A, b), b.P, b.mt_part, true, s,
+                             b.Y)) != hipSuccess)
+        return e;
+      if ((e = launch_fold_u(b.Y, A[1], T.dims[0], T.dims[1], r, b.P, s)) != hipSuccess)
+        return e;
+    } else if (b.Y && n == 1) {
+      if ((e = launch_fold_i(b.Y, b.A_hat[0], T.dims[0], T.dims[1], r, b.mt_part, b.P, s)) !=
+          hipSuccess)
+        return e;
+    } else if ((e = launch_mttkrp(plans[n], T.data, factors_for(n, N, A, b), b.P, b.mt_part,
+                                  true, s)) != hipSuccess) {
       return e;
+    }
     HalsArgs ha{};
     ha.W0 = A[n];
     ha.W = b.A_new[n];
@@ -224,15 +252,21 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
     plans[n] = plan_mttkrp(*T, n, r, h->num_cus);
     NTF_RETURN_IF(plans[n].chunks >= (int64_t(1) << 31), NTF_EUNSUPPORTED, "reduction too long");
   }
+  MttkrpPlan plan_y{};
+  bool shared_y = false;
+  if (N == 3) {
+    plan_y = plan_mttkrp(*T, 0, r, h->num_cus, true);
+    shared_y = use_shared_y(*T, r, plan_y);
+  }
   ntf_trace tr{};
   if (trace) tr = *trace;
 
   Arena dry;
   SolveBufs b{};
-  carve(dry, b, *T, r, params->max_inner, plans, state == nullptr);
+  carve(dry, b, *T, r, params->max_inner, plans, state == nullptr, shared_y);
   if ((st = ensure_workspace(h, dry.off + 256))) return st;
   Arena ar{h->ws, 0};
-  carve(ar, b, *T, r, params->max_inner, plans, state == nullptr);
+  carve(ar, b, *T, r, params->max_inner, plans, state == nullptr, shared_y);
   if (state) b.state = state;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -290,7 +324,8 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
     SolveGraph* g = new SolveGraph();
     g->key = key;
     NTF_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed));
-    hipError_t e = enqueue_iteration(h, *T, r, A, *params, b, plans, tr, h->capture_stream);
+    hipError_t e = enqueue_iteration(h, *T, r, A, *params, b, plans, &plan_y, tr,
+                                     h->capture_stream);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(h->capture_stream, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
