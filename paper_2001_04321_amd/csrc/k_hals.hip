@@ -10,13 +10,14 @@
 // (G_jj = 0) has q_j = 0, so it is 0 after its first update, as the method prescribes. The
 // rank is padded to a compile-time multiple of 8 with zero columns, whose updates are 0.
 //
-// Stopping rule: after sweep s every workgroup publishes its share of ||W_s - W_{s-1}||^2
-// (float64); one workgroup sums the shares in workgroup order and publishes the total, so
-// every workgroup sees the same value and takes the same decision. The rule for sweep
-// s - K + 1 is evaluated after sweep s, with the load of its total issued before the sweep;
-// a ring of the last K iterates (in LDS) restores the iterate the rule stops at. Waits are
-// bounded by a wall-clock deadline (timeout: NTF_FLAG_WAIT_TIMEOUT). The grid never
-// exceeds the CU count, so all workgroups are resident together.
+// Stopping rule: a fifth wave of each workgroup runs it while four waves sweep. It sums the
+// row waves' shares of ||W_s - W_{s-1}||^2 (float64, fixed order), publishes the
+// workgroup's share, sums every workgroup's shares in workgroup order (so every workgroup
+// takes the same decision) and posts the decisions in LDS. Row waves run up to `lag`
+// sweeps past the last decision, keeping those iterates in an LDS ring, and restore the
+// iterate of the sweep the rule stops at. Waits are bounded by a wall-clock deadline
+// (timeout: NTF_FLAG_WAIT_TIMEOUT). The grid never exceeds the CU count, so all
+// workgroups are resident together.
 //
 // Fused around the sweeps (each optional):
 //  - epilogue: extrapolation A_hat = max(0, W + beta (W - W_0)) (eq. extproj_her), the
@@ -28,9 +29,10 @@
 namespace ntf {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kBatch = 4;    // sweeps per stopping-rule exchange
-constexpr int kRing = 3 * kBatch;  // iterates kept: a decision lags at most 3 batches - 1
+constexpr int kWaves = 4;                  // waves that own rows
+constexpr int kCT = 64 * kWaves;           // their threads
+constexpr int kThreads = kCT + 64;         // plus one wave that runs the stopping rule
+constexpr int kMaxLag = 8;                 // sweeps the row waves may run ahead of a decision
 constexpr int kRefresh = 4;  // sweeps between exact recomputations of q
 constexpr uint64_t kSentinel = ~uint64_t(0);
 
@@ -53,6 +55,7 @@ struct HKArgs {
   double* gp_hat;
   double* err_part;
   int nwg;
+  int lag;                 // sweeps the row waves may run ahead of the last decision
   uint64_t timeout_ticks;
 };
 
@@ -119,7 +122,7 @@ template <int RPAD, int C, int NR, int NB>
 __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   constexpr int GPW = 64 / RPAD;        // row groups per wave
   constexpr int RPWV = GPW * NR;        // rows per wave
-  constexpr int WPG = kThreads / 64;    // waves per workgroup
+  constexpr int WPG = kWaves;           // waves that own rows
   constexpr int RPW = WPG * RPWV;       // rows per workgroup
   constexpr int RMAX = RPAD * C;        // columns held per row group
   constexpr int RB = NB * 8;            // columns swept
@@ -127,10 +130,13 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   // scaled G in registers when it fits, else read from LDS in blocks of 8 columns
   constexpr bool GREG = RB * C <= 64;
   extern __shared__ __attribute__((aligned(16))) float smem[];
-  // per-sweep LDS words alternate between two copies by sweep parity: a wave can reach the
-  // next sweep's write only after a barrier that every reader of the current copy has passed
-  __shared__ double s_part[2][WPG][kBatch];
-  __shared__ int s_dec[3];  // [b & 1]: decision at exchange b; [2]: after the last sweep
+  __shared__ double s_part[WPG + 1];  // epilogue: per-wave F-hat shares
+  // row waves -> rule wave: last sweep whose shares each row wave has posted;
+  // rule wave -> row waves: last sweep decided, and the sweep the rule stops at (0: none,
+  // -1: a wait timed out)
+  __shared__ int s_posted[WPG];
+  __shared__ int s_decided;
+  __shared__ int s_stop;
 
   const int r = a.r;
   float* s_g = smem;               // scaled G, RB x RMAX: s_g[j][k] = G_jk / G_kk, 0 if j == k
@@ -145,6 +151,11 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   const int64_t row0 = int64_t(blockIdx.x) * RPW;
   const int nrows = int(std::min<int64_t>(RPW, a.rows - row0));
 
+  if (tid < WPG) s_posted[tid] = 0;
+  if (tid == 0) {
+    s_decided = 0;
+    s_stop = 0;
+  }
   for (int e = tid; e < RB * RMAX; e += kThreads) {
     const int j = e / RMAX;
     const int k = e - j * RMAX;
@@ -169,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     lrow[q] = wave * RPWV + q * GPW + gi;
-    rok[q] = lrow[q] < nrows;
+    rok[q] = wave < WPG && lrow[q] < nrows;  // the rule wave owns no rows
   }
   float w[NR][C], pinv[NR][C], w0[NR][C], qv[NR][C];
 #pragma unroll
@@ -271,107 +282,138 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
     }
   };
 
-  // Stopping-rule exchange, every kBatch sweeps (batch b = sweeps (b-1)M+1 .. bM, M =
-  // kBatch). At exchange b every workgroup stores its shares of ||W_t - W_{t-1}||^2 for the
-  // sweeps of batch b in slot (b, wg) and issues the loads of all slots of batch b - 1; the
-  // values arrive while the next batch is computed and are summed, in workgroup order, at
-  // exchange b + 1, which decides the sweeps of batch b - 1. Every workgroup sums the same
-  // values in the same order, so all take the same decision. A slot still at the sentinel
-  // (its owner is behind) is re-read until it lands. Iterates are kept in an LDS ring long
-  // enough to restore the sweep the rule stops at.
-  uint64_t* const slots = a.slots;  // [batch][wg][kBatch]
-  auto spin_load = [&](const uint64_t* addr, bool& timeout) -> uint64_t {
-    uint64_t v = __hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (v == kSentinel) {
-      if (wall_clock64() - t_start > a.timeout_ticks) {
-        timeout = true;
-        return 0;
-      }
-      __builtin_amdgcn_s_sleep(1);
-      v = __hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return v;
+  // ---- stopping rule (Sec. 4.1) on a wave of its own ----
+  // After sweep s each row wave posts its threads' shares of ||W_s - W_{s-1}||^2 in LDS.
+  // The rule wave sums them (fixed order), publishes the workgroup's share in global slot
+  // (s, wg), reads every workgroup's slots for up to four published sweeps per round trip,
+  // sums them in workgroup order (every workgroup gets the same bits) and posts its
+  // decisions. Row waves never wait for memory: they run up to `lag` sweeps past the last
+  // decision, keeping those iterates in an LDS ring, and restore the sweep the rule stops
+  // at. All waits are bounded by a wall-clock deadline.
+  const int S = a.max_sweeps;
+  const int L = a.lag;
+  const int R = L + 1;  // ring slots (iterates)
+  const int K = L + 2;  // share slots
+  float* s_ring = s_rows2 + RPW * r;                                       // [R][NR*C][kCT]
+  // [K][kCT], at the 16-byte aligned end of the float area (as the host sizes it)
+  double* s_sh = reinterpret_cast<double*>(
+      reinterpret_cast<char*>(smem) +
+      align_up((size_t(RB) * RMAX + 2 * size_t(RPW) * r + size_t(R) * NR * C * kCT) * sizeof(float),
+               16));
+  uint64_t* const slots = a.slots;  // [sweep][wg]
+  auto lds_ld = [](const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   };
-  uint64_t u[4][kBatch];  // wave 0: slots of batch `lb` (workgroups lane, lane + 64, ...)
-  int lb = 0;             // batch whose slots are in flight in u, 0 for none
-  auto issue_loads = [&](int bb) {
-    const uint64_t* sl = slots + int64_t(bb - 1) * a.nwg * kBatch;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int m = 0; m < kBatch; ++m)
-        u[k][m] = lane + 64 * k < a.nwg
-                      ? __hip_atomic_load(&sl[int64_t(lane + 64 * k) * kBatch + m],
-                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                      : 0;
-    lb = bb;
+  auto lds_st = [](int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   };
-  // wave 0: totals of batch lb; false if a wait timed out
-  auto totals_of = [&](double (&D)[kBatch]) -> bool {
-    const uint64_t* sl = slots + int64_t(lb - 1) * a.nwg * kBatch;
-    bool to = false;
-#pragma unroll
-    for (int m = 0; m < kBatch; ++m) {
-      double v = 0.0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (lane + 64 * k < a.nwg && u[k][m] == kSentinel)
-          u[k][m] = spin_load(&sl[int64_t(lane + 64 * k) * kBatch + m], to);
-        v += __longlong_as_double(int64_t(u[k][m]));
-      }
-      D[m] = wave_sum64(v);
-    }
-    return !__any(to);
-  };
-  // stopping rule over the sweeps t of batch lb (t <= last): first t with
-  // ||dW_t||^2 <= tol^2 ||dW_1||^2; returns t, 0 for none, -1 on a timeout
-  double lim = 0.0;
-  const double tol2 = a.tol * a.tol;
-  auto rule = [&](int last) -> int {
-    double D[kBatch];
-    if (!totals_of(D)) return -1;
-#pragma unroll
-    for (int m = 0; m < kBatch; ++m) {
-      const int t = (lb - 1) * kBatch + m + 1;
-      if (t > last) break;
-      if (t == 1) lim = tol2 * D[m];
-      if (D[m] <= lim) return t;
-    }
-    return 0;
-  };
-
-  // ring of the last kRing iterates in LDS: [slot][q * C + c][thread]
-  float* s_ring = s_rows2 + RPW * r;
   auto ring_put = [&](int slot) {
 #pragma unroll
     for (int q = 0; q < NR; ++q)
 #pragma unroll
-      for (int c = 0; c < C; ++c) s_ring[(slot * NR * C + q * C + c) * kThreads + tid] = w[q][c];
+      for (int c = 0; c < C; ++c) s_ring[(slot * NR * C + q * C + c) * kCT + tid] = w[q][c];
   };
   auto ring_get = [&](int slot) {
 #pragma unroll
     for (int q = 0; q < NR; ++q)
 #pragma unroll
-      for (int c = 0; c < C; ++c) w[q][c] = s_ring[(slot * NR * C + q * C + c) * kThreads + tid];
+      for (int c = 0; c < C; ++c) w[q][c] = s_ring[(slot * NR * C + q * C + c) * kCT + tid];
   };
-
-  double sh[kBatch];  // this thread's shares of the current batch
-#pragma unroll
-  for (int m = 0; m < kBatch; ++m) sh[m] = 0.0;
-  int done = a.max_sweeps;
+  int done = S;
   bool timed_out = false;
-  bool stopped = false;
-  const int S = a.max_sweeps;
-  for (int s = 1; s <= S; ++s) {
-    float prev[NR][C];
+  if (wave == WPG) {
+    // ---- the rule wave ----
+    int t_pub = 1, t_dec = 1;
+    double lim = 0.0;
+    const double tol2 = a.tol * a.tol;
+    while (true) {
+      if (t_dec >= S) {  // sweeps 1 .. S-1 decided without a stop
+        if (lane == 0) lds_st(&s_decided, S);
+        break;
+      }
+      if (wall_clock64() - t_start > a.timeout_ticks) {
+        if (lane == 0) lds_st(&s_stop, -1);
+        break;
+      }
+      // publish every sweep whose shares all row waves have posted
+      int posted = lds_ld(&s_posted[0]);
 #pragma unroll
-    for (int q = 0; q < NR; ++q)
+      for (int k = 1; k < WPG; ++k) posted = min(posted, lds_ld(&s_posted[k]));
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      for (; t_pub <= posted && t_pub < S; ++t_pub) {
+        const double* sh = s_sh + (t_pub % K) * kCT;
+        const double v = ((sh[lane] + sh[lane + 64]) + sh[lane + 128]) + sh[lane + 192];
+        const double D = wave_sum64(v);
+        if (lane == 0)
+          __hip_atomic_store(&slots[int64_t(t_pub - 1) * a.nwg + blockIdx.x],
+                             uint64_t(__double_as_longlong(D)), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      }
+      // decide up to four published sweeps t_dec .. t_dec + n - 1 (< S) per round trip
+      const int n = min(4, min(t_pub, S) - t_dec);
+      if (n <= 0) {
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      uint64_t u[4][4];
 #pragma unroll
-      for (int c = 0; c < C; ++c) prev[q][c] = s == 1 ? w0[q][c] : w[q][c];
-    if ((s - 1) % kRefresh == 0) refresh();
-    sweep();
-    ring_put(s % kRing);
-    {
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          u[m][k] = (m < n && lane + 64 * k < a.nwg)
+                        ? __hip_atomic_load(
+                              &slots[int64_t(t_dec - 1 + m) * a.nwg + lane + 64 * k],
+                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                        : 0;
+      int ndone = 0, stop = 0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (m >= n) break;
+        bool missing = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) missing = missing || u[m][k] == kSentinel;
+        if (__any(missing)) break;  // a workgroup has not published this sweep yet
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v += __longlong_as_double(int64_t(u[m][k]));
+        const double D = wave_sum64(v);
+        const int t = t_dec + m;
+        if (t == 1) lim = tol2 * D;
+        ++ndone;
+        if (D <= lim) {
+          stop = t;
+          break;
+        }
+      }
+      t_dec += ndone;
+      if (stop) {
+        if (lane == 0) {
+          lds_st(&s_stop, stop);
+          lds_st(&s_decided, stop);
+        }
+        break;
+      }
+      if (lane == 0) lds_st(&s_decided, t_dec - 1);
+      if (ndone == 0) __builtin_amdgcn_s_sleep(2);
+    }
+  } else {
+    // ---- the row waves ----
+    int stp = 0;
+    for (int s = 1; s <= S; ++s) {
+      stp = lds_ld(&s_stop);
+      while (stp == 0 && s - lds_ld(&s_decided) > L) {
+        __builtin_amdgcn_s_sleep(1);
+        stp = lds_ld(&s_stop);
+      }
+      if (stp != 0) break;
+      float prev[NR][C];
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+#pragma unroll
+        for (int c = 0; c < C; ++c) prev[q][c] = s == 1 ? w0[q][c] : w[q][c];
+      if ((s - 1) % kRefresh == 0) refresh();
+      sweep();
+      ring_put(s % R);
       double d2 = 0.0;
 #pragma unroll
       for (int q = 0; q < NR; ++q)
@@ -380,73 +422,19 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
           const double df = double(w[q][c]) - double(prev[q][c]);
           d2 = fma(df, df, d2);
         }
-      const int m0 = (s - 1) % kBatch;
-#pragma unroll
-      for (int m = 0; m < kBatch; ++m)
-        if (m == m0) sh[m] = d2;
+      s_sh[(s % K) * kCT + tid] = d2;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0) lds_st(&s_posted[wave], s);
     }
-    if (s % kBatch != 0 && s != S) continue;
-
-    // ---- exchange b ----
-    const int b = (s + kBatch - 1) / kBatch;
-#pragma unroll
-    for (int m = 0; m < kBatch; ++m) {
-      const double ws = wave_sum64(sh[m]);
-      if (lane == 0) s_part[b & 1][wave][m] = ws;
-      sh[m] = 0.0;
+    // the decision for the sweeps still open
+    while (stp == 0 && lds_ld(&s_decided) < S) {
+      __builtin_amdgcn_s_sleep(1);
+      stp = lds_ld(&s_stop);
     }
-    // wave 0 decides batch b - 2 (loads issued at exchange b - 1) before the barrier
-    if (wave == 0) {
-      int st = 0;
-      if (lb > 0) st = rule(S);
-      if (lane == 0) s_dec[b & 1] = st;
-    }
-    __syncthreads();
-    const int st = s_dec[b & 1];
-    if (wave == 0) {
-      if (lane == 0) {
-        uint64_t* sl = slots + (int64_t(b - 1) * a.nwg + blockIdx.x) * kBatch;
-#pragma unroll
-        for (int m = 0; m < kBatch; ++m) {
-          double t = 0.0;
-          for (int k = 0; k < WPG; ++k) t += s_part[b & 1][k][m];
-          __hip_atomic_store(&sl[m], uint64_t(__double_as_longlong(t)), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
-      if (st == 0 && b >= 2) issue_loads(b - 1);
-    }
-    if (st > 0) {
-      ring_get(st % kRing);
-      done = st;
-      stopped = true;
-      break;
-    }
-    if (st < 0) {
-      done = s;
-      timed_out = true;
-      stopped = true;
-      break;
-    }
-  }
-  if (!stopped) {
-    // all S sweeps ran: decide batches B - 1 (loads in flight) and B, sweeps t <= S - 1
-    const int B = (S + kBatch - 1) / kBatch;
-    if (wave == 0) {
-      int st = 0;
-      if (lb > 0) st = rule(S - 1);
-      if (st == 0) {
-        issue_loads(B);
-        st = rule(S - 1);
-      }
-      if (lane == 0) s_dec[2] = st;
-    }
-    __syncthreads();
-    const int st = s_dec[2];
-    if (st > 0) {
-      ring_get(st % kRing);
-      done = st;
-    } else if (st < 0) {
+    if (stp > 0) {
+      ring_get(stp % R);
+      done = stp;
+    } else if (stp < 0) {
       timed_out = true;
     }
   }
@@ -501,11 +489,11 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
         }
       }
     const double ws = wave_sum64(t);
-    if (lane == 0) s_part[0][wave][0] = ws;
+    if (lane == 0) s_part[wave] = ws;
     __syncthreads();
     if (tid == 0) {
       double e = 0.0;
-      for (int k = 0; k < WPG; ++k) e += s_part[0][k][0];
+      for (int k = 0; k < WPG; ++k) e += s_part[k];
       a.err_part[blockIdx.x] = e;
     }
   }
@@ -545,14 +533,25 @@ HFn hals_fn(int r, int nr) {
   }
 }
 
-size_t hals_lds(int r, int64_t rows) {
+constexpr size_t kLdsBudget = 150 * 1024;  // dynamic LDS (static LDS is under 1 KB)
+
+// Dynamic LDS of a launch with run-ahead `lag`: scaled G, two row blocks, the iterate ring
+// (lag + 1 slots) and the share slots (lag + 2).
+size_t hals_lds_for(int r, int64_t rows, int lag) {
   const int rpad = r <= 32 ? 16 : 64;
   const int c = r <= 16 ? 1 : (r <= 32 ? 2 : (r <= 64 ? 1 : 2));
   const int rb = 8 * hals_nb(r);
   const int nr = hals_rows_interleaved(r, rows);
   const int rpw = gram_chunk_rows(r, rows);
-  const size_t ring = size_t(kRing) * nr * c * kThreads;
-  return (size_t(rb) * rpad * c + 2 * size_t(rpw) * r + ring) * sizeof(float);
+  const size_t fl = size_t(rb) * rpad * c + 2 * size_t(rpw) * r + size_t(lag + 1) * nr * c * kCT;
+  return align_up(fl * sizeof(float), 16) + size_t(lag + 2) * kCT * sizeof(double);
+}
+
+// the longest run-ahead (at most kMaxLag, at least 2) that fits the LDS budget
+int hals_lag(int r, int64_t rows) {
+  int lag = kMaxLag;
+  while (lag > 2 && hals_lds_for(r, rows, lag) > kLdsBudget) --lag;
+  return lag;
 }
 
 }  // namespace
@@ -565,8 +564,8 @@ bool hals_supported(int64_t rows, int r, int num_cus) {
 }
 
 int64_t hals_slot_count(int64_t rows, int r, int max_sweeps) {
-  // per batch of kBatch sweeps: kBatch shares per workgroup
-  return ceil_div(int64_t(max_sweeps), int64_t(kBatch)) * hals_wgs(rows, r) * kBatch;
+  // one share per workgroup and sweep
+  return int64_t(max_sweeps) * hals_wgs(rows, r);
 }
 
 hipError_t launch_hals(const HalsArgs& h, int num_cus, hipStream_t s) {
@@ -600,14 +599,16 @@ hipError_t launch_hals(const HalsArgs& h, int num_cus, hipStream_t s) {
   a.timeout_ticks = uint64_t(rate_khz) * 1000ull * 2ull;
   (void)num_cus;
   HFn fn = hals_fn(h.r, hals_rows_interleaved(h.r, h.rows));
-  const size_t lds = hals_lds(h.r, h.rows);
+  a.lag = hals_lag(h.r, h.rows);
+  const size_t lds = hals_lds_for(h.r, h.rows, a.lag);
+  if (lds > kLdsBudget) return hipErrorInvalidValue;
   static bool attr_done = false;
   if (!attr_done) {
     for (int rr : {8, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128})
       for (int nr : {1, 2, 4}) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(hals_fn(rr, nr)),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024 - 8 * 1024);  // room for static LDS
+                                           int(kLdsBudget));
         if (e != hipSuccess) return e;
       }
     attr_done = true;
