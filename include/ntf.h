@@ -10,7 +10,8 @@
  * Conventions shared by every call
  * --------------------------------
  *  - Modes are 0-based here (1-based in the paper). 2 <= order <= NTF_MAX_ORDER.
- *  - A tensor is dense and C-contiguous: the last mode is the fastest-varying index.
+ *  - A tensor is dense and C-contiguous: the last mode is the fastest-varying index. Its
+ *    size must stay below 2 GiB (NTF_EUNSUPPORTED otherwise).
  *  - A factor A^(n) is an I_n x r float32 matrix, row-major (row j holds the r entries
  *    a_1^(n)[j] .. a_r^(n)[j] contiguously). 1 <= r <= NTF_MAX_RANK.
  *  - Every data pointer is a DEVICE pointer on the handle's device unless stated

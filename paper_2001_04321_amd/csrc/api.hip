@@ -83,6 +83,11 @@ ntf_status check_tensor(const ntf_tensor* T) {
                   "tensor too large");
     total *= T->dims[l];
   }
+  // the MTTKRP streams the tensor through buffer resources with 32-bit byte offsets
+  const int64_t esize = T->dtype == NTF_BF16 ? 2 : 4;
+  NTF_RETURN_IF(total * esize >= (int64_t(1) << 31), NTF_EUNSUPPORTED,
+                "tensor of %lld bytes: at most 2 GiB - 1 supported",
+                static_cast<long long>(total * esize));
   // every mode view (L, I, R) must keep L and R below 2^31 (32-bit index arithmetic)
   for (int n = 0; n < T->order; ++n) {
     const ModeView v = make_mode_view(*T, n);

@@ -85,13 +85,26 @@ struct KArgs {
   int64_t per_split, extra;
   int64_t mtiles;              // row tiles (the grid is mtiles x splits workgroups)
   int av_vec;                  // A_v rows are RP floats (r == RP) and 16-byte aligned
+  int64_t tbytes;              // tensor size in bytes (< 2^31: buffer-resource offsets)
   float* ystore;               // case A, one wave per row tile: store Y[i][u][:] = T_u A_v
                                // rows instead of folding them (null: fold into P)
   int r;
   int vb;                      // v-block length (multiple of the chunk)
   int ub;                      // u values per X batch
-  int vec_ok;
 };
+
+// Tensor loads go through a buffer resource: an offset at or past the resource's size
+// (kOOB) reads zeros in hardware, so tails and padding need neither branches nor selects on
+// the loaded value (either would make the compiler drain the load queue at every join).
+// Resource word 3 (data format 32, the CDNA setting for raw buffer loads).
+constexpr int kBufWord3 = 0x00020000;
+constexpr uint32_t kOOB = 0x80000000u;
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint4 bload16(__amdgpu_buffer_rsrc_t rs, uint32_t byte_off) {
+  const i32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, byte_off, 0, 0);
+  return make_uint4(uint32_t(v.x), uint32_t(v.y), uint32_t(v.z), uint32_t(v.w));
+}
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   const uint32_t b = __float_as_uint(f);
@@ -119,7 +132,7 @@ __device__ __forceinline__ int64_t t_base(const KArgs& k, uint32_t u) {
   return int64_t(a) * k.a_stride + bhi * k.Iv;
 }
 
-template <bool BF16, int NT, int WM, int WK, bool LAST>
+template <bool BF16, int NT, int WM, int WK, bool LAST, bool VEC>
 __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
   constexpr int RP = 32 * NT;
   constexpr int KCH = BF16 ? 64 : 32;
@@ -180,26 +193,39 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) buf[d][q] = make_uint4(0, 0, 0, 0);
 
-  auto load_item = [&](uint4 (&reg)[4], int64_t base, int64_t v0c) {
+  // Loads are predicated by address, not by branches: an element outside the tensor (or an
+  // item past the end) loads from T[0] and is replaced by zero. Branch-free item code lets
+  // the compiler keep all prefetched items in flight instead of draining the load queue at
+  // every control-flow join.
+  const uint4 zero4 = make_uint4(0, 0, 0, 0);
+  (void)zero4;
+  const __amdgpu_buffer_rsrc_t trs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(k.T), short(0), int(k.tbytes), kBufWord3);
+  auto load_item = [&](uint4 (&reg)[4], int64_t base, int64_t v0c, bool valid) {
     if (!LAST) {
       // lane (row, half): elements v0c + half*KCH/2 + [0, KCH/2) of its row
       constexpr int EPL = KCH / 2;
+      constexpr int SLOT = EPL / 4;  // elements per 16 bytes
       const int64_t v = v0c + half * EPL;
       const int64_t off = base + row * k.R + v;
-      if (row_ok && k.vec_ok && v + EPL <= k.Iv) {
-        const uint4* p = reinterpret_cast<const uint4*>(T + off);
+      if constexpr (VEC) {
+        // rows 16-byte aligned and I_v a multiple of 16 bytes: whole slots in or out
 #pragma unroll
-        for (int q = 0; q < 4; ++q) reg[q] = p[q];
-      } else if (row_ok && k.vec_ok && k.Iv % (EPL / 4) == 0) {
-        // tail chunk with I_v a multiple of the 16-byte slot: whole slots or none
-        const uint4* p = reinterpret_cast<const uint4*>(T + off);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          reg[q] = v + (q + 1) * (EPL / 4) <= k.Iv ? p[q] : make_uint4(0, 0, 0, 0);
+        for (int q = 0; q < 4; ++q) {
+          const bool ok = valid && row_ok && v + (q + 1) * SLOT <= k.Iv;
+          reg[q] = bload16(trs, ok ? uint32_t((off + q * SLOT) * sizeof(TE)) : kOOB);
+        }
       } else {
         TE tmp[EPL];
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) tmp[e] = (row_ok && v + e < k.Iv) ? T[off + e] : TE(0);
+        for (int e = 0; e < EPL; ++e) {
+          const bool ok = valid && row_ok && v + e < k.Iv;
+          const uint32_t bo = ok ? uint32_t((off + e) * sizeof(TE)) : kOOB;
+          if constexpr (BF16)
+            tmp[e] = TE(__builtin_amdgcn_raw_buffer_load_b16(trs, bo, 0, 0));
+          else
+            tmp[e] = __builtin_bit_cast(TE, __builtin_amdgcn_raw_buffer_load_b32(trs, bo, 0, 0));
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) reg[q] = reinterpret_cast<uint4*>(tmp)[q];
       }
@@ -209,9 +235,10 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
 #pragma unroll
       for (int t = 0; t < 16; ++t) {
         const int64_t v = v0c + 2 * t + half;
-        tmp[t] = (row_ok && v < k.Iv)
-                     ? reinterpret_cast<const float*>(T)[base + v * k.I + row]
-                     : 0.f;
+        const bool ok = valid && row_ok && v < k.Iv;
+        tmp[t] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(
+                       trs, ok ? uint32_t((base + v * k.I + row) * 4) : kOOB, 0, 0));
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) reg[q] = reinterpret_cast<uint4*>(tmp)[q];
@@ -224,18 +251,20 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
       for (int q = 0; q < 4; ++q) {
         const int64_t v = v0c + q * 16 + (lane >> 2);
         const int64_t off = base + v * k.I + ic;
-        uint4 val = make_uint4(0, 0, 0, 0);
-        if (v < k.Iv) {
-          if (k.vec_ok && ic + 8 <= k.I) {
-            val = *reinterpret_cast<const uint4*>(T + off);
-          } else {
-            uint16_t tmp[8];
+        if constexpr (VEC) {
+          // I is a multiple of 8: a 16-byte group is wholly inside or outside
+          const bool ok = valid && v < k.Iv && ic + 8 <= k.I;
+          reg[q] = bload16(trs, ok ? uint32_t(off * 2) : kOOB);
+        } else {
+          uint16_t tmp[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) tmp[e] = (ic + e < k.I) ? T[off + e] : uint16_t(0);
-            val = *reinterpret_cast<uint4*>(tmp);
+          for (int e = 0; e < 8; ++e) {
+            const bool ok = valid && v < k.Iv && ic + e < k.I;
+            tmp[e] = uint16_t(
+                __builtin_amdgcn_raw_buffer_load_b16(trs, ok ? uint32_t((off + e) * 2) : kOOB, 0, 0));
           }
+          reg[q] = *reinterpret_cast<uint4*>(tmp);
         }
-        reg[q] = val;
       }
     }
   };
@@ -363,25 +392,28 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
     __syncthreads();
 
     const int nitems = nu * ipu;
-    // prefetch cursor (pu, pj) and compute cursor (cu, cj) over (u, chunk) items
-    int pu = 0, pj = 0;
+    // prefetch cursor (pu, pj) and compute cursor (cu, cj) over (u, chunk) items; items past
+    // the end load zeros (see load_item), so the loop body has no data-dependent branches
+    int pu = 0, pj = 0, pit = 0;
     auto prefetch = [&](uint4 (&reg)[4]) {
       const int kc = wk + pj * WK;
-      if (kc < nkc) load_item(reg, t_base<LAST>(k, uint32_t(u0 + pu)), v0 + int64_t(kc) * KCH);
+      const bool valid = pit < nitems && kc < nkc;
+      const uint32_t uq = uint32_t(u0 + (pit < nitems ? pu : 0));
+      load_item(reg, t_base<LAST>(k, uq), v0 + int64_t(kc) * KCH, valid);
+      ++pit;
       if (++pj == ipu) {
         pj = 0;
         ++pu;
       }
     };
 #pragma unroll
-    for (int d = 0; d < PD - 1; ++d)
-      if (d < nitems) prefetch(buf[d]);
+    for (int d = 0; d < PD - 1; ++d) prefetch(buf[d]);
     int cu = 0, cj = 0;
     for (int base = 0; base < nitems; base += PD) {
 #pragma unroll
       for (int d = 0; d < PD; ++d) {
+        prefetch(buf[(d + PD - 1) % PD]);
         if (base + d < nitems) {
-          if (base + d + PD - 1 < nitems) prefetch(buf[(d + PD - 1) % PD]);
           if (cj == 0) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
@@ -399,8 +431,10 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
                 const int p = nt * 32 + col;
 #pragma unroll
                 for (int e = 0; e < 16; ++e) {
+                  // out-of-range entries go to the padding past Y (no branches)
                   const int64_t i = i0 + wm * 32 + 8 * (e >> 2) + half * 4 + (e & 3);
-                  if (p < k.r && i < k.I) k.ystore[(i * k.U + uu) * k.r + p] = y[nt][e];
+                  const bool ok = p < k.r && i < k.I;
+                  k.ystore[ok ? (i * k.U + uu) * k.r + p : k.I * k.U * k.r + col] = y[nt][e];
                 }
               }
             } else {
@@ -540,35 +574,48 @@ __global__ __launch_bounds__(256) void fold_i_kernel(const float* __restrict__ Y
 
 using KernelFn = void (*)(KArgs);
 
-template <bool BF16, int NT, int WM, int WK, bool LAST>
+template <bool BF16, int NT, int WM, int WK, bool LAST, bool VEC>
 KernelFn pick() {
-  return mttkrp_kernel<BF16, NT, WM, WK, LAST>;
+  return mttkrp_kernel<BF16, NT, WM, WK, LAST, VEC>;
 }
 
 // WM x WK = 4 waves. Ranks above 64 use row tiles of at least 64 rows.
-template <bool BF16, bool LAST>
+template <bool BF16, bool LAST, bool VEC>
 KernelFn pick_shape(int wm, int nt) {
   if (nt == 1) {
-    if (wm == 1) return pick<BF16, 1, 1, 4, LAST>();
-    if (wm == 2) return pick<BF16, 1, 2, 2, LAST>();
-    return pick<BF16, 1, 4, 1, LAST>();
+    if (wm == 1) return pick<BF16, 1, 1, 4, LAST, VEC>();
+    if (wm == 2) return pick<BF16, 1, 2, 2, LAST, VEC>();
+    return pick<BF16, 1, 4, 1, LAST, VEC>();
   }
   if (nt == 2) {
-    if (wm == 1) return pick<BF16, 2, 1, 4, LAST>();
-    if (wm == 2) return pick<BF16, 2, 2, 2, LAST>();
-    return pick<BF16, 2, 4, 1, LAST>();
+    if (wm == 1) return pick<BF16, 2, 1, 4, LAST, VEC>();
+    if (wm == 2) return pick<BF16, 2, 2, 2, LAST, VEC>();
+    return pick<BF16, 2, 4, 1, LAST, VEC>();
   }
   if (nt == 4) {
-    if (wm == 4) return pick<BF16, 4, 4, 1, LAST>();
-    return pick<BF16, 4, 2, 2, LAST>();
+    if (wm == 4) return pick<BF16, 4, 4, 1, LAST, VEC>();
+    return pick<BF16, 4, 2, 2, LAST, VEC>();
   }
-  if (wm == 4) return pick<BF16, 8, 4, 1, LAST>();
-  return pick<BF16, 8, 2, 2, LAST>();
+  if (wm == 4) return pick<BF16, 8, 4, 1, LAST, VEC>();
+  return pick<BF16, 8, 2, 2, LAST, VEC>();
 }
 
-KernelFn select_kernel(bool bf16, bool last, int wm, int nt) {
-  if (bf16) return last ? pick_shape<true, true>(wm, nt) : pick_shape<true, false>(wm, nt);
-  return last ? pick_shape<false, true>(wm, nt) : pick_shape<false, false>(wm, nt);
+KernelFn select_kernel(bool bf16, bool last, int wm, int nt, bool vec) {
+  if (vec) {
+    if (bf16)
+      return last ? pick_shape<true, true, true>(wm, nt) : pick_shape<true, false, true>(wm, nt);
+    return last ? pick_shape<false, true, true>(wm, nt) : pick_shape<false, false, true>(wm, nt);
+  }
+  if (bf16)
+    return last ? pick_shape<true, true, false>(wm, nt) : pick_shape<true, false, false>(wm, nt);
+  return last ? pick_shape<false, true, false>(wm, nt) : pick_shape<false, false, false>(wm, nt);
+}
+
+// 16-byte loads apply: every row start is 16-byte aligned and the contiguous extent is a
+// multiple of 16 bytes (the tensor base is 16-byte aligned)
+bool vec_loads(const MttkrpPlan& pl) {
+  const int vec = pl.dtype == NTF_BF16 ? 8 : 4;
+  return pl.layout == 1 ? (pl.v.I % vec == 0) : (pl.v.R % vec == 0 && pl.Iv % vec == 0);
 }
 
 int n_tiles(int r) {
@@ -647,7 +694,7 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus, bool s
   // One residency wave: grid = resident workgroups per CU x CUs (a partial second wave
   // would double the time of the tail). The X batch (and so LDS and occupancy) depends on
   // the split count; two refinement passes settle it (LDS only shrinks between passes).
-  KernelFn fn = select_kernel(bf16, last, pl.wm, nt);
+  KernelFn fn = select_kernel(bf16, last, pl.wm, nt, vec_loads(pl));
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   pl.ub = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(8192 / pl.rpad), pl.U)));
@@ -700,13 +747,13 @@ hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& 
   k.vb = pl.vb;
   k.ub = pl.ub;
   const bool bf16 = pl.dtype == NTF_BF16;
-  const int vec = bf16 ? 8 : 4;
-  k.vec_ok = last ? (pl.v.I % vec == 0) : (pl.v.R % vec == 0 && pl.Iv % vec == 0);
+  const bool vec = vec_loads(pl);
+  k.tbytes = pl.v.L * pl.v.I * pl.v.R * (bf16 ? 2 : 4);
   const bool split = pl.splits > 1;
   k.out = split ? partials : P;
-  KernelFn fn = select_kernel(bf16, last, pl.wm, pl.variant);
-  static bool attr_done[2][2][4][8] = {};
-  bool& done = attr_done[bf16][last][pl.wm - 1][pl.variant - 1];
+  KernelFn fn = select_kernel(bf16, last, pl.wm, pl.variant, vec);
+  static bool attr_done[2][2][2][4][8] = {};
+  bool& done = attr_done[vec][bf16][last][pl.wm - 1][pl.variant - 1];
   if (!done) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);

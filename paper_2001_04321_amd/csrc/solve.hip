@@ -105,7 +105,8 @@ void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
     maxpart = std::max<size_t>(
         maxpart, size_t(fold_i_splits(T.dims[0], T.dims[1], r)) * T.dims[1] * r);
   b.mt_part = ar.take<float>(std::max<size_t>(maxpart, 1));
-  b.Y = shared_y ? ar.take<float>(size_t(T.dims[0]) * T.dims[1] * r) : nullptr;
+  // (+64: padding that out-of-range stores of the Y kernel write to)
+  b.Y = shared_y ? ar.take<float>(size_t(T.dims[0]) * T.dims[1] * r + 64) : nullptr;
   b.nslots = maxslots;
   b.slots = ar.take<double>(size_t(maxslots));
   b.sweeps = ar.take<int32_t>(kMaxOrder);
