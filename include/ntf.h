@@ -162,7 +162,7 @@ ntf_status ntf_gram(ntf_handle* h, const float* const* A, const int64_t* rows, i
  * ||W_1 - W_0||_F (Sec. 4.1; norms in float64). tol = 0 runs until a sweep changes
  * nothing or max_sweeps is reached. A column with G[j, j] = 0 is set to 0.
  * W: rows x r, in place (input = warm start). P: rows x r. G: r x r float32, symmetric.
- * sweeps_done: device int32 or NULL. rows <= 16384 for r <= 32, <= 4096 for r <= 128;
+ * sweeps_done: device int32 or NULL. rows <= 12288 for r <= 32, <= 3072 for r <= 128;
  * r > 128 or more rows return NTF_EUNSUPPORTED. */
 ntf_status ntf_hals_update(ntf_handle* h, float* W, const float* P, const float* G,
                            int64_t rows, int32_t r, int32_t max_sweeps, double tol,

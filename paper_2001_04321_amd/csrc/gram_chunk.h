@@ -7,46 +7,98 @@
 
 namespace ntf {
 
-// Row layout of the A-HALS kernel: a row group of 16 lanes (r <= 32) or of a whole wave
-// (r <= 128); NR rows per group are processed together, NR as small as keeps the grid
-// within 256 workgroups of 4 waves. The rows of one workgroup are also one Gram chunk.
+// Row layout of the A-HALS kernel: kHalsRowWaves waves own rows (a fourth wave runs the
+// stopping rule, on a SIMD of its own); a row group of 16 lanes (r <= 32) or of a whole
+// wave (r <= 128) owns a row; NR rows per group are processed together, NR as small as
+// keeps the grid within 256 workgroups. The rows of one workgroup are also one Gram chunk.
+constexpr int kHalsRowWaves = 3;
 __host__ __device__ inline int hals_rows_interleaved(int r, int64_t rows) {
-  const int64_t per_nr = 4 * (r <= 32 ? 4 : 1);  // rows per workgroup with NR = 1
+  const int64_t per_nr = kHalsRowWaves * (r <= 32 ? 4 : 1);  // rows per workgroup, NR = 1
   for (int nr = 1; nr < 4; nr *= 2)
     if ((rows + per_nr * nr - 1) / (per_nr * nr) <= 256) return nr;
   return 4;
 }
 __host__ __device__ inline int gram_chunk_rows(int r, int64_t rows) {
-  return 4 * (r <= 32 ? 4 : 1) * hals_rows_interleaved(r, rows);
+  return kHalsRowWaves * (r <= 32 ? 4 : 1) * hals_rows_interleaved(r, rows);
 }
 
 // out[p * r + q] = sum_{i < nrows} rows[i * r + p] * rows[i * r + q] in float64, rows taken
-// in order (products of float32 values are exact in float64). `rows` is in LDS; all
-// threads of the block take part; `out` is global.
-__device__ inline void chunk_gram(const float* rows, int nrows, int r, double* out) {
-  constexpr int kEPT = 8;
-  const int rr = r * r;
-  for (int base = 0; base < rr; base += blockDim.x * kEPT) {
-    double acc[kEPT];
-    int pp[kEPT], qq[kEPT];
+// in order (products of float32 values are exact in float64, so neither the tiling nor the
+// use of fused multiply-adds changes the bits). `rows` is in LDS; all threads of the block
+// take part, each owning T x T tiles of entries (tile t = threadIdx.x + k * blockDim.x);
+// `out` is global and may be NULL. Returns the thread's share of
+// sum_{p,q} M[p, q] out[p, q] for the optional float64 r x r matrix M (global), else 0.
+// With PRE, the M entries of the thread's first tile come from `mfirst` (loaded early by
+// the caller with gram_tile_m).
+template <int T>
+__device__ inline void gram_tile_m(const double* M, int r, int tile, double (&m)[T][T]) {
+  const int nt = (r + T - 1) / T;
+  const int p0 = (tile / nt) * T;
+  const int q0 = (tile - (tile / nt) * nt) * T;
 #pragma unroll
-    for (int t = 0; t < kEPT; ++t) {
-      const int e = base + t * blockDim.x + threadIdx.x;
-      acc[t] = 0.0;
-      pp[t] = e < rr ? e / r : 0;
-      qq[t] = e < rr ? e - (e / r) * r : 0;
+  for (int a = 0; a < T; ++a)
+#pragma unroll
+    for (int b = 0; b < T; ++b)
+      m[a][b] = (M && tile < nt * nt && p0 + a < r && q0 + b < r) ? M[(p0 + a) * r + q0 + b]
+                                                                  : 0.0;
+}
+
+template <int T, bool PRE>
+__device__ inline double chunk_gram_tiles(const float* rows, int nrows, int r, double* out,
+                                          const double* M, const double (&mfirst)[T][T]) {
+  const int nt = (r + T - 1) / T;
+  double dot = 0.0;
+  for (int tile = threadIdx.x; tile < nt * nt; tile += blockDim.x) {
+    const int p0 = (tile / nt) * T;
+    const int q0 = (tile - (tile / nt) * nt) * T;
+    double m[T][T];
+    if (PRE && tile == int(threadIdx.x)) {
+#pragma unroll
+      for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int b = 0; b < T; ++b) m[a][b] = mfirst[a][b];
+    } else {
+      gram_tile_m<T>(M, r, tile, m);
     }
+    double acc[T][T];
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+      for (int b = 0; b < T; ++b) acc[a][b] = 0.0;
     for (int i = 0; i < nrows; ++i) {
       const float* row = rows + i * r;
+      double xp[T], xq[T];
 #pragma unroll
-      for (int t = 0; t < kEPT; ++t) acc[t] += double(row[pp[t]]) * double(row[qq[t]]);
+      for (int a = 0; a < T; ++a) {
+        xp[a] = p0 + a < r ? double(row[p0 + a]) : 0.0;
+        xq[a] = q0 + a < r ? double(row[q0 + a]) : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int b = 0; b < T; ++b) acc[a][b] = fma(xp[a], xq[b], acc[a][b]);
     }
 #pragma unroll
-    for (int t = 0; t < kEPT; ++t) {
-      const int e = base + t * blockDim.x + threadIdx.x;
-      if (e < rr) out[e] = acc[t];
-    }
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+      for (int b = 0; b < T; ++b)
+        if (p0 + a < r && q0 + b < r) {
+          if (out) out[(p0 + a) * r + q0 + b] = acc[a][b];
+          dot = fma(m[a][b], acc[a][b], dot);
+        }
   }
+  return dot;
+}
+
+// tile edge used for rank r
+__host__ __device__ constexpr int gram_tile_edge(int r) { return r <= 32 ? 2 : 4; }
+
+__device__ inline double chunk_gram(const float* rows, int nrows, int r, double* out,
+                                    const double* M = nullptr) {
+  const double z2[2][2] = {};
+  const double z4[4][4] = {};
+  return r <= 32 ? chunk_gram_tiles<2, false>(rows, nrows, r, out, M, z2)
+                 : chunk_gram_tiles<4, false>(rows, nrows, r, out, M, z4);
 }
 
 }  // namespace ntf

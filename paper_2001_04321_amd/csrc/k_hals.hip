@@ -3,19 +3,24 @@
 //
 // Rows of the block are independent NNLS problems coupled only through the stopping rule.
 // A group of RPAD lanes (16 or 64) owns one row; lane g holds columns g, g + RPAD, ... The
-// column update W_j = max(0, P_j - sum_{l != j} W_l G_lj) / G_jj is computed as
-//   q_k = P_k / G_kk - sum_{l != k} W_l (G_lk / G_kk),   W_j <- max(0, q_j),
-// with q kept current by rank-one updates (after W_j changes by delta, q_k -= delta G_jk /
-// G_kk for every k != j) and formed from scratch every kRefresh sweeps. A dead component
-// (G_jj = 0) has q_j = 0, so it is 0 after its first update, as the method prescribes. The
-// rank is padded to a compile-time multiple of 8 with zero columns, whose updates are 0.
+// column update W_j = max(0, P_j - sum_{l != j} W_l G_lj) / G_jj is computed from
+//   q_k = P_k / G_kk - sum_{l != k} W_l (G_lk / G_kk)   (W_j <- max(0, q_j))
+// kept as the step z_k = q_k - W_k: the change of column j is delta = max(z_j, -W_j), and
+// then z_k -= delta G_jk / G_kk for k != j and z_j -= delta. With the scaled table
+// S_jk = -G_jk / G_kk (k != j), S_jj = -1, both are one multiply-add z_k += delta S_jk, so a
+// column costs a max and a broadcast multiply-add on its critical path. z is kept current
+// across sweeps and formed from scratch (z = P / diag(G) + W S) every kRefresh sweeps. A
+// dead component (G_jj = 0) has an all-zero column in S and z_j = W_j = 0, so it stays 0,
+// as the method prescribes. The rank is padded to a compile-time multiple of 8 with zero
+// columns, whose updates are 0.
 //
-// Stopping rule: a fifth wave of each workgroup runs it while four waves sweep. It sums the
-// row waves' shares of ||W_s - W_{s-1}||^2 (float64, fixed order), publishes the
-// workgroup's share, sums every workgroup's shares in workgroup order (so every workgroup
-// takes the same decision) and posts the decisions in LDS. Row waves run up to `lag`
-// sweeps past the last decision, keeping those iterates in an LDS ring, and restore the
-// iterate of the sweep the rule stops at. Waits are bounded by a wall-clock deadline
+// Stopping rule: a fourth wave of each workgroup runs it while three waves sweep (so it has
+// a SIMD of its own and takes no issue cycles from a row wave). It sums the row waves'
+// shares of ||W_s - W_{s-1}||^2 (float64, fixed order), publishes the workgroup's share,
+// sums every workgroup's shares in workgroup order (so every workgroup takes the same
+// decision) and posts the decisions in LDS. Row waves run up to `lag` sweeps past the last
+// decision, keeping those iterates in an LDS ring, and restore the iterate of the sweep
+// the rule stops at. Waits are bounded by a wall-clock deadline
 // (timeout: NTF_FLAG_WAIT_TIMEOUT). The grid never exceeds the CU count, so all
 // workgroups are resident together.
 //
@@ -29,10 +34,11 @@
 namespace ntf {
 namespace {
 
-constexpr int kWaves = 4;                  // waves that own rows
+constexpr int kWaves = kHalsRowWaves;      // waves that own rows
 constexpr int kCT = 64 * kWaves;           // their threads
 constexpr int kThreads = kCT + 64;         // plus one wave that runs the stopping rule
-constexpr int kMaxLag = 8;                 // sweeps the row waves may run ahead of a decision
+constexpr int kMaxLag = 16;                // sweeps the row waves may run ahead of a decision
+constexpr int kDecide = 4;                 // slot loads per lane in one round trip of the rule
 constexpr int kRefresh = 4;  // sweeps between exact recomputations of q
 constexpr uint64_t kSentinel = ~uint64_t(0);
 
@@ -116,6 +122,55 @@ __device__ __forceinline__ float bcast(float x, int o) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), o));
 }
 
+// One column step for 16-lane row groups, in the step form described at the top:
+//   d = max(z_cs, -w); w <- owner ? w + d : w; z_c += bcast_o(d) * g_c for every slot c,
+// where z_cs is the slot that holds the column and bcast_o is lane o of each 16-lane row.
+// Written out because the compiler does not fold a DPP broadcast into a multiply-add and
+// canonicalises the max operands; here the broadcast is a DPP operand of v_fmac_f32 and
+// the critical path of a column is the max and one multiply-add. The two instructions
+// between the max and the first DPP read meet the two wait states a DPP read of a freshly
+// written VGPR needs. `owner` is the wave-wide mask of the lanes that hold column o.
+#define NTF_COL_CASE2(n)                                                                  \
+  case n:                                                                                 \
+    asm volatile("v_max_f32_e64 %[d], %[zc], -%[w]\n\t"                                            \
+        "v_add_f32_e32 %[t], %[w], %[d]\n\t"                                              \
+        "v_cndmask_b32_e64 %[w], %[w], %[t], %[m]\n\t"                                     \
+        "v_fmac_f32_dpp %[z0], %[d], %[g0] row_newbcast:" #n                              \
+        " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"                                    \
+        "v_fmac_f32_dpp %[z1], %[d], %[g1] row_newbcast:" #n                              \
+        " row_mask:0xf bank_mask:0xf bound_ctrl:1"                                         \
+        : [z0] "+v"(z0), [z1] "+v"(z1), [w] "+v"(w), [d] "=&v"(d), [t] "=&v"(t)           \
+        : [zc] "v"(CS == 0 ? z0 : z1), [g0] "v"(g0), [g1] "v"(g1), [m] "s"(owner));        \
+    break;
+#define NTF_COL_CASE1(n)                                                                  \
+  case n:                                                                                 \
+    asm volatile("v_max_f32_e64 %[d], %[z0], -%[w]\n\t"                                            \
+        "v_add_f32_e32 %[t], %[w], %[d]\n\t"                                              \
+        "v_cndmask_b32_e64 %[w], %[w], %[t], %[m]\n\t"                                     \
+        "v_fmac_f32_dpp %[z0], %[d], %[g0] row_newbcast:" #n                              \
+        " row_mask:0xf bank_mask:0xf bound_ctrl:1"                                         \
+        : [z0] "+v"(z0), [w] "+v"(w), [d] "=&v"(d), [t] "=&v"(t)                          \
+        : [g0] "v"(g0), [m] "s"(owner));                                                   \
+    break;
+#define NTF_COL_CASES(X) \
+  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+
+template <int CS>
+__device__ __forceinline__ void col_step16x2(int o, float& z0, float& z1, float& w, float g0,
+                                             float g1, uint64_t owner) {
+  float d, t;
+  switch (o) { NTF_COL_CASES(NTF_COL_CASE2) }
+}
+
+__device__ __forceinline__ void col_step16x1(int o, float& z0, float& w, float g0,
+                                             uint64_t owner) {
+  float d, t;
+  switch (o) { NTF_COL_CASES(NTF_COL_CASE1) }
+}
+#undef NTF_COL_CASES
+#undef NTF_COL_CASE1
+#undef NTF_COL_CASE2
+
 // RPAD lanes per row group (16: four groups per wave; 64: one per wave), C columns per
 // lane, NR rows per group processed in lockstep, NB blocks of 8 columns swept (8 NB >= r).
 template <int RPAD, int C, int NR, int NB>
@@ -131,15 +186,13 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   constexpr bool GREG = RB * C <= 64;
   extern __shared__ __attribute__((aligned(16))) float smem[];
   __shared__ double s_part[WPG + 1];  // epilogue: per-wave F-hat shares
-  // row waves -> rule wave: last sweep whose shares each row wave has posted;
   // rule wave -> row waves: last sweep decided, and the sweep the rule stops at (0: none,
   // -1: a wait timed out)
-  __shared__ int s_posted[WPG];
   __shared__ int s_decided;
   __shared__ int s_stop;
 
   const int r = a.r;
-  float* s_g = smem;               // scaled G, RB x RMAX: s_g[j][k] = G_jk / G_kk, 0 if j == k
+  float* s_g = smem;               // scaled G, RB x RMAX: s_g[j][k] = S_jk (see above)
   float* s_rows = s_g + RB * RMAX;    // RPW x r: P block, then new rows
   float* s_rows2 = s_rows + RPW * r;  // RPW x r: extrapolated rows (ring follows)
 
@@ -151,30 +204,11 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   const int64_t row0 = int64_t(blockIdx.x) * RPW;
   const int nrows = int(std::min<int64_t>(RPW, a.rows - row0));
 
-  if (tid < WPG) s_posted[tid] = 0;
   if (tid == 0) {
     s_decided = 0;
     s_stop = 0;
   }
-  for (int e = tid; e < RB * RMAX; e += kThreads) {
-    const int j = e / RMAX;
-    const int k = e - j * RMAX;
-    float v = 0.f;
-    if (j < r && k < r && j != k) {
-      const float gkk = a.G[k * r + k];
-      v = gkk != 0.f ? a.G[j * r + k] * (1.f / gkk) : 0.f;
-    }
-    s_g[e] = v;
-  }
-  // P block of this workgroup: rows row0 .. row0+nrows-1 are contiguous in memory
-  {
-    const int n = nrows * r;
-    const float* Pb = a.P + row0 * r;
-    for (int e = tid; e < n; e += kThreads) s_rows[e] = Pb[e];
-  }
-  __syncthreads();
-
-  // local row q of this lane: wave * RPWV + q * GPW + gi
+  // global loads that do not depend on LDS go out first: this lane's W0 entries and diag(G)
   int lrow[NR];
   bool rok[NR];
 #pragma unroll
@@ -182,19 +216,90 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
     lrow[q] = wave * RPWV + q * GPW + gi;
     rok[q] = wave < WPG && lrow[q] < nrows;  // the rule wave owns no rows
   }
-  float w[NR][C], pinv[NR][C], w0[NR][C], qv[NR][C];
+  float w0[NR][C], ginv[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int k = c * RPAD + gl;
     const float gkk = k < r ? a.G[k * r + k] : 0.f;
-    const float inv = gkk != 0.f ? 1.f / gkk : 0.f;
+    ginv[c] = gkk != 0.f ? 1.f / gkk : 0.f;
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      w0[q][c] = (rok[q] && k < r) ? a.W0[(row0 + lrow[q]) * r + k] : 0.f;
+  }
+  // LDS beyond the two row blocks: the iterate ring and the share slots of the stopping
+  // rule (see below)
+  const int S = a.max_sweeps;
+  const int L = a.lag;
+  const int R = L + 1;  // ring slots (iterates)
+  const int K = L + 2;  // share slots
+  float* s_ring = s_rows2 + RPW * r;                                       // [R][NR*C][kCT]
+  // [K][kCT], at the 16-byte aligned end of the float area (as the host sizes it)
+  double* s_sh = reinterpret_cast<double*>(
+      reinterpret_cast<char*>(smem) +
+      align_up((size_t(RB) * RMAX + 2 * size_t(RPW) * r + size_t(R) * NR * C * kCT) * sizeof(float),
+               16));
+
+  // setup: the loads of each batch are all in flight before any is used
+  constexpr int kB = 8;
+  for (int base = 0; base < RB * RMAX; base += kB * kThreads) {
+    float gv[kB], gd[kB];
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      const int e = base + i * kThreads + tid;
+      const int j = e / RMAX;
+      const int k = e - j * RMAX;
+      const bool ok = e < RB * RMAX && j < r && k < r;
+      gv[i] = ok ? a.G[j * r + k] : 0.f;
+      gd[i] = ok ? a.G[k * r + k] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      const int e = base + i * kThreads + tid;
+      const int j = e / RMAX;
+      const int k = e - j * RMAX;
+      if (e < RB * RMAX)
+        s_g[e] = gd[i] != 0.f ? (j == k ? -1.f : -(gv[i] * (1.f / gd[i]))) : 0.f;
+    }
+  }
+  // P block of this workgroup: rows row0 .. row0+nrows-1 are contiguous in memory
+  {
+    const int n = nrows * r;
+    const float* Pb = a.P + row0 * r;
+    for (int base = 0; base < n; base += kB * kThreads) {
+      float pv[kB];
+#pragma unroll
+      for (int i = 0; i < kB; ++i) {
+        const int e = base + i * kThreads + tid;
+        pv[i] = e < n ? Pb[e] : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < kB; ++i) {
+        const int e = base + i * kThreads + tid;
+        if (e < n) s_rows[e] = pv[i];
+      }
+    }
+  }
+  for (int e = tid; e < K * kCT; e += kThreads) s_sh[e] = -1.0;  // every share slot empty
+  __syncthreads();
+  // for the F-hat share: the G entries of this thread's epilogue Gram tile, loaded after
+  // the last barrier before the epilogue so that the sweeps hide their latency
+  constexpr int TG = gram_tile_edge(RPAD == 16 ? 32 : 128);  // chunk_gram's tile edge
+  const int ntg = (r + TG - 1) / TG;
+  const bool gpre = a.err_part != nullptr && ntg * ntg <= kThreads;  // one tile per thread
+  double gm[TG][TG];
+  gram_tile_m<TG>(gpre ? a.G64 : nullptr, r, tid, gm);
+
+  // local row q of this lane: wave * RPWV + q * GPW + gi
+  float w[NR][C], pinv[NR][C], zv[NR][C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int k = c * RPAD + gl;
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       const bool ok = rok[q] && k < r;
-      w0[q][c] = ok ? a.W0[(row0 + lrow[q]) * r + k] : 0.f;
-      pinv[q][c] = ok ? s_rows[lrow[q] * r + k] * inv : 0.f;
+      pinv[q][c] = ok ? s_rows[lrow[q] * r + k] * ginv[c] : 0.f;
       // a dead component (G_kk = 0) is 0 after its first update and stays 0
-      w[q][c] = (ok && gkk != 0.f) ? w0[q][c] : 0.f;
+      w[q][c] = (ok && ginv[c] != 0.f) ? w0[q][c] : 0.f;
     }
   }
   float greg[GREG ? RB : 1][C];
@@ -215,13 +320,13 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
         gb[t][c] = GREG ? greg[GREG ? jb * 8 + t : 0][c] : s_g[(jb * 8 + t) * RMAX + c * RPAD + gl];
   };
   // lanes owning column offset o of their group, as a wave-wide constant mask
-  auto is_owner = [&](int o) {
+  auto owner_mask = [&](int o) {
     uint64_t m = 0;
 #pragma unroll
     for (int g = 0; g < GPW; ++g) m |= uint64_t(1) << (g * RPAD + o);
-    return __builtin_amdgcn_inverse_ballot_w64(m);
+    return m;
   };
-  // q = P / diag(G) - W G' from scratch, two interleaved accumulators (fixed order)
+  // z = P / diag(G) + W S from scratch, two interleaved accumulators (fixed order)
   auto refresh = [&]() {
     float gb0[8][C], gb1[8][C];
     float acc[2][NR][C];
@@ -245,18 +350,19 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
         for (int q = 0; q < NR; ++q) {
           const float wl = bcast<RPAD>(w[q][l / RPAD], l % RPAD);
 #pragma unroll
-          for (int c = 0; c < C; ++c) acc[t & 1][q][c] = fmaf(-wl, cur[t][c], acc[t & 1][q][c]);
+          for (int c = 0; c < C; ++c) acc[t & 1][q][c] = fmaf(wl, cur[t][c], acc[t & 1][q][c]);
         }
       }
     }
 #pragma unroll
     for (int q = 0; q < NR; ++q)
 #pragma unroll
-      for (int c = 0; c < C; ++c) qv[q][c] = acc[0][q][c] + acc[1][q][c];
+      for (int c = 0; c < C; ++c) zv[q][c] = acc[0][q][c] + acc[1][q][c];
   };
-  // one Gauss-Seidel sweep over the columns; every q_k (also k < j) follows each update, so
-  // q stays current across sweeps and is refreshed from scratch only every kRefresh sweeps
-  // to bound the drift of the rank-one updates
+  // one Gauss-Seidel sweep over the columns; every z_k (also k < j) follows each update, so
+  // z stays current across sweeps and is refreshed from scratch only every kRefresh sweeps
+  // to bound the drift of the rank-one updates. The owner's change reaches its group through
+  // a DPP broadcast that the compiler folds into the multiply-adds.
   auto sweep = [&]() {
     float gb0[8][C], gb1[8][C];
     load_gblk(0, gb0);
@@ -272,37 +378,46 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
         const int o = j % RPAD;
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
-          const float wn = fmaxf(qv[q][cs], 0.f);
-          const float delta = bcast<RPAD>(wn - w[q][cs], o);
-          if (is_owner(o)) w[q][cs] = wn;
+          // every lane forms the change of its own column in slot cs; the owner's is used
+          if constexpr (RPAD == 16 && C == 2) {
+            if (cs == 0)
+              col_step16x2<0>(o, zv[q][0], zv[q][1], w[q][0], cur[t][0], cur[t][1], owner_mask(o));
+            else
+              col_step16x2<1>(o, zv[q][0], zv[q][1], w[q][1], cur[t][0], cur[t][1], owner_mask(o));
+          } else if constexpr (RPAD == 16 && C == 1) {
+            col_step16x1(o, zv[q][0], w[q][0], cur[t][0], owner_mask(o));
+          } else {
+            const float d = fmaxf(zv[q][cs], -w[q][cs]);
+            const float wn = w[q][cs] + d;
+            if (__builtin_amdgcn_inverse_ballot_w64(owner_mask(o))) w[q][cs] = wn;
+            const float delta = bcast<RPAD>(d, o);
 #pragma unroll
-          for (int c = 0; c < C; ++c) qv[q][c] = fmaf(-delta, cur[t][c], qv[q][c]);
+            for (int c = 0; c < C; ++c) zv[q][c] = fmaf(delta, cur[t][c], zv[q][c]);
+          }
         }
       }
     }
   };
 
   // ---- stopping rule (Sec. 4.1) on a wave of its own ----
-  // After sweep s each row wave posts its threads' shares of ||W_s - W_{s-1}||^2 in LDS.
-  // The rule wave sums them (fixed order), publishes the workgroup's share in global slot
-  // (s, wg), reads every workgroup's slots for up to four published sweeps per round trip,
-  // sums them in workgroup order (every workgroup gets the same bits) and posts its
-  // decisions. Row waves never wait for memory: they run up to `lag` sweeps past the last
-  // decision, keeping those iterates in an LDS ring, and restore the sweep the rule stops
-  // at. All waits are bounded by a wall-clock deadline.
-  const int S = a.max_sweeps;
-  const int L = a.lag;
-  const int R = L + 1;  // ring slots (iterates)
-  const int K = L + 2;  // share slots
-  float* s_ring = s_rows2 + RPW * r;                                       // [R][NR*C][kCT]
-  // [K][kCT], at the 16-byte aligned end of the float area (as the host sizes it)
-  double* s_sh = reinterpret_cast<double*>(
-      reinterpret_cast<char*>(smem) +
-      align_up((size_t(RB) * RMAX + 2 * size_t(RPW) * r + size_t(R) * NR * C * kCT) * sizeof(float),
-               16));
+  // After sweep s each row thread stores its share of ||W_s - W_{s-1}||^2 in LDS slot
+  // s mod K; a slot holds -1 while empty, so the shares themselves say when a sweep is
+  // complete and the row waves need no flag or fence. The rule wave sums a complete slot
+  // (fixed order), empties it, publishes the workgroup's share in global slot (s, wg),
+  // reads every workgroup's slots for several published sweeps per round trip, sums them
+  // in workgroup order (every workgroup gets the same bits) and posts its decisions. Row
+  // waves never wait for memory: they run up to `lag` sweeps past the last decision they
+  // have seen (read one sweep ahead), keeping those iterates in an LDS ring, and restore
+  // the sweep the rule stops at. All waits are bounded by a wall-clock deadline.
   uint64_t* const slots = a.slots;  // [sweep][wg]
   auto lds_ld = [](const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  auto sh_ld = [](const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  auto sh_st = [](double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   };
   auto lds_st = [](int* p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -323,86 +438,118 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   bool timed_out = false;
   if (wave == WPG) {
     // ---- the rule wave ----
-    int t_pub = 1, t_dec = 1;
-    double lim = 0.0;
-    const double tol2 = a.tol * a.tol;
-    while (true) {
-      if (t_dec >= S) {  // sweeps 1 .. S-1 decided without a stop
-        if (lane == 0) lds_st(&s_decided, S);
-        break;
-      }
-      if (wall_clock64() - t_start > a.timeout_ticks) {
-        if (lane == 0) lds_st(&s_stop, -1);
-        break;
-      }
-      // publish every sweep whose shares all row waves have posted
-      int posted = lds_ld(&s_posted[0]);
-#pragma unroll
-      for (int k = 1; k < WPG; ++k) posted = min(posted, lds_ld(&s_posted[k]));
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      for (; t_pub <= posted && t_pub < S; ++t_pub) {
-        const double* sh = s_sh + (t_pub % K) * kCT;
-        const double v = ((sh[lane] + sh[lane + 64]) + sh[lane + 128]) + sh[lane + 192];
-        const double D = wave_sum64(v);
-        if (lane == 0)
-          __hip_atomic_store(&slots[int64_t(t_pub - 1) * a.nwg + blockIdx.x],
-                             uint64_t(__double_as_longlong(D)), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-      }
-      // decide up to four published sweeps t_dec .. t_dec + n - 1 (< S) per round trip
-      const int n = min(4, min(t_pub, S) - t_dec);
-      if (n <= 0) {
-        __builtin_amdgcn_s_sleep(1);
-        continue;
-      }
-      uint64_t u[4][4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          u[m][k] = (m < n && lane + 64 * k < a.nwg)
-                        ? __hip_atomic_load(
-                              &slots[int64_t(t_dec - 1 + m) * a.nwg + lane + 64 * k],
-                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                        : 0;
-      int ndone = 0, stop = 0;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        if (m >= n) break;
-        bool missing = false;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) missing = missing || u[m][k] == kSentinel;
-        if (__any(missing)) break;  // a workgroup has not published this sweep yet
-        double v = 0.0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v += __longlong_as_double(int64_t(u[m][k]));
-        const double D = wave_sum64(v);
-        const int t = t_dec + m;
-        if (t == 1) lim = tol2 * D;
-        ++ndone;
-        if (D <= lim) {
-          stop = t;
-          break;
+    // KC slots per lane and sweep (a power of two covering nwg / 64), kDecide / KC sweeps
+    // per round trip
+    auto rule = [&](auto kc_tag) {
+      constexpr int KC = decltype(kc_tag)::value;
+      constexpr int M = kDecide / KC;
+      int t_pub = 1, t_dec = 1;
+      double lim = 0.0;
+      const double tol2 = a.tol * a.tol;
+      while (true) {
+        if (t_dec >= S) {  // sweeps 1 .. S-1 decided without a stop
+          if (lane == 0) lds_st(&s_decided, S);
+          return;
         }
-      }
-      t_dec += ndone;
-      if (stop) {
-        if (lane == 0) {
-          lds_st(&s_stop, stop);
-          lds_st(&s_decided, stop);
+        if (wall_clock64() - t_start > a.timeout_ticks) {
+          if (lane == 0) lds_st(&s_stop, -1);
+          return;
         }
-        break;
+        // publish every complete sweep (emptying its LDS slot)
+        for (; t_pub < S; ++t_pub) {
+          double* sh = s_sh + (t_pub % K) * kCT;
+          double v[WPG];
+          bool empty = false;
+#pragma unroll
+          for (int k = 0; k < WPG; ++k) {
+            v[k] = sh_ld(sh + lane + 64 * k);
+            empty = empty || v[k] < 0.0;
+          }
+          if (__any(empty)) break;
+          double x = v[0];
+#pragma unroll
+          for (int k = 1; k < WPG; ++k) x += v[k];
+          const double D = wave_sum64(x);
+#pragma unroll
+          for (int k = 0; k < WPG; ++k) sh_st(sh + lane + 64 * k, -1.0);
+          if (lane == 0)
+            __hip_atomic_store(&slots[int64_t(t_pub - 1) * a.nwg + blockIdx.x],
+                               uint64_t(__double_as_longlong(D)), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // decide up to M published sweeps t_dec .. t_dec + n - 1 (< S) per round trip
+        const int n = min(M, min(t_pub, S) - t_dec);
+        if (n <= 0) {
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        uint64_t u[M][KC];
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+#pragma unroll
+          for (int k = 0; k < KC; ++k)
+            u[m][k] = (m < n && lane + 64 * k < a.nwg)
+                          ? __hip_atomic_load(
+                                &slots[int64_t(t_dec - 1 + m) * a.nwg + lane + 64 * k],
+                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                          : 0;
+        // every loaded sweep's sum (independent, so they overlap), then the scan in order
+        double Dm[M];
+        bool miss[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          bool ms = false;
+          double v = 0.0;
+#pragma unroll
+          for (int k = 0; k < KC; ++k) {
+            ms = ms || u[m][k] == kSentinel;
+            v += __longlong_as_double(int64_t(u[m][k]));
+          }
+          miss[m] = __any(ms);
+          Dm[m] = wave_sum64(v);
+        }
+        int ndone = 0, stop = 0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          if (m >= n || miss[m]) break;  // a workgroup has not published this sweep yet
+          const int t = t_dec + m;
+          if (t == 1) lim = tol2 * Dm[m];
+          ++ndone;
+          if (Dm[m] <= lim) {
+            stop = t;
+            break;
+          }
+        }
+        t_dec += ndone;
+        // the emptied share slots are visible before the decision that lets them refill
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (stop) {
+          if (lane == 0) {
+            lds_st(&s_stop, stop);
+            lds_st(&s_decided, stop);
+          }
+          return;
+        }
+        if (lane == 0) lds_st(&s_decided, t_dec - 1);
+        if (ndone == 0) __builtin_amdgcn_s_sleep(2);
       }
-      if (lane == 0) lds_st(&s_decided, t_dec - 1);
-      if (ndone == 0) __builtin_amdgcn_s_sleep(2);
-    }
+    };
+    if (a.nwg <= 64)
+      rule(std::integral_constant<int, 1>());
+    else if (a.nwg <= 128)
+      rule(std::integral_constant<int, 2>());
+    else
+      rule(std::integral_constant<int, 4>());
   } else {
     // ---- the row waves ----
-    int stp = 0;
+    int dec = 0, stp = 0;  // the decision state as last read (at most one sweep old)
+    int sr = 0, sk = 0;    // s mod R, s mod K
     for (int s = 1; s <= S; ++s) {
-      stp = lds_ld(&s_stop);
-      while (stp == 0 && s - lds_ld(&s_decided) > L) {
+      sr = sr + 1 == R ? 0 : sr + 1;
+      sk = sk + 1 == K ? 0 : sk + 1;
+      while (stp == 0 && s - dec > L) {
         __builtin_amdgcn_s_sleep(1);
+        dec = lds_ld(&s_decided);
         stp = lds_ld(&s_stop);
       }
       if (stp != 0) break;
@@ -412,8 +559,13 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
 #pragma unroll
         for (int c = 0; c < C; ++c) prev[q][c] = s == 1 ? w0[q][c] : w[q][c];
       if ((s - 1) % kRefresh == 0) refresh();
+      // read the decision state now, use it before the next sweep (the empty asm keeps
+      // the wait for the reads, and their move to scalar registers, after the sweep)
+      int dec_next = lds_ld(&s_decided);
+      int stp_next = lds_ld(&s_stop);
       sweep();
-      ring_put(s % R);
+      asm volatile("" : "+v"(dec_next), "+v"(stp_next));
+      ring_put(sr);
       double d2 = 0.0;
 #pragma unroll
       for (int q = 0; q < NR; ++q)
@@ -422,9 +574,9 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
           const double df = double(w[q][c]) - double(prev[q][c]);
           d2 = fma(df, df, d2);
         }
-      s_sh[(s % K) * kCT + tid] = d2;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      if (lane == 0) lds_st(&s_posted[wave], s);
+      sh_st(s_sh + sk * kCT + tid, d2);
+      dec = dec_next;
+      stp = stp_next;
     }
     // the decision for the sweeps still open
     while (stp == 0 && lds_ld(&s_decided) < S) {
@@ -471,29 +623,32 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
     }
   __syncthreads();
   const int64_t rr = int64_t(r) * r;
-  if (a.gp_new) chunk_gram(s_rows, nrows, r, a.gp_new + blockIdx.x * rr);
+  // Gram partials of the new and extrapolated rows; the first also yields this thread's
+  // share of <G, W^T W> over the chunk's rows for the F-hat share
+  double gdot = 0.0;
+  if (a.gp_new || a.err_part)
+    gdot = gpre ? chunk_gram_tiles<TG, true>(s_rows, nrows, r,
+                                            a.gp_new ? a.gp_new + blockIdx.x * rr : nullptr,
+                                            a.G64, gm)
+                : chunk_gram(s_rows, nrows, r, a.gp_new ? a.gp_new + blockIdx.x * rr : nullptr,
+                             a.err_part ? a.G64 : nullptr);
   if (a.gp_hat && a.A_hat) chunk_gram(s_rows2, nrows, r, a.gp_hat + blockIdx.x * rr);
   if (a.err_part) {
-    // share of 2 <P, W> - <G, W^T W> = sum_rows sum_j w_j (2 p_j - (G w)_j)
-    double t = 0.0;
+    // share of 2 <P, W> - <G, W^T W> over the chunk's rows
+    double t = -gdot;
 #pragma unroll
     for (int q = 0; q < NR; ++q)
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const int j = c * RPAD + gl;
-        if (rok[q] && j < r) {
-          double gw = 0.0;
-          for (int l = 0; l < r; ++l)
-            gw += a.G64[int64_t(j) * r + l] * double(s_rows[lrow[q] * r + l]);
-          t += double(w[q][c]) * (2.0 * double(pv_keep[q][c]) - gw);
-        }
+        if (rok[q] && j < r) t = fma(2.0 * double(w[q][c]), double(pv_keep[q][c]), t);
       }
     const double ws = wave_sum64(t);
     if (lane == 0) s_part[wave] = ws;
     __syncthreads();
     if (tid == 0) {
       double e = 0.0;
-      for (int k = 0; k < WPG; ++k) e += s_part[k];
+      for (int k = 0; k <= WPG; ++k) e += s_part[k];
       a.err_part[blockIdx.x] = e;
     }
   }
