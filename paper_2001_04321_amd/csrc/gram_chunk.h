@@ -35,15 +35,19 @@ __device__ inline void gram_tile_m(const double* M, int r, int tile, double (&m)
   const int nt = (r + T - 1) / T;
   const int p0 = (tile / nt) * T;
   const int q0 = (tile - (tile / nt) * nt) * T;
+  // loads at clamped indices, then a select (no branch per load)
 #pragma unroll
   for (int a = 0; a < T; ++a)
 #pragma unroll
-    for (int b = 0; b < T; ++b)
-      m[a][b] = (M && tile < nt * nt && p0 + a < r && q0 + b < r) ? M[(p0 + a) * r + q0 + b]
-                                                                  : 0.0;
+    for (int b = 0; b < T; ++b) {
+      const double v = M ? M[min(p0 + a, r - 1) * r + min(q0 + b, r - 1)] : 0.0;
+      m[a][b] = (tile < nt * nt && p0 + a < r && q0 + b < r) ? v : 0.0;
+    }
 }
 
-template <int T, bool PRE>
+// U > 1: the row loop runs in blocks of U rows whose LDS loads are all in flight at once
+// (rows past nrows add exact zeros, so the sums are the same); U = 1: a plain loop.
+template <int T, bool PRE, int U = 1>
 __device__ inline double chunk_gram_tiles(const float* rows, int nrows, int r, double* out,
                                           const double* M, const double (&mfirst)[T][T]) {
   const int nt = (r + T - 1) / T;
@@ -65,18 +69,33 @@ __device__ inline double chunk_gram_tiles(const float* rows, int nrows, int r, d
     for (int a = 0; a < T; ++a)
 #pragma unroll
       for (int b = 0; b < T; ++b) acc[a][b] = 0.0;
-    for (int i = 0; i < nrows; ++i) {
-      const float* row = rows + i * r;
-      double xp[T], xq[T];
+    for (int i0 = 0; i0 < nrows; i0 += U) {
+      float vp[U][T], vq[U][T];
 #pragma unroll
-      for (int a = 0; a < T; ++a) {
-        xp[a] = p0 + a < r ? double(row[p0 + a]) : 0.0;
-        xq[a] = q0 + a < r ? double(row[q0 + a]) : 0.0;
+      for (int u = 0; u < U; ++u) {
+        // loads at clamped indices, then a select: conditional loads would become branches
+        // that wait for each load in turn
+        const float* row = rows + min(i0 + u, nrows - 1) * r;
+#pragma unroll
+        for (int a = 0; a < T; ++a) {
+          vp[u][a] = row[min(p0 + a, r - 1)];
+          vq[u][a] = row[min(q0 + a, r - 1)];
+        }
       }
 #pragma unroll
-      for (int a = 0; a < T; ++a)
+      for (int u = 0; u < U; ++u) {
+        const bool live = i0 + u < nrows;
+        double xp[T], xq[T];
 #pragma unroll
-        for (int b = 0; b < T; ++b) acc[a][b] = fma(xp[a], xq[b], acc[a][b]);
+        for (int a = 0; a < T; ++a) {
+          xp[a] = live && p0 + a < r ? double(vp[u][a]) : 0.0;
+          xq[a] = live && q0 + a < r ? double(vq[u][a]) : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < T; ++a)
+#pragma unroll
+          for (int b = 0; b < T; ++b) acc[a][b] = fma(xp[a], xq[b], acc[a][b]);
+      }
     }
 #pragma unroll
     for (int a = 0; a < T; ++a)

@@ -122,54 +122,77 @@ __device__ __forceinline__ float bcast(float x, int o) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), o));
 }
 
-// One column step for 16-lane row groups, in the step form described at the top:
-//   d = max(z_cs, -w); w <- owner ? w + d : w; z_c += bcast_o(d) * g_c for every slot c,
-// where z_cs is the slot that holds the column and bcast_o is lane o of each 16-lane row.
-// Written out because the compiler does not fold a DPP broadcast into a multiply-add and
-// canonicalises the max operands; here the broadcast is a DPP operand of v_fmac_f32 and
-// the critical path of a column is the max and one multiply-add. The two instructions
-// between the max and the first DPP read meet the two wait states a DPP read of a freshly
-// written VGPR needs. `owner` is the wave-wide mask of the lanes that hold column o.
-#define NTF_COL_CASE2(n)                                                                  \
-  case n:                                                                                 \
-    asm volatile("v_max_f32_e64 %[d], %[zc], -%[w]\n\t"                                            \
-        "v_add_f32_e32 %[t], %[w], %[d]\n\t"                                              \
-        "v_cndmask_b32_e64 %[w], %[w], %[t], %[m]\n\t"                                     \
-        "v_fmac_f32_dpp %[z0], %[d], %[g0] row_newbcast:" #n                              \
-        " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"                                    \
-        "v_fmac_f32_dpp %[z1], %[d], %[g1] row_newbcast:" #n                              \
-        " row_mask:0xf bank_mask:0xf bound_ctrl:1"                                         \
-        : [z0] "+v"(z0), [z1] "+v"(z1), [w] "+v"(w), [d] "=&v"(d), [t] "=&v"(t)           \
-        : [zc] "v"(CS == 0 ? z0 : z1), [g0] "v"(g0), [g1] "v"(g1), [m] "s"(owner));        \
-    break;
-#define NTF_COL_CASE1(n)                                                                  \
-  case n:                                                                                 \
-    asm volatile("v_max_f32_e64 %[d], %[z0], -%[w]\n\t"                                            \
-        "v_add_f32_e32 %[t], %[w], %[d]\n\t"                                              \
-        "v_cndmask_b32_e64 %[w], %[w], %[t], %[m]\n\t"                                     \
-        "v_fmac_f32_dpp %[z0], %[d], %[g0] row_newbcast:" #n                              \
-        " row_mask:0xf bank_mask:0xf bound_ctrl:1"                                         \
-        : [z0] "+v"(z0), [w] "+v"(w), [d] "=&v"(d), [t] "=&v"(t)                          \
-        : [g0] "v"(g0), [m] "s"(owner));                                                   \
-    break;
-#define NTF_COL_CASES(X) \
-  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
-
-template <int CS>
-__device__ __forceinline__ void col_step16x2(int o, float& z0, float& z1, float& w, float g0,
-                                             float g1, uint64_t owner) {
-  float d, t;
-  switch (o) { NTF_COL_CASES(NTF_COL_CASE2) }
+// Workgroup barrier that orders LDS accesses only: global stores issued before it may still
+// be in flight (__syncthreads would wait for them too).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-__device__ __forceinline__ void col_step16x1(int o, float& z0, float& w, float g0,
-                                             uint64_t owner) {
-  float d, t;
-  switch (o) { NTF_COL_CASES(NTF_COL_CASE1) }
+// Column steps for 16-lane row groups, in the step form described at the top:
+//   d = max(z_cs, -w); w += f_o d; z_c += bcast_o(d) g_c for each slot c,
+// where slot cs holds the column, bcast_o is lane o of each 16-lane row (a DPP operand of
+// v_fmac_f32) and f_o is 1 on the lanes that hold column o, else 0. Written out because the
+// compiler neither folds a DPP broadcast into a multiply-add nor keeps the owner select off
+// the scalar unit. With two slots (C = 2) the update of the slot that the next column does
+// not read is deferred into the next column's step, so a column is four VALU instructions
+// and the critical path is the max and one multiply-add: the deferred update and the w
+// update fill the two wait states a DPP read of the freshly written d needs. Per element
+// the updates keep the column order, so the results do not depend on the deferral.
+// the DPP broadcast of lane %[n] (or %[p]) of each 16-lane row, as a source modifier
+#define NTF_BC(x) " row_newbcast:%[" #x "] row_mask:0xf bank_mask:0xf bound_ctrl:1"
+// next column in the same slot: zc holds the column and the next one; zo takes the deferred
+// update of the previous column (owner lane P)
+template <int N, int P>
+__device__ __forceinline__ void col_same(float& zc, float& zo, float& w, float& d, float dp,
+                                         float gp, float f, float gc) {
+  asm volatile("v_max_f32_e64 %[d], %[zc], -%[w]\n\t"
+               "v_fmac_f32_dpp %[zo], %[dp], %[gp]" NTF_BC(p) "\n\t"
+               "v_fmac_f32_e32 %[w], %[d], %[f]\n\t"
+               "v_fmac_f32_dpp %[zc], %[d], %[gc]" NTF_BC(n)
+               : [zc] "+v"(zc), [zo] "+v"(zo), [w] "+v"(w), [d] "=&v"(d)
+               : [dp] "v"(dp), [gp] "v"(gp), [f] "v"(f), [gc] "v"(gc), [n] "i"(N), [p] "i"(P));
 }
-#undef NTF_COL_CASES
-#undef NTF_COL_CASE1
-#undef NTF_COL_CASE2
+// next column in the other slot: zm holds the column, zo the next one (and takes the
+// deferred update of the previous column first)
+template <int N, int P>
+__device__ __forceinline__ void col_switch(float zm, float& zo, float& w, float& d, float dp,
+                                           float gp, float f, float gc) {
+  asm volatile("v_max_f32_e64 %[d], %[zm], -%[w]\n\t"
+               "v_fmac_f32_dpp %[zo], %[dp], %[gp]" NTF_BC(p) "\n\t"
+               "v_fmac_f32_e32 %[w], %[d], %[f]\n\t"
+               "v_fmac_f32_dpp %[zo], %[d], %[gc]" NTF_BC(n)
+               : [zo] "+v"(zo), [w] "+v"(w), [d] "=&v"(d)
+               : [zm] "v"(zm), [dp] "v"(dp), [gp] "v"(gp), [f] "v"(f), [gc] "v"(gc),
+                 [n] "i"(N), [p] "i"(P));
+}
+// first column of a sweep (nothing deferred yet), and the one-slot step (C = 1): the w
+// update and an s_nop fill the two wait states
+template <int N>
+__device__ __forceinline__ void col_first(float& zc, float& w, float& d, float f, float gc) {
+  asm volatile("v_max_f32_e64 %[d], %[zc], -%[w]\n\t"
+               "v_fmac_f32_e32 %[w], %[d], %[f]\n\t"
+               "s_nop 0\n\t"
+               "v_fmac_f32_dpp %[zc], %[d], %[gc]" NTF_BC(n)
+               : [zc] "+v"(zc), [w] "+v"(w), [d] "=&v"(d)
+               : [f] "v"(f), [gc] "v"(gc), [n] "i"(N));
+}
+// the update deferred from the last column of a sweep
+template <int P>
+__device__ __forceinline__ void col_flush(float& zo, float dp, float gp) {
+  asm volatile("v_fmac_f32_dpp %[zo], %[dp], %[gp]" NTF_BC(p)
+               : [zo] "+v"(zo)
+               : [dp] "v"(dp), [gp] "v"(gp), [p] "i"(P));
+}
+#undef NTF_BC
+
+// f(std::integral_constant<int, J>()) for J = B .. E - 1, in order
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>());
+    static_for<B + 1, E>(f);
+  }
+}
 
 // RPAD lanes per row group (16: four groups per wave; 64: one per wave), C columns per
 // lane, NR rows per group processed in lockstep, NB blocks of 8 columns swept (8 NB >= r).
@@ -288,6 +311,7 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   const bool gpre = a.err_part != nullptr && ntg * ntg <= kThreads;  // one tile per thread
   double gm[TG][TG];
   gram_tile_m<TG>(gpre ? a.G64 : nullptr, r, tid, gm);
+  const double beta = a.A_hat ? *a.beta_src : 0.0;  // for the epilogue
 
   // local row q of this lane: wave * RPWV + q * GPW + gi
   float w[NR][C], pinv[NR][C], zv[NR][C];
@@ -319,6 +343,10 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
       for (int c = 0; c < C; ++c)
         gb[t][c] = GREG ? greg[GREG ? jb * 8 + t : 0][c] : s_g[(jb * 8 + t) * RMAX + c * RPAD + gl];
   };
+  // 1 on the lanes that hold column offset o of their group, else 0 (16-lane groups)
+  float flag[16];
+#pragma unroll
+  for (int o = 0; o < 16; ++o) flag[o] = gl == o ? 1.f : 0.f;
   // lanes owning column offset o of their group, as a wave-wide constant mask
   auto owner_mask = [&](int o) {
     uint64_t m = 0;
@@ -364,29 +392,55 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   // to bound the drift of the rank-one updates. The owner's change reaches its group through
   // a DPP broadcast that the compiler folds into the multiply-adds.
   auto sweep = [&]() {
-    float gb0[8][C], gb1[8][C];
-    load_gblk(0, gb0);
+    if constexpr (RPAD == 16 && GREG) {
+      // 16-lane groups, scaled G in registers: one inline-asm step per column
 #pragma unroll
-    for (int jb = 0; jb < NB; ++jb) {
-      float (&cur)[8][C] = (jb & 1) ? gb1 : gb0;
-      float (&nxt)[8][C] = (jb & 1) ? gb0 : gb1;
-      if (jb + 1 < NB) load_gblk(jb + 1, nxt);
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int j = jb * 8 + t;
-        const int cs = j / RPAD;
-        const int o = j % RPAD;
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-          // every lane forms the change of its own column in slot cs; the owner's is used
-          if constexpr (RPAD == 16 && C == 2) {
-            if (cs == 0)
-              col_step16x2<0>(o, zv[q][0], zv[q][1], w[q][0], cur[t][0], cur[t][1], owner_mask(o));
+      for (int q = 0; q < NR; ++q) {
+        if constexpr (C == 1) {
+          static_for<0, RB>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            float d;
+            col_first<j>(zv[q][0], w[q][0], d, flag[j], greg[j][0]);
+          });
+        } else {
+          // the change d of the previous column and its G entry for the slot whose update is
+          // deferred into the next column's step
+          float dp = 0.f, gp = 0.f;
+          static_for<0, RB>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            constexpr int cs = j / 16, o = j % 16, po = (o + 15) % 16;
+            constexpr int ns = (j + 1 < RB ? j + 1 : 0) / 16;  // slot of the column read next
+            float d;
+            if constexpr (j == 0)
+              col_first<o>(zv[q][0], w[q][0], d, flag[o], greg[j][0]);
+            else if constexpr (ns == cs)
+              col_same<o, po>(zv[q][cs], zv[q][1 - cs], w[q][cs], d, dp, gp, flag[o],
+                              greg[j][cs]);
             else
-              col_step16x2<1>(o, zv[q][0], zv[q][1], w[q][1], cur[t][0], cur[t][1], owner_mask(o));
-          } else if constexpr (RPAD == 16 && C == 1) {
-            col_step16x1(o, zv[q][0], w[q][0], cur[t][0], owner_mask(o));
-          } else {
+              col_switch<o, po>(zv[q][cs], zv[q][ns], w[q][cs], d, dp, gp, flag[o],
+                                greg[j][ns]);
+            dp = d;
+            gp = greg[j][1 - ns];  // the slot the next column does not read
+            if constexpr (j + 1 == RB) col_flush<o>(zv[q][1 - ns], dp, gp);
+          });
+        }
+      }
+    } else {
+      float gb0[8][C], gb1[8][C];
+      load_gblk(0, gb0);
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) {
+        float (&cur)[8][C] = (jb & 1) ? gb1 : gb0;
+        float (&nxt)[8][C] = (jb & 1) ? gb0 : gb1;
+        if (jb + 1 < NB) load_gblk(jb + 1, nxt);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int j = jb * 8 + t;
+          const int cs = j / RPAD;
+          const int o = j % RPAD;
+#pragma unroll
+          for (int q = 0; q < NR; ++q) {
+            // every lane forms the change of its own column in slot cs; the owner's is used
             const float d = fmaxf(zv[q][cs], -w[q][cs]);
             const float wn = w[q][cs] + d;
             if (__builtin_amdgcn_inverse_ballot_w64(owner_mask(o))) w[q][cs] = wn;
@@ -595,13 +649,12 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
                           __HIP_MEMORY_SCOPE_AGENT);
 
   // ---- epilogue: write W (and A_hat); stage rows for the Gram partials ----
-  const double beta = a.A_hat ? *a.beta_src : 0.0;
   float pv_keep[NR][C];  // P entries of this lane's columns, read before the rows are replaced
 #pragma unroll
   for (int q = 0; q < NR; ++q)
 #pragma unroll
     for (int c = 0; c < C; ++c) pv_keep[q][c] = 0.f;
-  __syncthreads();  // every lane has its P entries in registers (pinv) by now
+  lds_barrier();  // every lane has its P entries in registers (pinv) by now
 #pragma unroll
   for (int q = 0; q < NR; ++q)
 #pragma unroll
@@ -621,18 +674,21 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
         }
       }
     }
-  __syncthreads();
+  lds_barrier();  // the W and A_hat stores may still be in flight
   const int64_t rr = int64_t(r) * r;
   // Gram partials of the new and extrapolated rows; the first also yields this thread's
   // share of <G, W^T W> over the chunk's rows for the F-hat share
   double gdot = 0.0;
-  if (a.gp_new || a.err_part)
-    gdot = gpre ? chunk_gram_tiles<TG, true>(s_rows, nrows, r,
-                                            a.gp_new ? a.gp_new + blockIdx.x * rr : nullptr,
-                                            a.G64, gm)
-                : chunk_gram(s_rows, nrows, r, a.gp_new ? a.gp_new + blockIdx.x * rr : nullptr,
-                             a.err_part ? a.G64 : nullptr);
-  if (a.gp_hat && a.A_hat) chunk_gram(s_rows2, nrows, r, a.gp_hat + blockIdx.x * rr);
+  const double no_tile[TG][TG] = {};
+  if (a.gp_new || a.err_part) {
+    double* out = a.gp_new ? a.gp_new + blockIdx.x * rr : nullptr;
+    gdot = gpre ? chunk_gram_tiles<TG, true, 4>(s_rows, nrows, r, out, a.G64, gm)
+                : chunk_gram_tiles<TG, false, 4>(s_rows, nrows, r, out,
+                                                   a.err_part ? a.G64 : nullptr, no_tile);
+  }
+  if (a.gp_hat && a.A_hat)
+    chunk_gram_tiles<TG, false, 4>(s_rows2, nrows, r, a.gp_hat + blockIdx.x * rr, nullptr,
+                                      no_tile);
   if (a.err_part) {
     // share of 2 <P, W> - <G, W^T W> over the chunk's rows
     double t = -gdot;
