@@ -91,6 +91,8 @@ struct KArgs {
   int r;
   int vb;                      // v-block length (multiple of the chunk)
   int ub;                      // u values per X batch
+  int uk;                      // 1: the WK waves of a row tile take interleaved u values
+                               // (each covers every v chunk); 0: interleaved v chunks
 };
 
 // Tensor loads go through a buffer resource: an offset at or past the resource's size
@@ -331,7 +333,8 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
     const int vbi = int(w / k.U);
     const int64_t v0 = int64_t(vbi) * vb;
     const int nkc = int(ceil_div(std::min<int64_t>(vb, k.Iv - v0), KCH));  // chunks with data
-    const int ipu = (nkc + WK - 1) / WK;                                 // items per u (this wave)
+    // items per u (this wave): every chunk when the waves split u, else every WK-th chunk
+    const int ipu = k.uk ? nkc : (nkc + WK - 1) / WK;
     // ---- A_v block into LDS (zero beyond I_v and r) ----
     if (vbi != cur_vb) {
       __syncthreads();
@@ -391,14 +394,18 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
     }
     __syncthreads();
 
-    const int nitems = nu * ipu;
+    // this wave's u values: all of the batch (waves split v chunks) or every WK-th from wk
+    const int nuw = k.uk ? (nu > wk ? (nu - wk + WK - 1) / WK : 0) : nu;
+    const int nitems = nuw * ipu;
+    auto u_of = [&](int m) { return k.uk ? wk + m * WK : m; };   // batch index of u number m
+    auto kc_of = [&](int j) { return k.uk ? j : wk + j * WK; };  // chunk of item number j
     // prefetch cursor (pu, pj) and compute cursor (cu, cj) over (u, chunk) items; items past
     // the end load zeros (see load_item), so the loop body has no data-dependent branches
     int pu = 0, pj = 0, pit = 0;
     auto prefetch = [&](uint4 (&reg)[4]) {
-      const int kc = wk + pj * WK;
+      const int kc = kc_of(pj);
       const bool valid = pit < nitems && kc < nkc;
-      const uint32_t uq = uint32_t(u0 + (pit < nitems ? pu : 0));
+      const uint32_t uq = uint32_t(u0 + (pit < nitems ? u_of(pu) : 0));
       load_item(reg, t_base<LAST>(k, uq), v0 + int64_t(kc) * KCH, valid);
       ++pit;
       if (++pj == ipu) {
@@ -420,12 +427,12 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
 #pragma unroll
               for (int e = 0; e < 16; ++e) y[nt][e] = 0.f;
           }
-          const int kc = wk + cj * WK;
+          const int kc = kc_of(cj);
           if (kc < nkc) compute_item(buf[d], kc);
           if (cj == ipu - 1) {
             if (k.ystore) {
-              // Y[i][u][p] (the wave covers every v chunk of u: WK == 1)
-              const int64_t uu = u0 + cu;
+              // Y[i][u][p] (the wave covers every v chunk of u: WK == 1 or waves split u)
+              const int64_t uu = u0 + u_of(cu);
 #pragma unroll
               for (int nt = 0; nt < NT; ++nt) {
                 const int p = nt * 32 + col;
@@ -438,7 +445,7 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
                 }
               }
             } else {
-              const float* xs = s_x + cu * RP;
+              const float* xs = s_x + u_of(cu) * RP;
 #pragma unroll
               for (int nt = 0; nt < NT; ++nt) {
                 const float x = xs[nt * 32 + col];
@@ -502,8 +509,17 @@ __global__ __launch_bounds__(256) void mttkrp_reduce_kernel(const float* __restr
   for (int64_t e0 = int64_t(blockIdx.x) * 64; e0 < n; e0 += int64_t(gridDim.x) * 64) {
     const int64_t e = e0 + o;
     double acc = 0.0;
-    if (e < n)
-      for (int64_t q = g; q < splits; q += 4) acc += double(part[q * n + e]);
+    if (e < n) {
+      // splits g, g + 4, ... in order; eight loads in flight (clamped, no branch per load)
+      for (int64_t q0 = g; q0 < splits; q0 += 32) {
+        float v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = part[std::min<int64_t>(q0 + 4 * t, splits - 1) * n + e];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (q0 + 4 * t < splits) acc += double(v[t]);
+      }
+    }
     s[g][o] = acc;
     __syncthreads();
     if (g == 0 && e < n) P[e] = float(((s[0][o] + s[1][o]) + s[2][o]) + s[3][o]);
@@ -677,7 +693,9 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus, bool s
       pl.wm = wm;
     }
   }
-  if (store_y) pl.wm = 4;  // one wave covers all v chunks of a row tile: Y rows are whole
+  // Y rows are whole only when one wave covers every v chunk of its u: the WK waves of a
+  // row tile take interleaved u values instead of interleaved v chunks
+  pl.uk = store_y;
   pl.wk = 4 / pl.wm;
   // v-block: all of I_v when its A_v block fits 64 KB of LDS
   const int kch = bf16 ? 64 : 32;
@@ -746,6 +764,7 @@ hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& 
   k.r = pl.r;
   k.vb = pl.vb;
   k.ub = pl.ub;
+  k.uk = pl.uk ? 1 : 0;
   const bool bf16 = pl.dtype == NTF_BF16;
   const bool vec = vec_loads(pl);
   k.tbytes = pl.v.L * pl.v.I * pl.v.R * (bf16 ? 2 : 4);
