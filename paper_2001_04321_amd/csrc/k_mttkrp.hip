@@ -134,8 +134,14 @@ __device__ __forceinline__ int64_t t_base(const KArgs& k, uint32_t u) {
   return int64_t(a) * k.a_stride + bhi * k.Iv;
 }
 
+// Workgroup barrier that orders LDS accesses only: tensor loads issued before it stay in
+// flight (__syncthreads would wait for them too).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 template <bool BF16, int NT, int WM, int WK, bool LAST, bool VEC>
-__global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
+__global__ __launch_bounds__(kThreads, 2) void mttkrp_kernel(KArgs k) {
   constexpr int RP = 32 * NT;
   constexpr int KCH = BF16 ? 64 : 32;
   constexpr int MT = 32 * WM;
@@ -335,65 +341,11 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
     const int nkc = int(ceil_div(std::min<int64_t>(vb, k.Iv - v0), KCH));  // chunks with data
     // items per u (this wave): every chunk when the waves split u, else every WK-th chunk
     const int ipu = k.uk ? nkc : (nkc + WK - 1) / WK;
-    // ---- A_v block into LDS (zero beyond I_v and r) ----
-    if (vbi != cur_vb) {
-      __syncthreads();
-      if (k.av_vec) {
-        // r == RP and A_v 16-byte aligned: the block is contiguous; 16-byte loads, eight
-        // in flight per thread
-        const int nv = int(std::min<int64_t>(vb, k.Iv - v0));
-        const int n4 = vb * RP / 4;
-        const float4* src = reinterpret_cast<const float4*>(k.Av + v0 * RP);
-        for (int b0 = tid; b0 < n4; b0 += kThreads * 8) {
-          float4 t[8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int e4 = b0 + j * kThreads;
-            t[j] = (e4 < n4 && (e4 * 4) / RP < nv) ? src[e4] : make_float4(0.f, 0.f, 0.f, 0.f);
-          }
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int e4 = b0 + j * kThreads;
-            if (e4 >= n4) continue;
-            const int kk = (e4 * 4) / RP;
-            const int p = e4 * 4 - kk * RP;
-            if (BF16) {
-              uint16_t* d = reinterpret_cast<uint16_t*>(s_av);
-              d[(p + 0) * ldb + kk] = f2bf(t[j].x);
-              d[(p + 1) * ldb + kk] = f2bf(t[j].y);
-              d[(p + 2) * ldb + kk] = f2bf(t[j].z);
-              d[(p + 3) * ldb + kk] = f2bf(t[j].w);
-            } else {
-              *reinterpret_cast<float4*>(&reinterpret_cast<float*>(s_av)[kk * RP + p]) = t[j];
-            }
-          }
-        }
-      } else {
-        for (int e = tid; e < vb * RP; e += kThreads) {
-          const int kk = e / RP;
-          const int p = e - kk * RP;
-          const int64_t v = v0 + kk;
-          const float val = (p < k.r && v < k.Iv) ? k.Av[v * k.r + p] : 0.f;
-          if (BF16)
-            reinterpret_cast<uint16_t*>(s_av)[p * ldb + kk] = f2bf(val);
-          else
-            reinterpret_cast<float*>(s_av)[kk * RP + p] = val;
-        }
-      }
-      cur_vb = vbi;
-    }
-    // ---- a batch of u values within this v-block ----
+    // ---- a batch of u values within this v-block; the first items' tensor loads go out
+    // before the A_v block and X are staged, so their latency overlaps the staging ----
     const int64_t u0 = w - int64_t(vbi) * k.U;
     const int64_t w_stop = std::min<int64_t>(w_end, int64_t(vbi + 1) * k.U);
     const int nu = int(std::min<int64_t>(k.ub, w_stop - w));
-    __syncthreads();
-    for (int e = tid; e < nu * RP; e += kThreads) {
-      const int uu = e / RP;
-      const int p = e - uu * RP;
-      s_x[e] = p < k.r ? x_value(k, uint32_t(u0 + uu), p) : 0.f;
-    }
-    __syncthreads();
-
     // this wave's u values: all of the batch (waves split v chunks) or every WK-th from wk
     const int nuw = k.uk ? (nu > wk ? (nu - wk + WK - 1) / WK : 0) : nu;
     const int nitems = nuw * ipu;
@@ -415,6 +367,84 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kernel(KArgs k) {
     };
 #pragma unroll
     for (int d = 0; d < PD - 1; ++d) prefetch(buf[d]);
+
+    // ---- A_v block into LDS (zero beyond I_v and r) ----
+    if (vbi != cur_vb) {
+      lds_barrier();
+      const int nv = int(std::min<int64_t>(vb, k.Iv - v0));
+      if (BF16 && k.av_vec) {
+        // r == RP and A_v 16-byte aligned: the block is contiguous; 16-byte loads, eight
+        // in flight per thread, converted and written transposed (s_av[p][kk])
+        const int n4 = vb * RP / 4;
+        const float4* src = reinterpret_cast<const float4*>(k.Av + v0 * RP);
+        uint16_t* d = reinterpret_cast<uint16_t*>(s_av);
+        for (int b0 = tid; b0 < n4; b0 += kThreads * 8) {
+          float4 t[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int e4 = b0 + j * kThreads;
+            t[j] = (e4 < n4 && (e4 * 4) / RP < nv) ? src[e4] : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int e4 = b0 + j * kThreads;
+            if (e4 >= n4) continue;
+            const int kk = (e4 * 4) / RP;
+            const int p = e4 * 4 - kk * RP;
+            d[(p + 0) * ldb + kk] = f2bf(t[j].x);
+            d[(p + 1) * ldb + kk] = f2bf(t[j].y);
+            d[(p + 2) * ldb + kk] = f2bf(t[j].z);
+            d[(p + 3) * ldb + kk] = f2bf(t[j].w);
+          }
+        }
+      } else if (BF16) {
+        for (int e = tid; e < vb * RP; e += kThreads) {
+          const int kk = e / RP;
+          const int p = e - kk * RP;
+          const int64_t v = v0 + kk;
+          reinterpret_cast<uint16_t*>(s_av)[p * ldb + kk] =
+              f2bf((p < k.r && v < k.Iv) ? k.Av[v * k.r + p] : 0.f);
+        }
+      } else if (k.av_vec) {
+        // r == RP and A_v 16-byte aligned: the block is contiguous; 16-byte loads, eight
+        // in flight per thread
+        const int n4 = vb * RP / 4;
+        const float4* src = reinterpret_cast<const float4*>(k.Av + v0 * RP);
+        for (int b0 = tid; b0 < n4; b0 += kThreads * 8) {
+          float4 t[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int e4 = b0 + j * kThreads;
+            t[j] = (e4 < n4 && (e4 * 4) / RP < nv) ? src[e4] : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int e4 = b0 + j * kThreads;
+            if (e4 >= n4) continue;
+            const int kk = (e4 * 4) / RP;
+            const int p = e4 * 4 - kk * RP;
+            *reinterpret_cast<float4*>(&reinterpret_cast<float*>(s_av)[kk * RP + p]) = t[j];
+          }
+        }
+      } else {
+        for (int e = tid; e < vb * RP; e += kThreads) {
+          const int kk = e / RP;
+          const int p = e - kk * RP;
+          const int64_t v = v0 + kk;
+          reinterpret_cast<float*>(s_av)[kk * RP + p] =
+              (p < k.r && v < k.Iv) ? k.Av[v * k.r + p] : 0.f;
+        }
+      }
+      cur_vb = vbi;
+    }
+    lds_barrier();
+    for (int e = tid; e < nu * RP; e += kThreads) {
+      const int uu = e / RP;
+      const int p = e - uu * RP;
+      s_x[e] = p < k.r ? x_value(k, uint32_t(u0 + uu), p) : 0.f;
+    }
+    lds_barrier();
+
     int cu = 0, cj = 0;
     for (int base = 0; base < nitems; base += PD) {
 #pragma unroll
