@@ -109,6 +109,39 @@ __device__ inline double chunk_gram_tiles(const float* rows, int nrows, int r, d
   return dot;
 }
 
+// G = Hadamard product over the job's factors of their Grams (each the sum of its chunk
+// partials in chunk order), as float32 and/or float64, and the reset of `nslots` inner
+// solver wait slots to the sentinel; this block is number blk of nblk doing the work.
+__device__ inline void hadamard_work(const HadamardJob& job, int r, float* G32, double* G64,
+                                     double* slots, int64_t nslots, int64_t blk, int64_t nblk) {
+  const int64_t tid = blk * blockDim.x + threadIdx.x;
+  const int rr = r * r;
+  for (int64_t e64 = tid; e64 < rr; e64 += nblk * blockDim.x) {
+    const int e = int(e64);
+    double g = 1.0;
+    for (int f = 0; f < job.nfac; ++f) {
+      // chunk order; loads in batches of 8 so that they are in flight together
+      double s = 0.0;
+      const double* part = job.part[f];
+      const int64_t nc = job.nchunks[f];
+      int64_t c = 0;
+      for (; c + 8 <= nc; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = part[(c + t) * rr + e];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s += v[t];
+      }
+      for (; c < nc; ++c) s += part[c * rr + e];
+      g *= s;
+    }
+    if (G32) G32[e] = float(g);
+    if (G64) G64[e] = g;
+  }
+  for (int64_t e = tid; e < nslots; e += nblk * blockDim.x)
+    slots[e] = __longlong_as_double(-1ll);
+}
+
 // tile edge used for rank r
 __host__ __device__ constexpr int gram_tile_edge(int r) { return r <= 32 ? 2 : 4; }
 

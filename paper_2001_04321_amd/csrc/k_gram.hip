@@ -30,32 +30,7 @@ __global__ __launch_bounds__(256) void gram_partials_kernel(GramJob job, int r) 
 __global__ __launch_bounds__(256) void hadamard_kernel(HadamardJob job, int r, float* G32,
                                                        double* G64, double* slots,
                                                        int64_t nslots) {
-  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int rr = r * r;
-  if (tid < rr) {
-    const int e = int(tid);
-    double g = 1.0;
-    for (int f = 0; f < job.nfac; ++f) {
-      // chunk order; loads in batches of 8 so that they are in flight together
-      double s = 0.0;
-      const double* part = job.part[f];
-      const int64_t nc = job.nchunks[f];
-      int64_t c = 0;
-      for (; c + 8 <= nc; c += 8) {
-        double v[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) v[t] = part[(c + t) * rr + e];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) s += v[t];
-      }
-      for (; c < nc; ++c) s += part[c * rr + e];
-      g *= s;
-    }
-    if (G32) G32[e] = float(g);
-    if (G64) G64[e] = g;
-  }
-  for (int64_t e = tid; e < nslots; e += int64_t(gridDim.x) * blockDim.x)
-    slots[e] = __longlong_as_double(-1ll);
+  hadamard_work(job, r, G32, G64, slots, nslots, blockIdx.x, gridDim.x);
 }
 
 }  // namespace

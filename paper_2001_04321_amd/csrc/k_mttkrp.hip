@@ -27,6 +27,7 @@
 // waves share a row tile and take interleaved 64-element (bf16) / 32-element (f32) chunks
 // of v; their accumulators are summed once at the end. Splits write partial tiles that
 // a second pass sums in a fixed order: the result is deterministic.
+#include "gram_chunk.h"
 #include "ntf_internal.h"
 
 namespace ntf {
@@ -93,6 +94,8 @@ struct KArgs {
   int ub;                      // u values per X batch
   int uk;                      // 1: the WK waves of a row tile take interleaved u values
                                // (each covers every v chunk); 0: interleaved v chunks
+  int nh;                      // leading workgroups that compute a Hadamard product instead
+  HadamardLaunch had;
 };
 
 // Tensor loads go through a buffer resource: an offset at or past the resource's size
@@ -142,6 +145,11 @@ __device__ __forceinline__ void lds_barrier() {
 
 template <bool BF16, int NT, int WM, int WK, bool LAST, bool VEC>
 __global__ __launch_bounds__(kThreads, 2) void mttkrp_kernel(KArgs k) {
+  if (int(blockIdx.x) < k.nh) {  // the Hadamard product of the next A-HALS launch
+    hadamard_work(k.had.job, k.had.r, k.had.G32, k.had.G64, k.had.slots, k.had.nslots,
+                  blockIdx.x, k.nh);
+    return;
+  }
   constexpr int RP = 32 * NT;
   constexpr int KCH = BF16 ? 64 : 32;
   constexpr int MT = 32 * WM;
@@ -166,9 +174,9 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_kernel(KArgs k) {
   // XCD-aware numbering: workgroups are dealt to the 8 XCDs round-robin by launch index;
   // logical workgroups are renumbered so that consecutive row tiles of a split (which
   // share cache lines at their edges) run on the same XCD and hit the same L2
-  uint32_t lw = blockIdx.x;
+  uint32_t lw = blockIdx.x - uint32_t(k.nh);  // (nh is a multiple of 8)
   {
-    const uint32_t per = gridDim.x / 8;
+    const uint32_t per = (gridDim.x - uint32_t(k.nh)) / 8;
     if (lw < per * 8) lw = (lw % 8) * per + lw / 8;
   }
   const int64_t tile = lw % uint32_t(k.mtiles);
@@ -598,13 +606,20 @@ __global__ __launch_bounds__(256) void fold_u_kernel(const float* __restrict__ Y
 }
 
 // fold_i: workgroup (u tile of 256 / r' outputs, i range); partial[split][u][p].
+// With a Hadamard job, the first row of blocks (blockIdx.y == 0) computes it instead.
 __global__ __launch_bounds__(256) void fold_i_kernel(const float* __restrict__ Y,
                                                      const float* __restrict__ X, int64_t I,
                                                      int64_t U, int r, int64_t per,
-                                                     float* __restrict__ part) {
+                                                     float* __restrict__ part, int has_had,
+                                                     HadamardLaunch had) {
+  if (has_had && blockIdx.y == 0) {
+    hadamard_work(had.job, had.r, had.G32, had.G64, had.slots, had.nslots, blockIdx.x,
+                  gridDim.x);
+    return;
+  }
   const int64_t n = U * r;
   const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;  // (u, p) flattened
-  const int64_t split = blockIdx.y;
+  const int64_t split = blockIdx.y - has_had;
   const int64_t i_lo = split * per, i_hi = std::min<int64_t>(I, i_lo + per);
   if (e >= n) return;
   const int p = int(e % r);
@@ -765,8 +780,13 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus, bool s
 }
 
 hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& A, float* P,
-                         float* partials, bool reduce, hipStream_t s, float* ystore) {
+                         float* partials, bool reduce, hipStream_t s, float* ystore,
+                         const HadamardLaunch* had) {
   KArgs k{};
+  if (had) {
+    k.nh = kHadamardBlocks;
+    k.had = *had;
+  }
   k.ystore = pl.store_y ? ystore : nullptr;
   k.T = T;
   const int N = pl.v.order;
@@ -809,7 +829,7 @@ hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& 
     if (e != hipSuccess) return e;
     done = true;
   }
-  dim3 grid(unsigned(pl.mtiles * pl.splits));
+  dim3 grid(unsigned(pl.mtiles * pl.splits + k.nh));
   hipLaunchKernelGGL(fn, grid, dim3(kThreads), pl.lds, s, k);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -837,12 +857,16 @@ int64_t fold_i_splits(int64_t I, int64_t U, int r) {
 }
 
 hipError_t launch_fold_i(const float* Y, const float* X, int64_t I, int64_t U, int r,
-                         float* partials, float* P, hipStream_t s) {
+                         float* partials, float* P, hipStream_t s, const HadamardLaunch* had) {
   const int64_t splits = fold_i_splits(I, U, r);
   const int64_t per = ceil_div(I, splits);
   const int64_t n = U * r;
-  hipLaunchKernelGGL(fold_i_kernel, dim3(unsigned(ceil_div(n, 256)), unsigned(splits)),
-                     dim3(256), 0, s, Y, X, I, U, r, per, partials);
+  const int has_had = had ? 1 : 0;
+  HadamardLaunch h{};
+  if (had) h = *had;
+  hipLaunchKernelGGL(fold_i_kernel,
+                     dim3(unsigned(ceil_div(n, 256)), unsigned(splits + has_had)), dim3(256),
+                     0, s, Y, X, I, U, r, per, partials, has_had, h);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 64), 4096)));

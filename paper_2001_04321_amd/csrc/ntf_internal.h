@@ -153,8 +153,10 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus,
 // them into P in a fixed order, otherwise the caller (A-HALS) consumes the partials.
 // A plan made with store_y (case A only) writes Y[i][u][:] = T_u A_v (I x U x r floats)
 // to `ystore` instead, and nothing to P.
+struct HadamardLaunch;
 hipError_t launch_mttkrp(const MttkrpPlan& plan, const void* T, const FactorPtrs& A, float* P,
-                         float* partials, bool reduce, hipStream_t s, float* ystore = nullptr);
+                         float* partials, bool reduce, hipStream_t s, float* ystore = nullptr,
+                         const HadamardLaunch* had = nullptr);
 // 3-way tensors, from a stored Y (mode 0 plan with store_y, u = mode 1):
 //   P[i, p] = sum_u X[u, p] Y[i, u, p]            (mode-0 MTTKRP, X = A_1)
 //   P[u, p] = sum_i X[i, p] Y[i, u, p]            (mode-1 MTTKRP, X = A_0; `partials`
@@ -163,7 +165,8 @@ hipError_t launch_fold_u(const float* Y, const float* X, int64_t I, int64_t U, i
                          hipStream_t s);
 int64_t fold_i_splits(int64_t I, int64_t U, int r);
 hipError_t launch_fold_i(const float* Y, const float* X, int64_t I, int64_t U, int r,
-                         float* partials, float* P, hipStream_t s);
+                         float* partials, float* P, hipStream_t s,
+                         const HadamardLaunch* had = nullptr);
 
 // Gram partials: for factor f (rows[f] x r), out[f] gets gram_chunks(rows, r) partial
 // r x r float64 Grams (row chunks of the A-HALS workgroup size, so the A-HALS epilogue
@@ -186,6 +189,17 @@ struct HadamardJob {
 };
 hipError_t launch_hadamard(const HadamardJob& job, int r, float* G32, double* G64,
                            double* slots, int64_t nslots, hipStream_t s);
+// The same work done by kHadamardBlocks leading workgroups of another launch (the MTTKRP
+// or fold that precedes the A-HALS launch needing G), which saves a launch per block.
+struct HadamardLaunch {
+  HadamardJob job;
+  int r;
+  float* G32;
+  double* G64;
+  double* slots;
+  int64_t nslots;
+};
+constexpr int kHadamardBlocks = 8;  // a multiple of 8 keeps the XCD dealing of the rest
 
 // A-HALS on one block. `slots` holds hals_slot_count(rows, r, max_sweeps) doubles that
 // are set to the sentinel (launch_fill_sentinel or launch_hadamard) before the call.

@@ -140,22 +140,23 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
       hj.nchunks[hj.nfac] = gram_chunks(T.dims[l], r);
       hj.nfac++;
     }
-    const int64_t nslots = hals_slot_count(I, r, p.max_inner);
-    if ((e = launch_hadamard(hj, r, b.G32, b.G64, b.slots, nslots, s)) != hipSuccess) return e;
-    // split partials are summed by the wide reduction kernel: the A-HALS grid is too
-    // narrow (one workgroup per row chunk) to stream them quickly
+    // G^(n) (and the reset of the A-HALS wait slots) is computed by leading workgroups of
+    // the tensor pass or fold that precedes the A-HALS launch, not by a launch of its own.
+    // Split partials are summed by the wide reduction kernel: the A-HALS grid is too
+    // narrow (one workgroup per row chunk) to stream them quickly.
+    HadamardLaunch hl{hj, r, b.G32, b.G64, b.slots, hals_slot_count(I, r, p.max_inner)};
     if (b.Y && n == 0) {
       if ((e = launch_mttkrp(*plan_y, T.data, factors_for(0, N, A, b), b.P, b.mt_part, true, s,
-                             b.Y)) != hipSuccess)
+                             b.Y, &hl)) != hipSuccess)
         return e;
       if ((e = launch_fold_u(b.Y, A[1], T.dims[0], T.dims[1], r, b.P, s)) != hipSuccess)
         return e;
     } else if (b.Y && n == 1) {
-      if ((e = launch_fold_i(b.Y, b.A_hat[0], T.dims[0], T.dims[1], r, b.mt_part, b.P, s)) !=
-          hipSuccess)
+      if ((e = launch_fold_i(b.Y, b.A_hat[0], T.dims[0], T.dims[1], r, b.mt_part, b.P, s,
+                             &hl)) != hipSuccess)
         return e;
     } else if ((e = launch_mttkrp(plans[n], T.data, factors_for(n, N, A, b), b.P, b.mt_part,
-                                  true, s)) != hipSuccess) {
+                                  true, s, nullptr, &hl)) != hipSuccess) {
       return e;
     }
     HalsArgs ha{};
