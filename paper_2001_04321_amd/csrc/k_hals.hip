@@ -183,6 +183,21 @@ __device__ __forceinline__ void col_flush(float& zo, float dp, float gp) {
                : [zo] "+v"(zo)
                : [dp] "v"(dp), [gp] "v"(gp), [p] "i"(P));
 }
+// refresh term of column N: a_c += bcast_N(w) g_c (w is not written during the refresh, so
+// its DPP reads need no wait states)
+template <int N>
+__device__ __forceinline__ void acc_bcast2(float& a0, float& a1, float w, float g0, float g1) {
+  asm volatile("v_fmac_f32_dpp %[a0], %[w], %[g0]" NTF_BC(n) "\n\t"
+               "v_fmac_f32_dpp %[a1], %[w], %[g1]" NTF_BC(n)
+               : [a0] "+v"(a0), [a1] "+v"(a1)
+               : [w] "v"(w), [g0] "v"(g0), [g1] "v"(g1), [n] "i"(N));
+}
+template <int N>
+__device__ __forceinline__ void acc_bcast1(float& a0, float w, float g0) {
+  asm volatile("v_fmac_f32_dpp %[a0], %[w], %[g0]" NTF_BC(n)
+               : [a0] "+v"(a0)
+               : [w] "v"(w), [g0] "v"(g0), [n] "i"(N));
+}
 #undef NTF_BC
 
 // f(std::integral_constant<int, J>()) for J = B .. E - 1, in order
@@ -356,6 +371,27 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   };
   // z = P / diag(G) + W S from scratch, two interleaved accumulators (fixed order)
   auto refresh = [&]() {
+    if constexpr (RPAD == 16 && GREG) {
+      // z = P / diag(G) + W S, one broadcast multiply-add per column and slot (in column
+      // order)
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        float a[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) a[c] = pinv[q][c];
+        asm volatile("s_nop 1");  // w may have been written just before (DPP read below)
+        static_for<0, RB>([&](auto lc) {
+          constexpr int l = decltype(lc)::value;
+          if constexpr (C == 2)
+            acc_bcast2<l % 16>(a[0], a[1], w[q][l / 16], greg[l][0], greg[l][1]);
+          else
+            acc_bcast1<l % 16>(a[0], w[q][0], greg[l][0]);
+        });
+#pragma unroll
+        for (int c = 0; c < C; ++c) zv[q][c] = a[c];
+      }
+      return;
+    }
     float gb0[8][C], gb1[8][C];
     float acc[2][NR][C];
 #pragma unroll
