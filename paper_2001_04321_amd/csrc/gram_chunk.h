@@ -142,6 +142,81 @@ __device__ inline void hadamard_work(const HadamardJob& job, int r, float* G32, 
     slots[e] = __longlong_as_double(-1ll);
 }
 
+// Both chunk Grams of two row blocks of the same shape in one pass (the A-HALS epilogue:
+// new and extrapolated rows): each entry is summed exactly as chunk_gram_tiles sums it, so
+// the partials are bit-identical to two separate calls. Returns the share of
+// sum M .* out_a (as chunk_gram_tiles does for rows_a).
+template <int T, bool PRE, int U>
+__device__ inline double chunk_gram2_tiles(const float* rows_a, const float* rows_b,
+                                           int nrows, int r, double* out_a, double* out_b,
+                                           const double* M, const double (&mfirst)[T][T]) {
+  const int nt = (r + T - 1) / T;
+  double dot = 0.0;
+  for (int tile = threadIdx.x; tile < nt * nt; tile += blockDim.x) {
+    const int p0 = (tile / nt) * T;
+    const int q0 = (tile - (tile / nt) * nt) * T;
+    double m[T][T];
+    if (PRE && tile == int(threadIdx.x)) {
+#pragma unroll
+      for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int b = 0; b < T; ++b) m[a][b] = mfirst[a][b];
+    } else {
+      gram_tile_m<T>(M, r, tile, m);
+    }
+    double acc[2][T][T];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int b = 0; b < T; ++b) acc[h][a][b] = 0.0;
+    for (int i0 = 0; i0 < nrows; i0 += U) {
+      float vp[2][U][T], vq[2][U][T];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          // loads at clamped indices, then a select (no branch per load)
+          const float* row = (h ? rows_b : rows_a) + min(i0 + u, nrows - 1) * r;
+#pragma unroll
+          for (int a = 0; a < T; ++a) {
+            vp[h][u][a] = row[min(p0 + a, r - 1)];
+            vq[h][u][a] = row[min(q0 + a, r - 1)];
+          }
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool live = i0 + u < nrows;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          double xp[T], xq[T];
+#pragma unroll
+          for (int a = 0; a < T; ++a) {
+            xp[a] = live && p0 + a < r ? double(vp[h][u][a]) : 0.0;
+            xq[a] = live && q0 + a < r ? double(vq[h][u][a]) : 0.0;
+          }
+#pragma unroll
+          for (int a = 0; a < T; ++a)
+#pragma unroll
+            for (int b = 0; b < T; ++b) acc[h][a][b] = fma(xp[a], xq[b], acc[h][a][b]);
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+      for (int b = 0; b < T; ++b)
+        if (p0 + a < r && q0 + b < r) {
+          const int e = (p0 + a) * r + q0 + b;
+          if (out_a) out_a[e] = acc[0][a][b];
+          if (out_b) out_b[e] = acc[1][a][b];
+          dot = fma(m[a][b], acc[0][a][b], dot);
+        }
+  }
+  return dot;
+}
+
 // tile edge used for rank r
 __host__ __device__ constexpr int gram_tile_edge(int r) { return r <= 32 ? 2 : 4; }
 

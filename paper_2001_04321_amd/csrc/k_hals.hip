@@ -716,15 +716,27 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   // share of <G, W^T W> over the chunk's rows for the F-hat share
   double gdot = 0.0;
   const double no_tile[TG][TG] = {};
-  if (a.gp_new || a.err_part) {
-    double* out = a.gp_new ? a.gp_new + blockIdx.x * rr : nullptr;
-    gdot = gpre ? chunk_gram_tiles<TG, true, 4>(s_rows, nrows, r, out, a.G64, gm)
-                : chunk_gram_tiles<TG, false, 4>(s_rows, nrows, r, out,
-                                                   a.err_part ? a.G64 : nullptr, no_tile);
+  double* out_new = a.gp_new ? a.gp_new + blockIdx.x * rr : nullptr;
+  double* out_hat = (a.gp_hat && a.A_hat) ? a.gp_hat + blockIdx.x * rr : nullptr;
+  const double* gmat = a.err_part ? a.G64 : nullptr;
+  if constexpr (TG == 2) {
+    if (out_hat) {
+      // both partials in one pass over the two row blocks (small tiles only: with 4 x 4
+      // tiles the two accumulator sets would not fit in registers)
+      gdot = gpre ? chunk_gram2_tiles<TG, true, 4>(s_rows, s_rows2, nrows, r, out_new,
+                                                   out_hat, a.G64, gm)
+                  : chunk_gram2_tiles<TG, false, 4>(s_rows, s_rows2, nrows, r, out_new,
+                                                    out_hat, gmat, no_tile);
+      out_hat = nullptr;
+      out_new = nullptr;
+      gmat = nullptr;
+    }
   }
-  if (a.gp_hat && a.A_hat)
-    chunk_gram_tiles<TG, false, 4>(s_rows2, nrows, r, a.gp_hat + blockIdx.x * rr, nullptr,
-                                      no_tile);
+  if (out_new || gmat) {
+    gdot = gpre ? chunk_gram_tiles<TG, true, 4>(s_rows, nrows, r, out_new, a.G64, gm)
+                : chunk_gram_tiles<TG, false, 4>(s_rows, nrows, r, out_new, gmat, no_tile);
+  }
+  if (out_hat) chunk_gram_tiles<TG, false, 4>(s_rows2, nrows, r, out_hat, nullptr, no_tile);
   if (a.err_part) {
     // share of 2 <P, W> - <G, W^T W> over the chunk's rows
     double t = -gdot;
