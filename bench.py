@@ -44,7 +44,7 @@ def _source_digest(names) -> str:
     return h.hexdigest()[:16]
 
 
-KERNEL_SOURCES = {"mttkrp": ["k_mttkrp.hip"], "hals": ["k_hals.hip", "gram_chunk.h"]}
+KERNEL_SOURCES = {"mttkrp": ["k_mttkrp.hip", "gram_chunk.h"], "hals": ["k_hals.hip", "gram_chunk.h"]}
 
 
 def traffic_for(kind: str):
