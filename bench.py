@@ -13,10 +13,12 @@ MTTKRP throughput, final relative errors (explicit residual against the float32 
 and the FP64 oracle's rate on the host are reported beside it.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
-                    [--no-autograd] [--copy-probe]
+                    [--no-autograd] [--no-quad] [--copy-probe]
 
-Also reported (not the headline value): the 256-problem batched workload solved in one
-persistent launch, and the 512^3 r=50 autograd loss with its backward.
+Also reported (not the headline value): the read-only streaming rate at each tensor's
+footprint (the MTTKRP's practical roof), the 4-way 128^4 bf16 r=64 workload (solver rate,
+per-mode MTTKRP and its fraction of the bf16 MFMA peak), the 256-problem batched workload
+solved in one persistent launch, and the 512^3 r=50 autograd loss with its backward.
 """
 from __future__ import annotations
 
@@ -31,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 WORKLOAD = "cube400_r32_corr"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cube400_r32.json")
 
@@ -203,6 +206,58 @@ def bench_autograd(ntf, torch, reps: int):
                 loss=float(L.item()))
 
 
+def stream_gbs(ntf, torch, Td, reps: int = 20) -> float:
+    """Read-only streaming rate at the tensor's footprint: one ntf_norm2 pass (a plain
+    fixed-order sum of squares that reads every element once), GB/s."""
+    ntf.ntf_norm2(Td)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(reps):
+        ntf.ntf_norm2(Td)
+    e1.record()
+    torch.cuda.synchronize()
+    return Td.numel() * Td.element_size() / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
+
+
+def bench_quad128(ntf, torch, iters: int, warmup: int, reps: int):
+    """The 4-way workload: 128^4 stored in bfloat16 (537 MB), r = 64, factors U[0,1] with
+    30 % zeros, 20 dB, clipped. Outer iterations/s of the solver, the MTTKRP of every mode
+    (TFLOP/s, GB/s, fraction of the dense bf16 MFMA peak) and the final fit against the
+    bfloat16 tensor."""
+    import numpy as np
+
+    import synth
+    w = synth.WORKLOADS["quad128_r64_sparse"]
+    pr = synth.workload("quad128_r64_sparse")
+    Td32 = torch.from_numpy(pr.T.astype(np.float32)).cuda()
+    A0 = [torch.from_numpy(a.astype(np.float32)).cuda() for a in pr.A0]
+    del pr
+    Td = ntf.ntf_cast_bf16(Td32)
+    del Td32
+    torch.cuda.synchronize()
+    r = int(w["r"])
+    A = [a.clone() for a in A0]
+    ms, _, _, trace = time_solve(ntf, torch, Td, A, A0, iters, warmup, ntf.HerParams())
+    res = float(ntf.ntf_residual_norm2(Td, A).item()) ** 0.5
+    relerr = res / float(ntf.ntf_norm2(Td).item()) ** 0.5
+    mt = time_mttkrp(ntf, torch, Td, A, reps)
+    n = int(Td.numel())
+    tf = [2.0 * r * n / (t / 1e3) / 1e12 for t in mt]
+    out = dict(workload="quad128_r64_sparse", dims=list(w["dims"]), rank=r, tensor="bf16",
+               iters=iters, iters_per_s=round(iters / (ms / 1e3), 2),
+               ms_per_iter=round(ms / iters, 4), final_relerr=relerr,
+               restarts=int(trace["restart"].sum().item()),
+               mean_inner_sweeps=round(trace["sweeps"].float().mean().item(), 2),
+               mttkrp_ms=[round(t, 4) for t in mt], mttkrp_tflops=[round(x, 2) for x in tf],
+               mttkrp_gbs=[round(n * 2 / (t / 1e3) / 1e9, 1) for t in mt],
+               mttkrp_mfma_frac=[round(x / BF16_MFMA_PEAK_TFLOPS, 4) for x in tf],
+               stream_gbs=round(stream_gbs(ntf, torch, Td), 1))
+    del Td, A, A0
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_probe(torch, nbytes: int = 256 << 20):
     """A plain device copy of known size (traffic counters are scaled by it)."""
     x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -299,6 +354,8 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--autograd-reps", type=int, default=5)
     ap.add_argument("--no-autograd", action="store_true")
+    ap.add_argument("--quad-iters", type=int, default=200)
+    ap.add_argument("--no-quad", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MB device copy (reference for traffic counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -368,6 +425,7 @@ def main(argv=None):
             f"mttkrp ms {['%.4f' % t for t in mt_ms]}")
         del A_dev
     flags = ntf.ntf_device_flags()
+    streams = {"bf16_128MB": stream_gbs(ntf, torch, Td16), "f32_256MB": stream_gbs(ntf, torch, Td32)}
 
     golden = None
     gpath = os.path.join(ROOT, "tests", "golden", "oracle_fits.json")
@@ -386,6 +444,9 @@ def main(argv=None):
                "traffic": traffic_for("mttkrp"),
                "kernel": "mttkrp_kernel + mttkrp_reduce_kernel (one ntf_mttkrp call), bf16 "
                          "tensor, mean over the 3 modes",
+               "stream_gbs": round(streams["bf16_128MB"], 1),
+               "frac_of_stream": round(achieved / streams["bf16_128MB"], 4),
+               "mfma_frac": round(2.0 * r * n_elem / (t_mt / 1e3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4),
                "step_share": round(sum(bf["mttkrp_ms"]) / bf["ms_per_step"], 3)}
     # A-HALS: algorithmic flops = 2 r^2 per row per sweep (r multiply-adds per column);
     # fp32 vector peak (the kernel is bound by its column-to-column dependency chain)
@@ -431,6 +492,11 @@ def main(argv=None):
         "device_flags": flags,
         "cpu_baseline": None,
     }
+    line["stream_gbs"] = {k: round(v, 1) for k, v in streams.items()}
+    if not a.no_quad:
+        log(f"[bench] 4-way: 128^4 bf16, r=64, {a.quad_iters} outer iterations")
+        line["quad128"] = bench_quad128(ntf, torch, a.quad_iters, 5, a.mttkrp_reps)
+        line["stream_gbs"]["bf16_537MB"] = line["quad128"]["stream_gbs"]
     if not a.no_batched:
         log(f"[bench] batched: 256 problems, {a.batched_iters} iterations, one launch")
         line["batched"] = bench_batched(ntf, torch, a.batched_iters)

@@ -536,6 +536,201 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_kernel(KArgs k) {
   }
 }
 
+// ---- Row-slab variant (bfloat16, n < N-1) ----
+// The kernel above puts 32 rows i of the output in the MFMA M dimension, so every load
+// instruction touches 32 rows of T at the row stride. When that stride is a multiple of a
+// large power of two (e.g. 4 MiB for the first mode of a 128^4 tensor) all 32 rows fall in the
+// same DRAM bank and channel and the stream slows down by a third. This variant keeps one
+// output row i per workgroup and puts 32 consecutive values of the innermost u mode in M:
+//
+//   Z[u, p] = sum_v T(u, i, v) A_v[v, p]   (MFMA, A operand = 32 u rows of T),
+//   P[i, p] += sum_u X[u][p] Z[u, p],       X[u][p] = C[p] * A_in[j_in(u), p],
+//
+// where A_in is the factor of the innermost u mode and C[p] the product of the other u
+// modes' factor rows (one value per batch of 32 u). Consecutive u are adjacent runs of T
+// for modes before N-2, so a workgroup streams long contiguous ranges. Batches (32 values
+// of the innermost u mode, the other u modes fixed) are split over `S` workgroups per row
+// and interleaved over the 4 waves; the waves' sums are combined in a fixed order and
+// written as split partials [split][I][r] (P itself when S == 1).
+struct SArgs {
+  const void* T;
+  int64_t tbytes;
+  float* out;
+  const float* Av;             // I_v x r
+  const float* Ain;            // I_in x r (innermost u mode)
+  const float* Ao[kMaxOrder];  // the other u modes, slowest first
+  FastDiv fd_o[kMaxOrder];
+  int n_o;
+  int64_t I, Iv, R, a_stride, Rp;
+  FastDiv fd_Rp;
+  int64_t I_in, nb_in, nbatch, S;
+  int r, vb;
+  int nh;
+  HadamardLaunch had;
+};
+
+template <int NT>
+__global__ __launch_bounds__(kThreads, 2) void mttkrp_slab_kernel(SArgs k) {
+  if (int(blockIdx.x) < k.nh) {
+    hadamard_work(k.had.job, k.had.r, k.had.G32, k.had.G64, k.had.slots, k.had.nslots,
+                  blockIdx.x, k.nh);
+    return;
+  }
+  constexpr int RP = 32 * NT;
+  constexpr int KCH = 64;
+  constexpr int PD = 4;
+  constexpr int NW = kThreads / 64;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int ldb = k.vb + 8;
+  uint16_t* s_av = reinterpret_cast<uint16_t*>(smem);
+  float* s_ain = reinterpret_cast<float*>(smem + align_up(size_t(RP) * ldb * 2, 16));
+  float* s_red = s_ain + k.I_in * RP;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int col = lane & 31;
+  const int half = lane >> 5;
+  const int64_t lw = int64_t(blockIdx.x) - k.nh;
+  const int64_t i = lw % k.I;
+  const int64_t split = lw / k.I;
+  const int64_t per = k.nbatch / k.S, extra = k.nbatch % k.S;
+  const int64_t b_beg = split * per + (split < extra ? split : extra);
+  const int64_t b_end = b_beg + per + (split < extra ? 1 : 0);
+  // this wave's batches: b_beg + wave + NW * m
+  const int64_t nbw = b_end - b_beg > wave ? (b_end - b_beg - wave + NW - 1) / NW : 0;
+  const int nkc = int(ceil_div(k.Iv, int64_t(KCH)));
+  const int64_t nitems = nbw * nkc;
+
+  const __amdgpu_buffer_rsrc_t trs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(k.T), short(0), int(k.tbytes), kBufWord3);
+  // item (batch m of this wave, chunk c): lane (row, half) loads 32 elements of v along its
+  // u row; rows past I_in and items past the end load zeros (buffer out-of-range reads)
+  auto load_item = [&](uint4 (&reg)[4], int64_t m, int c) {
+    const bool valid = m < nbw;
+    const int64_t b = b_beg + wave + NW * (valid ? m : 0);
+    const int64_t uo = b / k.nb_in;
+    const int64_t j = (b - uo * k.nb_in) * 32 + col;
+    const bool ok_row = valid && j < k.I_in;
+    const uint32_t u = uint32_t(uo * k.I_in + (ok_row ? j : 0));
+    const uint32_t a = fdiv(u, k.fd_Rp);
+    const int64_t bhi = int64_t(u) - int64_t(a) * k.Rp;
+    const int64_t v = int64_t(c) * KCH + half * 32;
+    const int64_t off = int64_t(a) * k.a_stride + i * k.R + bhi * k.Iv + v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool ok = ok_row && v + (q + 1) * 8 <= k.Iv;
+      reg[q] = bload16(trs, ok ? uint32_t((off + q * 8) * 2) : kOOB);
+    }
+  };
+
+  uint4 buf[PD][4];
+  int64_t pm = 0;
+  int pc = 0;
+  auto prefetch = [&](uint4 (&reg)[4]) {
+    load_item(reg, pm, pc);
+    if (++pc == nkc) {
+      pc = 0;
+      ++pm;
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < PD - 1; ++d) prefetch(buf[d]);
+
+  // A_v (bf16, s_av[p][v]) and A_in (float32, s_ain[j][p]) into LDS, zero-padded
+  for (int e = tid; e < k.vb * RP; e += kThreads) {
+    const int kk = e / RP;
+    const int p = e - kk * RP;
+    s_av[p * ldb + kk] = f2bf((p < k.r && kk < k.Iv) ? k.Av[int64_t(kk) * k.r + p] : 0.f);
+  }
+  for (int64_t e = tid; e < k.I_in * RP; e += kThreads) {
+    const int64_t j = e / RP;
+    const int p = int(e - j * RP);
+    s_ain[e] = p < k.r ? k.Ain[j * k.r + p] : 0.f;
+  }
+  lds_barrier();
+
+  f32x16 acc[NT], y[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[nt][e] = 0.f;
+
+  int64_t cm = 0;
+  int cc = 0;
+  for (int64_t base = 0; base < nitems; base += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      prefetch(buf[(d + PD - 1) % PD]);
+      if (base + d < nitems) {
+        if (cc == 0) {
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) y[nt][e] = 0.f;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const bf16x8 av = *reinterpret_cast<const bf16x8*>(&buf[d][t]);
+          const int kk = cc * KCH + half * 32 + t * 8;
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&s_av[(nt * 32 + col) * ldb + kk]);
+            y[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, y[nt], 0, 0, 0);
+          }
+        }
+        if (cc == nkc - 1) {
+          // fold the batch: acc[u, p] += C[p] * A_in[j(u), p] * Z[u, p]
+          const int64_t b = b_beg + wave + NW * cm;
+          const int64_t uo = b / k.nb_in;
+          const int64_t j0 = (b - uo * k.nb_in) * 32;
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const int p = nt * 32 + col;
+            float c = 1.f;
+            uint32_t rest = uint32_t(uo);
+            for (int q = k.n_o - 1; q >= 0; --q) {
+              const uint32_t qq = fdiv(rest, k.fd_o[q]);
+              const uint32_t dd = rest - qq * k.fd_o[q].d;
+              rest = qq;
+              c *= p < k.r ? k.Ao[q][int64_t(dd) * k.r + p] : 0.f;
+            }
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+              const int64_t j = std::min<int64_t>(j0 + 8 * (e >> 2) + half * 4 + (e & 3),
+                                                  k.I_in - 1);
+              acc[nt][e] = fmaf(c * s_ain[j * RP + p], y[nt][e], acc[nt][e]);
+            }
+          }
+        }
+        if (++cc == nkc) {
+          cc = 0;
+          ++cm;
+        }
+      }
+    }
+  }
+
+  // sum over the 32 u rows (registers, then the two lane halves), then over the waves in
+  // order; lanes < 32 of each wave hold the column sums
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    float s = 0.f;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) s += acc[nt][e];
+    const float o = __shfl_xor(s, 32);
+    s = half ? o + s : s + o;
+    if (half == 0) s_red[wave * RP + nt * 32 + col] = s;
+  }
+  __syncthreads();
+  if (tid < RP && tid < k.r) {
+    float s = s_red[tid];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s += s_red[w * RP + tid];
+    k.out[(split * k.I + i) * k.r + tid] = s;
+  }
+}
+
 // Fixed-order sum of split partials: each output element is summed by 4 threads over
 // interleaved splits (float64), then combined in thread order.
 __global__ __launch_bounds__(256) void mttkrp_reduce_kernel(const float* __restrict__ part,
@@ -661,6 +856,11 @@ KernelFn pick_shape(int wm, int nt) {
   return pick<BF16, 8, 2, 2, LAST, VEC>();
 }
 
+using SlabFn = void (*)(SArgs);
+SlabFn select_slab(int nt) {
+  return nt == 1 ? mttkrp_slab_kernel<1> : mttkrp_slab_kernel<2>;
+}
+
 KernelFn select_kernel(bool bf16, bool last, int wm, int nt, bool vec) {
   if (vec) {
     if (bf16)
@@ -704,6 +904,44 @@ ModeView make_mode_view(const ntf_tensor& T, int mode) {
   for (int l = mode + 1; l < T.order; ++l) v.R *= T.dims[l];
   v.I = T.dims[mode];
   return v;
+}
+
+// The row-slab variant replaces the row-tile kernel for bfloat16 modes before the last
+// whose row stride is a multiple of 1 MiB (rows that share DRAM banks), when r <= 64, the
+// tensor's rows and runs are 16-byte aligned, the innermost u mode has at least 16 values,
+// and the LDS blocks fit.
+static void plan_slab(MttkrpPlan& pl, const ntf_tensor& T, int num_cus) {
+  const int N = T.order;
+  const int n = pl.v.mode;
+  // (r <= 64: two N tiles keep the accumulators, the batch and its prefetch in 256 registers)
+  if (pl.dtype != NTF_BF16 || pl.layout != 0 || pl.store_y || pl.variant > 2 || N < 3) return;
+  if (!vec_loads(pl) || (pl.v.R * 2) % (int64_t(1) << 20) != 0) return;
+  const int inner = n < N - 2 ? N - 2 : N - 3;
+  const int64_t I_in = T.dims[inner];
+  if (I_in < 16) return;
+  const int64_t vb = ceil_div(pl.Iv, int64_t(64)) * 64;
+  const size_t lds = align_up(size_t(pl.rpad) * (vb + 8) * 2, 16) + size_t(I_in) * pl.rpad * 4 +
+                     size_t(kThreads / 64) * pl.rpad * 4;
+  if (lds > 72 * 1024) return;
+  SlabFn fn = select_slab(pl.variant);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn),
+                                                   kThreads, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const int64_t nb_in = ceil_div(I_in, int64_t(32));
+  const int64_t nbatch = pl.U / I_in * nb_in;
+  const int64_t slots = int64_t(per_cu) * num_cus;
+  int64_t S = std::max<int64_t>(1, slots / pl.v.I);
+  S = std::min<int64_t>({S, std::max<int64_t>(1, nbatch / 4), int64_t(65535)});
+  pl.slab = true;
+  pl.slab_inner = inner;
+  pl.vb = int(vb);
+  pl.nvb = 1;
+  pl.splits = S;
+  pl.lds = lds;
 }
 
 MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus, bool store_y) {
@@ -776,13 +1014,65 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus, bool s
     pl.ub = int(std::max<int64_t>(1, std::min<int64_t>({per, int64_t(8192 / pl.rpad), pl.U})));
   }
   pl.lds = std::max(lds_bytes(bf16, last, pl.rpad, pl.vb, pl.ub), red);
+  plan_slab(pl, T, num_cus);
   return pl;
+}
+
+static hipError_t launch_slab(const MttkrpPlan& pl, const void* T, const FactorPtrs& A, float* P,
+                              float* partials, bool reduce, hipStream_t s,
+                              const HadamardLaunch* had) {
+  SArgs k{};
+  if (had) {
+    k.nh = kHadamardBlocks;
+    k.had = *had;
+  }
+  const int N = pl.v.order;
+  const int n = pl.v.mode;
+  k.T = T;
+  k.tbytes = pl.v.L * pl.v.I * pl.v.R * 2;
+  k.Av = A.p[pl.vmode];
+  k.Ain = A.p[pl.slab_inner];
+  k.n_o = 0;
+  for (int l = 0; l < N; ++l) {
+    if (l == n || l == pl.vmode || l == pl.slab_inner) continue;
+    k.Ao[k.n_o] = A.p[l];
+    k.fd_o[k.n_o] = make_fastdiv(uint32_t(pl.v.dims[l]));
+    k.n_o++;
+  }
+  k.I = pl.v.I;
+  k.Iv = pl.Iv;
+  k.R = pl.v.R;
+  k.a_stride = pl.v.I * pl.v.R;
+  k.Rp = pl.v.R / pl.Iv;
+  k.fd_Rp = make_fastdiv(uint32_t(k.Rp));
+  k.I_in = pl.v.dims[pl.slab_inner];
+  k.nb_in = ceil_div(k.I_in, int64_t(32));
+  k.nbatch = pl.U / k.I_in * k.nb_in;
+  k.S = pl.splits;
+  k.r = pl.r;
+  k.vb = pl.vb;
+  const bool split = pl.splits > 1;
+  k.out = split ? partials : P;
+  SlabFn fn = select_slab(pl.variant);
+  dim3 grid(unsigned(pl.v.I * pl.splits + k.nh));
+  hipLaunchKernelGGL(fn, grid, dim3(kThreads), pl.lds, s, k);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (split && reduce) {
+    const int64_t nout = pl.v.I * pl.r;
+    const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(ceil_div(nout, 64), 4096)));
+    hipLaunchKernelGGL(mttkrp_reduce_kernel, dim3(blocks), dim3(256), 0, s, partials,
+                       pl.splits, nout, P);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& A, float* P,
                          float* partials, bool reduce, hipStream_t s, float* ystore,
                          const HadamardLaunch* had) {
   KArgs k{};
+  if (pl.slab) return launch_slab(pl, T, A, P, partials, reduce, s, had);
   if (had) {
     k.nh = kHadamardBlocks;
     k.had = *had;

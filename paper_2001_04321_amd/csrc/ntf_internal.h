@@ -143,6 +143,8 @@ struct MttkrpPlan {
   int64_t chunks;  // work items (v-block, u)
   bool store_y = false;  // store Y = T_u A_v rows instead of folding (case A, 3-way solver)
   bool uk = false;       // the WK waves of a row tile split u (not v chunks)
+  bool slab = false;     // row-slab kernel (one output row per workgroup, u rows in M)
+  int slab_inner = -1;   // its innermost u mode
   int64_t splits;  // splits of the work items (grid.y)
   size_t partial_floats() const { return splits > 1 ? size_t(splits) * v.I * r : 0; }
 };

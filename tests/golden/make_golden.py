@@ -1,12 +1,16 @@
 """Write tests/golden/oracle_fits.json: the FP64 oracle's final fit on named workloads.
 
-    python tests/golden/make_golden.py cube50_r10 cube400_r32_corr ...
+    python tests/golden/make_golden.py cube50_r10 cube400_r32_corr quad128_r64_sparse:bf16:20
 
 Calls only the oracle (and the seeded input generator for its inputs). The oracle sees
-the float32 values of the tensor and the initial factors, as the GPU does. For each
-workload it records the final relative error / fit of Algorithm 2 (HER with A-HALS,
-the paper's default parameters) after the workload's outer-iteration count, the number
-of restarts, and the F-hat trace.
+the float32 values of the tensor and the initial factors, as the GPU does; a spec
+`name:bf16` rounds the tensor to bfloat16 first (round to nearest even, as the inputs of
+the GPU tests are rounded),
+for workloads whose tensor is stored in that format, and a third field `:K` overrides the
+workload's outer-iteration count. For each spec it records the final relative error / fit
+of Algorithm 2 (HER with A-HALS, the paper's default parameters; the fit is taken against
+the tensor the oracle solved), the number of restarts, and the F-hat trace, under the key
+`name` (float32 tensor, the workload's own count) or the spec itself.
 """
 import json
 import os
@@ -24,17 +28,28 @@ import synth  # noqa: E402
 OUT = os.path.join(HERE, "oracle_fits.json")
 
 
-def run(name: str) -> dict:
+def run(spec: str) -> dict:
+    parts = spec.split(":")
+    name = parts[0]
+    dtype = parts[1] if len(parts) > 1 else "f32"
     w = synth.WORKLOADS[name]
+    iters = int(parts[2]) if len(parts) > 2 else w["iters"]
     pr = synth.workload(name)
-    T64 = pr.T.astype(np.float32).astype(np.float64)
+    T32 = pr.T.astype(np.float32)
+    if dtype == "bf16":
+        T64 = synth.bf16_to_f32(synth.bf16_bits(T32)).astype(np.float64)
+    elif dtype == "f32":
+        T64 = T32.astype(np.float64)
+    else:
+        raise ValueError(f"unknown tensor format {dtype}")
+    del T32
     A0 = [a.astype(np.float32).astype(np.float64) for a in pr.A0]
     del pr
     t0 = time.perf_counter()
-    res = oracle.her_solve(T64, A0, w["iters"])
+    res = oracle.her_solve(T64, A0, iters)
     dt = time.perf_counter() - t0
     rel = oracle.relative_error(T64, res.factors)
-    return dict(workload=name, iters=w["iters"], relerr=rel, fit=1.0 - rel,
+    return dict(workload=name, tensor=dtype, iters=iters, relerr=rel, fit=1.0 - rel,
                 restarts=int(sum(res.restart)), fhat=res.fhat, fhat0=res.fhat0,
                 oracle_seconds=dt, cpu_count=os.cpu_count())
 

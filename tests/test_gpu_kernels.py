@@ -80,6 +80,32 @@ def test_mttkrp_signed_data_and_determinism(ntf, dtype):
         assert err <= (1e-6 if dtype == "f32" else 1e-2)
 
 
+# bf16 tensors whose row stride (in the mode under test) is a multiple of 1 MiB: that
+# mode runs on the row-slab kernel (one output row per workgroup, u rows in the MFMA M
+# dimension). Cases: innermost u mode a multiple of 32 and not (48: a ragged last block),
+# v not a multiple of the 64-element chunk (72), r in one and two N tiles (40: a ragged
+# second tile), and a 5-way tensor whose slab mode is not the first, with two outer u modes.
+SLAB = [((3, 64, 64, 128), 40, 0), ((2, 256, 48, 128), 20, 0), ((2, 256, 256, 72), 24, 0),
+        ((2, 3, 64, 64, 128), 8, 1)]
+
+
+@pytest.mark.parametrize("dims,r,mode", SLAB)
+def test_mttkrp_row_slab_modes(ntf, dims, r, mode):
+    g = np.random.default_rng(7)
+    T = g.random(dims).astype(np.float32)
+    A = [g.random((I, r)).astype(np.float32) for I in dims]
+    Td, T64 = dev_tensor(T, "bf16")
+    Ad = [dev_f32(a) for a in A]
+    A64 = [a.astype(np.float64) for a in A]
+    P1 = ntf.ntf_mttkrp(Td, Ad, mode)
+    P2 = ntf.ntf_mttkrp(Td, Ad, mode)
+    assert torch.equal(P1, P2)
+    ref = oracle.mttkrp(T64, A64, mode)
+    err = rel_fro(to_np(P1), ref)
+    print(f"slab dims={dims} r={r} mode={mode} relerr={err:.3e}")
+    assert err <= 2e-2
+
+
 FULL = [("cube400_r32_corr", "f32"), ("cube400_r32_corr", "bf16"),
         ("quad128_r64_sparse", "bf16"), ("cube512_r50", "f32")]
 

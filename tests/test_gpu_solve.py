@@ -40,7 +40,8 @@ def _fit(T64, A):
 
 
 @pytest.mark.parametrize("dims,r,seed", [((12, 10, 8), 3, 0), ((30, 20, 25), 5, 1),
-                                         ((9, 8, 7, 6), 3, 2), ((40, 35), 4, 3)])
+                                         ((9, 8, 7, 6), 3, 2), ((40, 35), 4, 3),
+                                         ((16, 14, 12, 10), 40, 11)])
 def test_small_problem_trajectory_and_fit(ntf, dims, r, seed):
     pr = synth.make_problem(dims, r, snr_db=30.0, data_seed=seed, init_seed=seed + 50)
     T32 = pr.T.astype(np.float32)
