@@ -220,7 +220,7 @@ def stream_gbs(ntf, torch, Td, reps: int = 20) -> float:
     return Td.numel() * Td.element_size() / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
 
 
-def bench_quad128(ntf, torch, iters: int, warmup: int, reps: int):
+def bench_quad128(ntf, torch, iters: int, warmup: int, reps: int, autotune: bool):
     """The 4-way workload: 128^4 stored in bfloat16 (537 MB), r = 64, factors U[0,1] with
     30 % zeros, 20 dB, clipped. Outer iterations/s of the solver, the MTTKRP of every mode
     (TFLOP/s, GB/s, fraction of the dense bf16 MFMA peak) and the final fit against the
@@ -237,6 +237,12 @@ def bench_quad128(ntf, torch, iters: int, warmup: int, reps: int):
     del Td32
     torch.cuda.synchronize()
     r = int(w["r"])
+    tuned = []
+    if autotune:
+        for n in range(Td.dim()):
+            _, info = ntf.ntf_mttkrp_autotune(Td, A0, n, reps=5)
+            tuned.append({"mode": n, "kernel": info["kernel"], "wm": info["wm"],
+                          "ms": round(info["ms"], 4)})
     A = [a.clone() for a in A0]
     ms, _, _, trace = time_solve(ntf, torch, Td, A, A0, iters, warmup, ntf.HerParams())
     res = float(ntf.ntf_residual_norm2(Td, A).item()) ** 0.5
@@ -252,7 +258,7 @@ def bench_quad128(ntf, torch, iters: int, warmup: int, reps: int):
                mttkrp_ms=[round(t, 4) for t in mt], mttkrp_tflops=[round(x, 2) for x in tf],
                mttkrp_gbs=[round(n * 2 / (t / 1e3) / 1e9, 1) for t in mt],
                mttkrp_mfma_frac=[round(x / BF16_MFMA_PEAK_TFLOPS, 4) for x in tf],
-               stream_gbs=round(stream_gbs(ntf, torch, Td), 1))
+               stream_gbs=round(stream_gbs(ntf, torch, Td), 1), mttkrp_autotune=tuned or None)
     del Td, A, A0
     torch.cuda.empty_cache()
     return out
@@ -354,6 +360,8 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--autograd-reps", type=int, default=5)
     ap.add_argument("--no-autograd", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the planner's default MTTKRP shapes")
     ap.add_argument("--quad-iters", type=int, default=200)
     ap.add_argument("--no-quad", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -402,6 +410,16 @@ def main(argv=None):
     params = ntf.HerParams()
     n_elem = int(np.prod(T32.shape))
     r = int(w["r"])
+    tuned = {}
+    if not a.no_autotune:
+        # the autotuner picks each mode's MTTKRP shape (timed on the workload's own tensor)
+        for form, Td in (("bf16", Td16), ("fp32", Td32)):
+            tuned[form] = []
+            for n in range(Td.dim()):
+                _, info = ntf.ntf_mttkrp_autotune(Td, A0_dev, n, reps=10)
+                tuned[form].append({"mode": n, "kernel": info["kernel"], "wm": info["wm"],
+                                    "ms": round(info["ms"], 4)})
+        log(f"[bench] autotuned MTTKRP shapes: {tuned}")
     forms = {}
     for form, Td, s in (("bf16", Td16, 2), ("fp32", Td32, 4)):
         A_dev = [x.clone() for x in A0_dev]
@@ -488,6 +506,7 @@ def main(argv=None):
         "oracle_relerr": golden,
         "restarts": {k: v["restarts"] for k, v in forms.items()},
         "mean_inner_sweeps": {k: round(v["mean_inner_sweeps"], 2) for k, v in forms.items()},
+        "mttkrp_autotune": tuned or None,
         "bf16_cast_ms": round(cast_ms, 4),
         "device_flags": flags,
         "cpu_baseline": None,
@@ -495,7 +514,8 @@ def main(argv=None):
     line["stream_gbs"] = {k: round(v, 1) for k, v in streams.items()}
     if not a.no_quad:
         log(f"[bench] 4-way: 128^4 bf16, r=64, {a.quad_iters} outer iterations")
-        line["quad128"] = bench_quad128(ntf, torch, a.quad_iters, 5, a.mttkrp_reps)
+        line["quad128"] = bench_quad128(ntf, torch, a.quad_iters, 5, a.mttkrp_reps,
+                                        not a.no_autotune)
         line["stream_gbs"]["bf16_537MB"] = line["quad128"]["stream_gbs"]
     if not a.no_batched:
         log(f"[bench] batched: 256 problems, {a.batched_iters} iterations, one launch")

@@ -149,6 +149,33 @@ ntf_status ntf_cast_bf16(ntf_handle* h, const float* src, uint16_t* dst, int64_t
 ntf_status ntf_mttkrp(ntf_handle* h, const ntf_tensor* T, const float* const* A, int32_t r,
                       int32_t mode, float* P, void* stream);
 
+/* MTTKRP autotuner. Times every kernel shape the planner can take for mode `mode` of a
+ * tensor of T's shape, dtype and rank r (row tiles of 32, 64 or 128 rows; the row-slab
+ * kernel where it applies), `reps` calls each after one warm-up, with HIP events on
+ * `stream`, on the caller's T and A; records the fastest in the handle's tuning table,
+ * which later ntf_mttkrp and ntf_solve calls on the same shape, dtype, mode and rank use
+ * (a cached solver graph is rebuilt). P (I_mode x r) receives the MTTKRP from the chosen
+ * shape. Synchronizes `stream` (not for use under stream capture). kernel_out (1 row
+ * tiles, 2 row slab), wm_out (row-tile waves along rows) and ms_out (milliseconds per call
+ * of the chosen shape) are host pointers and may be NULL. reps outside [1, 1000]:
+ * NTF_EINVAL. */
+ntf_status ntf_mttkrp_autotune(ntf_handle* h, const ntf_tensor* T, const float* const* A,
+                               int32_t r, int32_t mode, float* P, int32_t reps,
+                               int32_t* kernel_out, int32_t* wm_out, float* ms_out,
+                               void* stream);
+
+/* The handle's tuning table as text, one entry per line: "<key> <kernel> <wm>", where key
+ * names dtype, shape, mode and rank (e.g. "bf16:400x400x400:mode2:r32"). Returns the bytes
+ * needed including the terminating NUL and copies the text into buf if cap is at least
+ * that (buf may be NULL to ask for the size); -1 for a NULL handle. */
+int64_t ntf_tune_export(ntf_handle* h, char* buf, int64_t cap);
+
+/* Adds the entries of a text in ntf_tune_export's format to the handle's tuning table
+ * (replacing entries with the same key). Blank lines are skipped; a malformed line returns
+ * NTF_EINVAL and adds nothing. A choice that does not apply to a shape is ignored by the
+ * planner (it falls back to its default). */
+ntf_status ntf_tune_import(ntf_handle* h, const char* text);
+
 /* Hadamard product of factor Grams, G = (*)_{l != exclude} A_l^T A_l (r x r, row-major);
  * with exclude = n this is (B^(n))^T B^(n) (Appendix A gradient; Sec. 2.2 Lipschitz
  * matrix). rows: host array of the I_l. exclude = -1 multiplies all `nfac` Grams.

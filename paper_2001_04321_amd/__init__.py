@@ -4,10 +4,11 @@ Every function here marshals torch tensors (device memory, current stream) into 
 declared in include/ntf.h and calls it; all arithmetic runs in the library's HIP kernels.
 There is no CPU fallback: if libntf.so is missing the import of a call raises.
 
-Functions carry the C names: ntf_norm2, ntf_cast_bf16, ntf_mttkrp, ntf_gram,
-ntf_hals_update, ntf_her_step, ntf_error, ntf_solve, ntf_residual_norm2, ntf_cp_loss,
-ntf_cp_grad, ntf_solve_batched, plus the autograd loss `NTFLoss` / `ntf_loss` (module
-`autograd`).
+Functions carry the C names: ntf_norm2, ntf_cast_bf16, ntf_mttkrp, ntf_mttkrp_autotune,
+ntf_tune_export, ntf_tune_import, ntf_gram, ntf_hals_update, ntf_her_step, ntf_error,
+ntf_solve, ntf_residual_norm2, ntf_cp_loss, ntf_cp_grad, ntf_solve_batched, plus the
+autograd loss `NTFLoss` / `ntf_loss` (module `autograd`) and a JSON file for the tuning
+table (`save_tuning`, `load_tuning`).
 """
 from __future__ import annotations
 
@@ -23,7 +24,8 @@ __all__ = [
     "Handle", "HerParams", "NtfError", "handle", "ntf_norm2", "ntf_cast_bf16", "ntf_mttkrp",
     "ntf_gram", "ntf_hals_update", "ntf_her_step", "ntf_error", "ntf_solve",
     "ntf_residual_norm2", "ntf_device_flags", "new_state", "state_dict", "ntf_cp_loss",
-    "ntf_cp_grad", "NTFLoss", "ntf_loss", "ntf_solve_batched",
+    "ntf_cp_grad", "NTFLoss", "ntf_loss", "ntf_solve_batched", "ntf_mttkrp_autotune",
+    "ntf_tune_export", "ntf_tune_import", "save_tuning", "load_tuning",
 ]
 
 _DTYPES = {torch.float32: _abi.NTF_F32, torch.bfloat16: _abi.NTF_BF16}
@@ -144,6 +146,58 @@ def ntf_mttkrp(T: torch.Tensor, factors, mode: int, out: torch.Tensor | None = N
     check(lib().ntf_mttkrp(_h(h), C.byref(d), ptrs, r, int(mode), _dev(out, "P", torch.float32),
                            _stream(stream)))
     return out
+
+
+def ntf_mttkrp_autotune(T: torch.Tensor, factors, mode: int, reps: int = 5,
+                        out: torch.Tensor | None = None, h=None, stream=None):
+    """Time the MTTKRP shapes for this mode and record the fastest in the handle's table.
+
+    Returns (out, {"kernel": 1 row tiles | 2 row slab, "wm": waves along rows, "ms": ...}).
+    Synchronizes the stream.
+    """
+    r = int(factors[(mode + 1) % T.dim()].shape[1])
+    out = torch.empty((T.shape[mode], r), dtype=torch.float32, device=T.device) if out is None else out
+    d = _tensor_desc(T)
+    ptrs = ptr_array([(_dev(A, f"A[{l}]", torch.float32) if (A is not None and l != mode) else None)
+                      for l, A in enumerate(factors)])
+    kern, wm, ms = C.c_int32(), C.c_int32(), C.c_float()
+    check(lib().ntf_mttkrp_autotune(_h(h), C.byref(d), ptrs, r, int(mode),
+                                    _dev(out, "P", torch.float32), int(reps), C.byref(kern),
+                                    C.byref(wm), C.byref(ms), _stream(stream)))
+    return out, {"kernel": kern.value, "wm": wm.value, "ms": ms.value}
+
+
+def ntf_tune_export(h=None) -> str:
+    """The handle's tuning table as text ("<key> <kernel> <wm>" per line)."""
+    n = lib().ntf_tune_export(_h(h), None, 0)
+    if n < 0:
+        raise NtfError(1, "handle is NULL")
+    buf = C.create_string_buffer(int(n))
+    lib().ntf_tune_export(_h(h), buf, int(n))
+    return buf.value.decode()
+
+
+def ntf_tune_import(text: str, h=None) -> None:
+    check(lib().ntf_tune_import(_h(h), text.encode()))
+
+
+def save_tuning(path: str, h=None) -> None:
+    """Write the handle's tuning table to a JSON file {key: [kernel, wm]}."""
+    import json
+    table = {}
+    for ln in ntf_tune_export(h).splitlines():
+        k, kern, wm = ln.split()
+        table[k] = [int(kern), int(wm)]
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+
+
+def load_tuning(path: str, h=None) -> None:
+    """Add the entries of a JSON file written by save_tuning to the handle's table."""
+    import json
+    with open(path) as f:
+        table = json.load(f)
+    ntf_tune_import("".join(f"{k} {int(v[0])} {int(v[1])}\n" for k, v in table.items()), h)
 
 
 def ntf_gram(factors, exclude: int = -1, want32: bool = True, want64: bool = True, h=None,

@@ -75,6 +75,11 @@ SIGNATURES = {
     "ntf_solve_batched": (C.c_int, [PTR, C.c_int32, C.POINTER(NtfProblem),
                                     C.POINTER(NtfHerParams), C.c_int32, C.c_int32, PTR]),
     "ntf_residual_norm2": (C.c_int, [PTR, C.POINTER(NtfTensor), PTRS, C.c_int32, PTR, PTR]),
+    "ntf_mttkrp_autotune": (C.c_int, [PTR, C.POINTER(NtfTensor), PTRS, C.c_int32, C.c_int32,
+                                      PTR, C.c_int32, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_float), PTR]),
+    "ntf_tune_export": (C.c_int64, [PTR, C.c_char_p, C.c_int64]),
+    "ntf_tune_import": (C.c_int, [PTR, C.c_char_p]),
 }
 
 _lib = None

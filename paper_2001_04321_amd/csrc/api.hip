@@ -249,12 +249,121 @@ ntf_status ntf_mttkrp(ntf_handle* h, const ntf_tensor* T, const float* const* A,
     fp.p[l] = A[l];
   }
   fp.p[mode] = A[(mode + 1) % T->order];  // never read; keeps the slot non-null
-  const MttkrpPlan pl = plan_mttkrp(*T, mode, r, h->num_cus);
+  const MttkrpPlan pl =
+      plan_mttkrp(*T, mode, r, h->num_cus, false, tuned_choice(h, *T, mode, r));
   NTF_RETURN_IF(pl.chunks >= (int64_t(1) << 31), NTF_EUNSUPPORTED, "reduction too long");
   st = ensure_workspace(h, pl.partial_floats() * sizeof(float) + 256);
   if (st) return st;
   NTF_HIP(launch_mttkrp(pl, T->data, fp, P, reinterpret_cast<float*>(h->ws), true,
                         as_stream(stream)));
+  return NTF_OK;
+}
+
+ntf_status ntf_mttkrp_autotune(ntf_handle* h, const ntf_tensor* T, const float* const* A,
+                               int32_t r, int32_t mode, float* P, int32_t reps,
+                               int32_t* kernel_out, int32_t* wm_out, float* ms_out,
+                               void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_tensor(T);
+  if (st) return st;
+  if ((st = check_rank(r))) return st;
+  NTF_RETURN_IF(mode < 0 || mode >= T->order, NTF_EINVAL, "mode %d outside [0, %d)", mode,
+                T->order);
+  NTF_RETURN_IF(!A || !P, NTF_EINVAL, "factor array or output is NULL");
+  NTF_RETURN_IF(reps < 1 || reps > 1000, NTF_EINVAL, "reps %d outside [1, 1000]", reps);
+  FactorPtrs fp{};
+  for (int l = 0; l < T->order; ++l) {
+    if (l == mode) continue;
+    NTF_RETURN_IF(!A[l], NTF_EINVAL, "factor %d is NULL", l);
+    fp.p[l] = A[l];
+  }
+  fp.p[mode] = A[(mode + 1) % T->order];
+  MttkrpChoice cand[8];
+  const int nc = mttkrp_candidates(*T, mode, r, cand, 8);
+  MttkrpPlan plans[8];
+  size_t need = 0;
+  for (int c = 0; c < nc; ++c) {
+    plans[c] = plan_mttkrp(*T, mode, r, h->num_cus, false, &cand[c]);
+    NTF_RETURN_IF(plans[c].chunks >= (int64_t(1) << 31), NTF_EUNSUPPORTED,
+                  "reduction too long");
+    need = std::max(need, plans[c].partial_floats());
+  }
+  if ((st = ensure_workspace(h, need * sizeof(float) + 256))) return st;
+  hipStream_t s = as_stream(stream);
+  float* part = reinterpret_cast<float*>(h->ws);
+  struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  NTF_HIP(hipEventCreate(&ev.a));
+  NTF_HIP(hipEventCreate(&ev.b));
+  int best = 0;
+  float best_ms = 0.f;
+  for (int c = 0; c < nc; ++c) {
+    NTF_HIP(launch_mttkrp(plans[c], T->data, fp, P, part, true, s));  // warm-up
+    NTF_HIP(hipEventRecord(ev.a, s));
+    for (int k = 0; k < reps; ++k) NTF_HIP(launch_mttkrp(plans[c], T->data, fp, P, part, true, s));
+    NTF_HIP(hipEventRecord(ev.b, s));
+    NTF_HIP(hipEventSynchronize(ev.b));
+    float ms = 0.f;
+    NTF_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+    ms /= float(reps);
+    if (c == 0 || ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  // the result in P comes from the chosen shape
+  NTF_HIP(launch_mttkrp(plans[best], T->data, fp, P, part, true, s));
+  h->tune[tune_key(*T, mode, r)] = cand[best];
+  release_solve_graph(h);  // cached solver graphs were built with the previous plans
+  if (kernel_out) *kernel_out = cand[best].kernel;
+  if (wm_out) *wm_out = cand[best].wm;
+  if (ms_out) *ms_out = best_ms;
+  return NTF_OK;
+}
+
+int64_t ntf_tune_export(ntf_handle* h, char* buf, int64_t cap) {
+  if (!h) return -1;
+  std::string text;
+  for (const auto& kv : h->tune)
+    text += kv.first + " " + std::to_string(kv.second.kernel) + " " +
+            std::to_string(kv.second.wm) + "\n";
+  const int64_t need = int64_t(text.size()) + 1;
+  if (buf && cap >= need) std::memcpy(buf, text.c_str(), size_t(need));
+  return need;
+}
+
+ntf_status ntf_tune_import(ntf_handle* h, const char* text) {
+  clear_error();
+  NTF_RETURN_IF(!h, NTF_EINVAL, "handle is NULL");
+  NTF_RETURN_IF(!text, NTF_EINVAL, "text is NULL");
+  std::map<std::string, MttkrpChoice> add;
+  const char* q = text;
+  int line = 0;
+  while (*q) {
+    const char* e = std::strchr(q, '\n');
+    const std::string ln(q, e ? size_t(e - q) : std::strlen(q));
+    q = e ? e + 1 : q + ln.size();
+    ++line;
+    if (ln.find_first_not_of(" \t\r") == std::string::npos) continue;
+    char key[256];
+    int kernel = -1, wm = -1;
+    char extra = 0;
+    const int got = std::sscanf(ln.c_str(), "%255s %d %d %c", key, &kernel, &wm, &extra);
+    NTF_RETURN_IF(got != 3 || kernel < 0 || kernel > 2 || !(wm == 0 || wm == 1 || wm == 2 || wm == 4),
+                  NTF_EINVAL, "tuning line %d is not '<key> <kernel 0..2> <wm 0|1|2|4>'", line);
+    add[key] = MttkrpChoice{kernel, wm};
+  }
+  for (const auto& kv : add) h->tune[kv.first] = kv.second;
+  if (!add.empty()) {
+    DeviceGuard guard_(h->device);
+    release_solve_graph(h);
+  }
   return NTF_OK;
 }
 

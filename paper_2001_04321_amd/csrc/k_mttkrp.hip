@@ -906,23 +906,37 @@ ModeView make_mode_view(const ntf_tensor& T, int mode) {
   return v;
 }
 
-// The row-slab variant replaces the row-tile kernel for bfloat16 modes before the last
-// whose row stride is a multiple of 1 MiB (rows that share DRAM banks), when r <= 64, the
-// tensor's rows and runs are 16-byte aligned, the innermost u mode has at least 16 values,
-// and the LDS blocks fit.
-static void plan_slab(MttkrpPlan& pl, const ntf_tensor& T, int num_cus) {
+// The row-slab kernel applies to bfloat16 modes before the last (order >= 3, r <= 64: two N
+// tiles keep the accumulators, the batch and its prefetch in 256 registers) when the
+// tensor's rows and runs are 16-byte aligned, the innermost u mode has at least 16 values
+// and the LDS blocks fit; returns the LDS bytes, or 0 where it does not apply.
+static size_t slab_lds(const MttkrpPlan& pl, const ntf_tensor& T) {
   const int N = T.order;
   const int n = pl.v.mode;
-  // (r <= 64: two N tiles keep the accumulators, the batch and its prefetch in 256 registers)
-  if (pl.dtype != NTF_BF16 || pl.layout != 0 || pl.store_y || pl.variant > 2 || N < 3) return;
-  if (!vec_loads(pl) || (pl.v.R * 2) % (int64_t(1) << 20) != 0) return;
+  if (pl.dtype != NTF_BF16 || pl.layout != 0 || pl.store_y || pl.variant > 2 || N < 3) return 0;
+  if (!vec_loads(pl)) return 0;
   const int inner = n < N - 2 ? N - 2 : N - 3;
   const int64_t I_in = T.dims[inner];
-  if (I_in < 16) return;
+  if (I_in < 16) return 0;
   const int64_t vb = ceil_div(pl.Iv, int64_t(64)) * 64;
   const size_t lds = align_up(size_t(pl.rpad) * (vb + 8) * 2, 16) + size_t(I_in) * pl.rpad * 4 +
                      size_t(kThreads / 64) * pl.rpad * 4;
-  if (lds > 72 * 1024) return;
+  return lds > 72 * 1024 ? 0 : lds;
+}
+
+// Switch a plan to the row-slab kernel. By default the planner does so when the row stride
+// is a multiple of 1 MiB (rows that share DRAM banks); a tuned choice decides otherwise.
+static void plan_slab(MttkrpPlan& pl, const ntf_tensor& T, int num_cus,
+                      const MttkrpChoice* choice) {
+  if (choice && choice->kernel == 1) return;
+  const size_t lds = slab_lds(pl, T);
+  if (lds == 0) return;
+  const bool forced = choice && choice->kernel == 2;
+  if (!forced && (pl.v.R * 2) % (int64_t(1) << 20) != 0) return;
+  const int N = T.order;
+  const int inner = pl.v.mode < N - 2 ? N - 2 : N - 3;
+  const int64_t I_in = T.dims[inner];
+  const int64_t vb = ceil_div(pl.Iv, int64_t(64)) * 64;
   SlabFn fn = select_slab(pl.variant);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -944,7 +958,8 @@ static void plan_slab(MttkrpPlan& pl, const ntf_tensor& T, int num_cus) {
   pl.lds = lds;
 }
 
-MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus, bool store_y) {
+MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus, bool store_y,
+                       const MttkrpChoice* choice) {
   MttkrpPlan pl;
   pl.store_y = store_y;
   pl.v = make_mode_view(T, mode);
@@ -976,6 +991,9 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus, bool s
       pl.wm = wm;
     }
   }
+  if (choice && choice->kernel == 1 && !store_y &&
+      (choice->wm == 1 || choice->wm == 2 || choice->wm == 4) && choice->wm >= wm_min)
+    pl.wm = choice->wm;
   // Y rows are whole only when one wave covers every v chunk of its u: the WK waves of a
   // row tile take interleaved u values instead of interleaved v chunks
   pl.uk = store_y;
@@ -1014,8 +1032,33 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus, bool s
     pl.ub = int(std::max<int64_t>(1, std::min<int64_t>({per, int64_t(8192 / pl.rpad), pl.U})));
   }
   pl.lds = std::max(lds_bytes(bf16, last, pl.rpad, pl.vb, pl.ub), red);
-  plan_slab(pl, T, num_cus);
+  if (!store_y) plan_slab(pl, T, num_cus, choice);
   return pl;
+}
+
+int mttkrp_candidates(const ntf_tensor& T, int mode, int r, MttkrpChoice* out, int cap) {
+  // same rules as plan_mttkrp: rank above 64 or a bf16 last mode needs tiles of 2+ waves
+  const bool last = mode == T.order - 1;
+  const int wm_min = (n_tiles(r) >= 4 || (T.dtype == NTF_BF16 && last)) ? 2 : 1;
+  int n = 0;
+  for (int wm : {4, 2, 1})
+    if (wm >= wm_min && n < cap) out[n++] = MttkrpChoice{1, wm};
+  MttkrpPlan pl = plan_mttkrp(T, mode, r, 1, false, &out[0]);
+  if (slab_lds(pl, T) > 0 && n < cap) out[n++] = MttkrpChoice{2, 0};
+  return n;
+}
+
+std::string tune_key(const ntf_tensor& T, int mode, int r) {
+  std::string k = T.dtype == NTF_BF16 ? "bf16" : "f32";
+  for (int l = 0; l < T.order; ++l) k += (l ? "x" : ":") + std::to_string(T.dims[l]);
+  k += ":mode" + std::to_string(mode) + ":r" + std::to_string(r);
+  return k;
+}
+
+const MttkrpChoice* tuned_choice(const ntf_handle* h, const ntf_tensor& T, int mode, int r) {
+  if (h->tune.empty()) return nullptr;
+  const auto it = h->tune.find(tune_key(T, mode, r));
+  return it == h->tune.end() ? nullptr : &it->second;
 }
 
 static hipError_t launch_slab(const MttkrpPlan& pl, const void* T, const FactorPtrs& A, float* P,

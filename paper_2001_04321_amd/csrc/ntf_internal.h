@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstdint>
+#include <map>
+#include <string>
 #include <type_traits>
 
 #include "ntf.h"
@@ -79,6 +81,14 @@ struct Arena {
 
 struct SolveGraph;  // defined in solve.hip
 
+// MTTKRP shape choice, as picked by the autotuner: the kernel family (0 = the planner's
+// default, 1 = row tiles, 2 = row slab) and, for row tiles, the waves along rows (tile
+// height 32 * wm; 0 = the planner's default).
+struct MttkrpChoice {
+  int kernel = 0;
+  int wm = 0;
+};
+
 }  // namespace ntf
 
 struct ntf_handle {
@@ -99,6 +109,8 @@ struct ntf_handle {
   hipEvent_t bstage_done = nullptr;
   hipGraphExec_t bgraph = nullptr;
   unsigned char bgraph_key[160] = {};
+  // MTTKRP tuning table: key (tensor shape, dtype, mode, rank) -> shape choice
+  std::map<std::string, ntf::MttkrpChoice> tune;
 };
 
 namespace ntf {
@@ -148,8 +160,15 @@ struct MttkrpPlan {
   int64_t splits;  // splits of the work items (grid.y)
   size_t partial_floats() const { return splits > 1 ? size_t(splits) * v.I * r : 0; }
 };
+// `choice` (may be NULL) overrides the planner's default shape where it applies.
 MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus,
-                       bool store_y = false);
+                       bool store_y = false, const MttkrpChoice* choice = nullptr);
+// Shapes the planner can take for this mode (what the autotuner times), at most `cap`.
+int mttkrp_candidates(const ntf_tensor& T, int mode, int r, MttkrpChoice* out, int cap);
+// Key of the tuning table for (T's shape and dtype, mode, r).
+std::string tune_key(const ntf_tensor& T, int mode, int r);
+// The handle's tuned choice for this key, or NULL.
+const MttkrpChoice* tuned_choice(const ntf_handle* h, const ntf_tensor& T, int mode, int r);
 // MTTKRP. With one split the kernel writes P (I x r) directly. With several it writes
 // plan.partial_floats() floats of split partials; if `reduce` is set a second kernel sums
 // them into P in a fixed order, otherwise the caller (A-HALS) consumes the partials.

@@ -251,7 +251,7 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
   }
   MttkrpPlan plans[kMaxOrder];
   for (int n = 0; n < N; ++n) {
-    plans[n] = plan_mttkrp(*T, n, r, h->num_cus);
+    plans[n] = plan_mttkrp(*T, n, r, h->num_cus, false, tuned_choice(h, *T, n, r));
     NTF_RETURN_IF(plans[n].chunks >= (int64_t(1) << 31), NTF_EUNSUPPORTED, "reduction too long");
   }
   MttkrpPlan plan_y{};

@@ -63,10 +63,14 @@ def test_null_handle_is_rejected_without_device_work(lib):
         lambda: lib.ntf_solve(None, C.byref(T), 4, None, C.byref(p), 10, None, 0, None, None),
         lambda: lib.ntf_residual_norm2(None, C.byref(T), None, 4, None, None),
         lambda: lib.ntf_cast_bf16(None, None, None, 4, None),
+        lambda: lib.ntf_mttkrp_autotune(None, C.byref(T), None, 4, 0, None, 3, None, None,
+                                        None, None),
+        lambda: lib.ntf_tune_import(None, b"f32:4x4x4:mode0:r4 1 4\n"),
     ]
     for call in calls:
         assert call() == _abi.NTF_EINVAL
         assert b"handle" in lib.ntf_last_error()
+    assert lib.ntf_tune_export(None, None, 0) == -1
 
 
 def test_handle_create_rejects_bad_pointer(lib):
