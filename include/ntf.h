@@ -149,6 +149,17 @@ ntf_status ntf_cast_bf16(ntf_handle* h, const float* src, uint16_t* dst, int64_t
 ntf_status ntf_mttkrp(ntf_handle* h, const ntf_tensor* T, const float* const* A, int32_t r,
                       int32_t mode, float* P, void* stream);
 
+/* The MTTKRPs of every mode n with bit n of `mask` set, all with the same factors (the
+ * partial derivatives of the objective for every block at one point, Sec. 2, eq.
+ * def:grad), in as few passes over T as the shapes allow: for a 3-way tensor the first
+ * two modes share one pass that forms Y = T x_3 A_3 (I_1 x I_2 x r, kept in the handle's
+ * workspace when it is smaller than T) and two folds of Y. A: `order` device pointers (a
+ * factor may be NULL only if its mode is the only one requested); P: host array of
+ * `order` device pointers, P[n] (I_n x r float32) written for the requested modes, others
+ * ignored. Results equal ntf_mttkrp's up to the order of float32 summation. */
+ntf_status ntf_mttkrp_multi(ntf_handle* h, const ntf_tensor* T, const float* const* A,
+                            int32_t r, int32_t mask, float* const* P, void* stream);
+
 /* MTTKRP autotuner. Times every kernel shape the planner can take for mode `mode` of a
  * tensor of T's shape, dtype and rank r (row tiles of 32, 64 or 128 rows; the row-slab
  * kernel where it applies), `reps` calls each after one warm-up, with HIP events on

@@ -4,7 +4,8 @@ Every function here marshals torch tensors (device memory, current stream) into 
 declared in include/ntf.h and calls it; all arithmetic runs in the library's HIP kernels.
 There is no CPU fallback: if libntf.so is missing the import of a call raises.
 
-Functions carry the C names: ntf_norm2, ntf_cast_bf16, ntf_mttkrp, ntf_mttkrp_autotune,
+Functions carry the C names: ntf_norm2, ntf_cast_bf16, ntf_mttkrp, ntf_mttkrp_multi,
+ntf_mttkrp_autotune,
 ntf_tune_export, ntf_tune_import, ntf_gram, ntf_hals_update, ntf_her_step, ntf_error,
 ntf_solve, ntf_residual_norm2, ntf_cp_loss, ntf_cp_grad, ntf_solve_batched, plus the
 autograd loss `NTFLoss` / `ntf_loss` (module `autograd`) and a JSON file for the tuning
@@ -25,7 +26,7 @@ __all__ = [
     "ntf_gram", "ntf_hals_update", "ntf_her_step", "ntf_error", "ntf_solve",
     "ntf_residual_norm2", "ntf_device_flags", "new_state", "state_dict", "ntf_cp_loss",
     "ntf_cp_grad", "NTFLoss", "ntf_loss", "ntf_solve_batched", "ntf_mttkrp_autotune",
-    "ntf_tune_export", "ntf_tune_import", "save_tuning", "load_tuning",
+    "ntf_tune_export", "ntf_tune_import", "save_tuning", "load_tuning", "ntf_mttkrp_multi",
 ]
 
 _DTYPES = {torch.float32: _abi.NTF_F32, torch.bfloat16: _abi.NTF_BF16}
@@ -145,6 +146,22 @@ def ntf_mttkrp(T: torch.Tensor, factors, mode: int, out: torch.Tensor | None = N
                       for l, A in enumerate(factors)])
     check(lib().ntf_mttkrp(_h(h), C.byref(d), ptrs, r, int(mode), _dev(out, "P", torch.float32),
                            _stream(stream)))
+    return out
+
+
+def ntf_mttkrp_multi(T: torch.Tensor, factors, modes, h=None, stream=None) -> dict:
+    """MTTKRPs of several modes with the same factors ({mode: P}); a 3-way tensor's first two
+    modes share one pass over T."""
+    N = T.dim()
+    modes = sorted(set(int(m) for m in modes))
+    r = int(next(f for f in factors if f is not None).shape[1])
+    out = {n: torch.empty((T.shape[n], r), dtype=torch.float32, device=T.device) for n in modes}
+    d = _tensor_desc(T)
+    ptrs = ptr_array([(_dev(A, f"A[{l}]", torch.float32) if A is not None else None)
+                      for l, A in enumerate(factors)])
+    P = ptr_array([out[n].data_ptr() if n in out else None for n in range(N)])
+    mask = sum(1 << n for n in modes)
+    check(lib().ntf_mttkrp_multi(_h(h), C.byref(d), ptrs, r, mask, P, _stream(stream)))
     return out
 
 

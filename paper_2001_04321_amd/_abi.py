@@ -80,6 +80,8 @@ SIGNATURES = {
                                       C.POINTER(C.c_int32), C.POINTER(C.c_float), PTR]),
     "ntf_tune_export": (C.c_int64, [PTR, C.c_char_p, C.c_int64]),
     "ntf_tune_import": (C.c_int, [PTR, C.c_char_p]),
+    "ntf_mttkrp_multi": (C.c_int, [PTR, C.POINTER(NtfTensor), PTRS, C.c_int32, C.c_int32, PTRS,
+                                   PTR]),
 }
 
 _lib = None

@@ -259,6 +259,67 @@ ntf_status ntf_mttkrp(ntf_handle* h, const ntf_tensor* T, const float* const* A,
   return NTF_OK;
 }
 
+ntf_status ntf_mttkrp_multi(ntf_handle* h, const ntf_tensor* T, const float* const* A,
+                            int32_t r, int32_t mask, float* const* P, void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_tensor(T);
+  if (st) return st;
+  if ((st = check_rank(r))) return st;
+  const int N = T->order;
+  NTF_RETURN_IF(mask <= 0 || mask >= (1 << N), NTF_EINVAL, "mode mask %d outside [1, 2^%d)",
+                mask, N);
+  NTF_RETURN_IF(!A || !P, NTF_EINVAL, "factor or output array is NULL");
+  // every factor is read by some requested mode unless only that factor's mode is requested
+  FactorPtrs fp{};
+  for (int l = 0; l < N; ++l) {
+    NTF_RETURN_IF(!A[l] && (mask & ~(1 << l)) != 0, NTF_EINVAL, "factor %d is NULL", l);
+    fp.p[l] = A[l] ? A[l] : A[(l + 1) % N];
+    NTF_RETURN_IF(((mask >> l) & 1) && !P[l], NTF_EINVAL, "output %d is NULL", l);
+  }
+  MttkrpPlan plans[kMaxOrder];
+  size_t need = 0;
+  for (int n = 0; n < N; ++n) {
+    if (!((mask >> n) & 1)) continue;
+    plans[n] = plan_mttkrp(*T, n, r, h->num_cus, false, tuned_choice(h, *T, n, r));
+    NTF_RETURN_IF(plans[n].chunks >= (int64_t(1) << 31), NTF_EUNSUPPORTED,
+                  "reduction too long");
+    need = std::max(need, plans[n].partial_floats());
+  }
+  // 3-way, modes 1 and 2 both asked: one pass forms Y = T x_3 A_3, two folds finish them
+  MttkrpPlan plan_y{};
+  bool shared = false;
+  if (N == 3 && (mask & 3) == 3) {
+    plan_y = plan_mttkrp(*T, 0, r, h->num_cus, true);
+    shared = use_shared_y(*T, r, plan_y) && plan_y.chunks < (int64_t(1) << 31);
+  }
+  Arena dry;
+  float* part = nullptr;
+  float* Y = nullptr;
+  if (shared)
+    need = std::max<size_t>(need, size_t(fold_i_splits(T->dims[0], T->dims[1], r)) *
+                                      T->dims[1] * r);
+  dry.take<float>(std::max<size_t>(need, 1));
+  if (shared) dry.take<float>(size_t(T->dims[0]) * T->dims[1] * r + 64);
+  if ((st = ensure_workspace(h, dry.off + 256))) return st;
+  Arena ar{h->ws, 0};
+  part = ar.take<float>(std::max<size_t>(need, 1));
+  if (shared) Y = ar.take<float>(size_t(T->dims[0]) * T->dims[1] * r + 64);
+  hipStream_t s = as_stream(stream);
+  for (int n = 0; n < N; ++n) {
+    if (!((mask >> n) & 1)) continue;
+    if (shared && n == 0) {
+      NTF_HIP(launch_mttkrp(plan_y, T->data, fp, P[0], part, true, s, Y));
+      NTF_HIP(launch_fold_u(Y, A[1], T->dims[0], T->dims[1], r, P[0], s));
+    } else if (shared && n == 1) {
+      NTF_HIP(launch_fold_i(Y, A[0], T->dims[0], T->dims[1], r, part, P[1], s));
+    } else {
+      NTF_HIP(launch_mttkrp(plans[n], T->data, fp, P[n], part, true, s));
+    }
+  }
+  return NTF_OK;
+}
+
 ntf_status ntf_mttkrp_autotune(ntf_handle* h, const ntf_tensor* T, const float* const* A,
                                int32_t r, int32_t mode, float* P, int32_t reps,
                                int32_t* kernel_out, int32_t* wm_out, float* ms_out,

@@ -185,6 +185,9 @@ hipError_t launch_mttkrp(const MttkrpPlan& plan, const void* T, const FactorPtrs
 hipError_t launch_fold_u(const float* Y, const float* X, int64_t I, int64_t U, int r, float* P,
                          hipStream_t s);
 int64_t fold_i_splits(int64_t I, int64_t U, int r);
+// 3-way tensors: whether the mode-1 and mode-2 MTTKRPs share one pass through Y (Y smaller
+// than the tensor and A_3 in one LDS block of the store-Y plan `plan_y`).
+bool use_shared_y(const ntf_tensor& T, int r, const MttkrpPlan& plan_y);
 hipError_t launch_fold_i(const float* Y, const float* X, int64_t I, int64_t U, int r,
                          float* partials, float* P, hipStream_t s,
                          const HadamardLaunch* had = nullptr);

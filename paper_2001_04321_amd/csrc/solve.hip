@@ -65,16 +65,6 @@ struct SolveBufs {
   int64_t nerr;
 };
 
-// 3-way tensors: the mode-1 and mode-2 MTTKRPs share Y = T x_3 A-hat^(3) (A-hat^(3) does not
-// change before the mode-3 update), so the tensor is streamed twice per iteration instead of
-// three times. Used when Y is smaller than the tensor and A_3 fits one LDS block.
-bool use_shared_y(const ntf_tensor& T, int r, const MttkrpPlan& plan_y) {
-  if (T.order != 3 || plan_y.nvb != 1) return false;
-  const int64_t s = T.dtype == NTF_BF16 ? 2 : 4;
-  const int64_t ybytes = T.dims[0] * T.dims[1] * int64_t(r) * 4;
-  return ybytes < T.dims[0] * T.dims[1] * T.dims[2] * s;
-}
-
 void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
            const MttkrpPlan* plans, bool own_state, bool shared_y) {
   const int N = T.order;
@@ -207,6 +197,16 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
 }
 
 }  // namespace
+
+// 3-way tensors: the mode-1 and mode-2 MTTKRPs share Y = T x_3 A-hat^(3) (A-hat^(3) does not
+// change before the mode-3 update), so the tensor is streamed twice per iteration instead of
+// three times. Used when Y is smaller than the tensor and A_3 fits one LDS block.
+bool use_shared_y(const ntf_tensor& T, int r, const MttkrpPlan& plan_y) {
+  if (T.order != 3 || plan_y.nvb != 1) return false;
+  const int64_t s = T.dtype == NTF_BF16 ? 2 : 4;
+  const int64_t ybytes = T.dims[0] * T.dims[1] * int64_t(r) * 4;
+  return ybytes < T.dims[0] * T.dims[1] * T.dims[2] * s;
+}
 
 void release_solve_graph(ntf_handle* h) {
   if (!h->graph) return;

@@ -106,6 +106,28 @@ def test_mttkrp_row_slab_modes(ntf, dims, r, mode):
     assert err <= 2e-2
 
 
+@pytest.mark.parametrize("dims,r,dtype,modes", [
+    ((70, 90, 110), 24, "f32", (0, 1)), ((70, 90, 110), 24, "bf16", (0, 1, 2)),
+    ((70, 90, 110), 24, "f32", (2,)), ((20, 20, 8), 40, "f32", (0, 1, 2)),
+    ((9, 8, 7, 6), 5, "f32", (0, 1, 2, 3)), ((60, 50, 40), 70, "bf16", (0, 1))])
+def test_mttkrp_multi(ntf, dims, r, dtype, modes):
+    """Several modes with the same factors in one call (3-way: the first two modes through
+    Y = T x_3 A_3 when Y is smaller than T; (20, 20, 8) r = 40 is not)."""
+    g = np.random.default_rng(5)
+    T = g.random(dims).astype(np.float32)
+    A = [g.random((I, r)).astype(np.float32) for I in dims]
+    Td, T64 = dev_tensor(T, dtype)
+    Ad = [dev_f32(a) for a in A]
+    A64 = [a.astype(np.float64) for a in A]
+    out = ntf.ntf_mttkrp_multi(Td, Ad, modes)
+    assert sorted(out) == sorted(modes)
+    tol = 1e-5 if dtype == "f32" else 2e-2
+    for n, P in out.items():
+        err = rel_fro(to_np(P), oracle.mttkrp(T64, A64, n))
+        print(f"multi {dtype} dims={dims} r={r} mode={n} relerr={err:.3e}")
+        assert err <= tol, (n, err)
+
+
 FULL = [("cube400_r32_corr", "f32"), ("cube400_r32_corr", "bf16"),
         ("quad128_r64_sparse", "bf16"), ("cube512_r50", "f32")]
 
