@@ -156,7 +156,11 @@ ntf_status ntf_mttkrp(ntf_handle* h, const ntf_tensor* T, const float* const* A,
  * workspace when it is smaller than T) and two folds of Y. A: `order` device pointers (a
  * factor may be NULL only if its mode is the only one requested); P: host array of
  * `order` device pointers, P[n] (I_n x r float32) written for the requested modes, others
- * ignored. Results equal ntf_mttkrp's up to the order of float32 summation. */
+ * ignored. A 4-way bfloat16 tensor whose last two modes have 128 indices, with r <= 64 and
+ * all four modes asked, takes a fused kernel that reads T once: per slab T(i, j, :, :) two
+ * matrix-core products (with A_4 and with A_3) give the last two MTTKRPs and an
+ * I_1 x I_2 x r array that two folds turn into the first two. Results equal
+ * ntf_mttkrp's up to the order of float32 summation. */
 ntf_status ntf_mttkrp_multi(ntf_handle* h, const ntf_tensor* T, const float* const* A,
                             int32_t r, int32_t mask, float* const* P, void* stream);
 

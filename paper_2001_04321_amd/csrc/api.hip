@@ -277,6 +277,14 @@ ntf_status ntf_mttkrp_multi(ntf_handle* h, const ntf_tensor* T, const float* con
     fp.p[l] = A[l] ? A[l] : A[(l + 1) % N];
     NTF_RETURN_IF(((mask >> l) & 1) && !P[l], NTF_EINVAL, "output %d is NULL", l);
   }
+  // 4-way bf16, every mode asked: the fused one-pass kernel where its shape applies
+  if (mask == 15 && fused4_applies(*T, r)) {
+    if ((st = ensure_workspace(h, fused4_workspace_floats(*T, r, h->num_cus) * 4 + 256)))
+      return st;
+    NTF_HIP(launch_fused4(*T, A, r, h->num_cus, P, reinterpret_cast<float*>(h->ws),
+                          as_stream(stream)));
+    return NTF_OK;
+  }
   MttkrpPlan plans[kMaxOrder];
   size_t need = 0;
   for (int n = 0; n < N; ++n) {

@@ -731,6 +731,194 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_slab_kernel(SArgs k) {
   }
 }
 
+// ---- Fused all-mode MTTKRP of a 4-way bfloat16 tensor (modes 3 and 4 of size 128) ----
+// Every mode's MTTKRP with the same factors A_1..A_4 in one pass over T (the gradient of the
+// objective at one point, Sec. 2, eq. def:grad). T is a sequence of slabs M_ij = T(i, j, :, :)
+// (128 x 128, 32 KB). Per slab, on matrix cores:
+//   Z = M_ij A_4      (rows k of M, K = l),   U = M_ij^T A_3   (rows l, K = k),
+// and in float32 registers, with ab[p] = A_1[i, p] A_2[j, p]:
+//   P_3[k, p] += ab[p] Z[k, p],   P_4[l, p] += ab[p] U[l, p],
+//   W[i, j, p] = sum_k A_3[k, p] Z[k, p],
+// after which P_1 = sum_j A_2[j, p] W[i, j, p] and P_2 = sum_i A_1[i, p] W[i, j, p] are the
+// two folds of W used by the 3-way solver. 4r flops of MFMA per tensor element instead of
+// 8r for four MTTKRPs; T is read once. A workgroup takes slabs gridDim.x apart, holds the
+// slab in LDS (rows padded to 136 elements), prefetches the next one into registers, and
+// writes its P_3 and P_4 sums as split partials that the fixed-order reduction adds.
+struct F4Args {
+  const uint16_t* T;
+  const float* A1;
+  const float* A2;
+  const float* A3;
+  const float* A4;
+  float* W;      // I_1 x I_2 x r
+  float* part3;  // [nwg][128][r]
+  float* part4;  // [nwg][128][r]
+  int64_t I2, nslab;
+  int r;
+};
+
+constexpr int kF4Ld = 136;  // LDS row stride (elements) of the slab and the factor blocks
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
+  return __uint_as_float(uint32_t(b) << 16);
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads, 2) void mttkrp_fused4_kernel(F4Args k) {
+  constexpr int RP = 32 * NT;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  uint16_t* s_m = reinterpret_cast<uint16_t*>(smem);       // [128][kF4Ld]
+  uint16_t* s_d = s_m + 128 * kF4Ld;                        // A_4 as [p][l]
+  uint16_t* s_c = s_d + RP * kF4Ld;                         // A_3 as [p][k]
+  float* s_w = reinterpret_cast<float*>(s_c + RP * kF4Ld);  // [2][4][RP]
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int col = lane & 31;
+  const int half = lane >> 5;
+  const int64_t stride = gridDim.x;
+
+  for (int e = tid; e < 128 * RP; e += kThreads) {
+    const int x = e / RP;
+    const int p = e - x * RP;
+    s_d[p * kF4Ld + x] = f2bf(p < k.r ? k.A4[x * k.r + p] : 0.f);
+    s_c[p * kF4Ld + x] = f2bf(p < k.r ? k.A3[x * k.r + p] : 0.f);
+  }
+
+  // slab s: thread tid loads 16-byte chunks q = tid + 256 t (row q / 16, 8 elements each)
+  uint4 pf[8];
+  auto load_slab = [&](int64_t s) {
+    const bool ok = s < k.nslab;
+    const uint4* src = reinterpret_cast<const uint4*>(k.T + (ok ? s : 0) * 16384);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) pf[t] = ok ? src[tid + 256 * t] : make_uint4(0, 0, 0, 0);
+  };
+
+  f32x16 acc3[NT], acc4[NT], z[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      acc3[nt][e] = 0.f;
+      acc4[nt][e] = 0.f;
+    }
+
+  int64_t s = blockIdx.x;
+  load_slab(s);
+  int64_t prev = -1;
+  int par = 0;
+  for (; s < k.nslab; s += stride) {
+    lds_barrier();  // every wave is done with the previous slab in LDS
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int q = tid + 256 * t;
+      *reinterpret_cast<uint4*>(&s_m[(q >> 4) * kF4Ld + (q & 15) * 8]) = pf[t];
+    }
+    lds_barrier();
+    // W of the previous slab: the four waves' sums in order
+    if (prev >= 0 && tid < k.r) {
+      const float* w = s_w + (par ^ 1) * 4 * RP;
+      k.W[prev * k.r + tid] = ((w[tid] + w[RP + tid]) + w[2 * RP + tid]) + w[3 * RP + tid];
+    }
+    load_slab(s + stride);
+    const int64_t i = s / k.I2;
+    const int64_t j = s - i * k.I2;
+    float ab[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int p = nt * 32 + col;
+      ab[nt] = p < k.r ? k.A1[i * k.r + p] * k.A2[j * k.r + p] : 0.f;
+    }
+    // Z = M A_4 for this wave's rows k = 32 wave + [0, 32)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) z[nt][e] = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const bf16x8 a =
+          *reinterpret_cast<const bf16x8*>(&s_m[(32 * wave + col) * kF4Ld + c * 16 + half * 8]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const bf16x8 b =
+            *reinterpret_cast<const bf16x8*>(&s_d[(nt * 32 + col) * kF4Ld + c * 16 + half * 8]);
+        z[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, z[nt], 0, 0, 0);
+      }
+    }
+    // P_3 += ab Z; this wave's share of W = sum_k A_3[k, p] Z[k, p]
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int p = nt * 32 + col;
+      float w = 0.f;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int kk = 32 * wave + 8 * (e >> 2) + half * 4 + (e & 3);
+        w = fmaf(bf16_bits_to_f32(s_c[p * kF4Ld + kk]), z[nt][e], w);
+        acc3[nt][e] = fmaf(ab[nt], z[nt][e], acc3[nt][e]);
+      }
+      const float o = __shfl_xor(w, 32);
+      if (half == 0) s_w[(par * 4 + wave) * RP + p] = w + o;
+    }
+    // U = M^T A_3 for this wave's rows l = 32 wave + [0, 32): transposing LDS reads of the
+    // slab give each lane 8 consecutive k of its column l
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) z[nt][e] = 0.f;
+    {
+      const int g = lane >> 4;
+      const int m0 = 16 * (g & 1);
+      const int src = lane & 15;
+      const int jj = src >> 2;
+      const int s4 = (src & 3) * 4;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int kq = 16 * c + 8 * (g >> 1);
+        union {
+          i16x4 h[2];
+          bf16x8 v;
+        } a;
+        a.h[0] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (lds_i16x4*)(&s_m[(kq + jj) * kF4Ld + 32 * wave + m0 + s4]));
+        a.h[1] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (lds_i16x4*)(&s_m[(kq + 4 + jj) * kF4Ld + 32 * wave + m0 + s4]));
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const bf16x8 b = *reinterpret_cast<const bf16x8*>(
+              &s_c[(nt * 32 + col) * kF4Ld + 16 * c + 8 * half]);
+          z[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, b, z[nt], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc4[nt][e] = fmaf(ab[nt], z[nt][e], acc4[nt][e]);
+    prev = s;
+    par ^= 1;
+  }
+  __syncthreads();
+  if (prev >= 0 && tid < k.r) {
+    const float* w = s_w + (par ^ 1) * 4 * RP;
+    k.W[prev * k.r + tid] = ((w[tid] + w[RP + tid]) + w[2 * RP + tid]) + w[3 * RP + tid];
+  }
+  // this workgroup's P_3 and P_4 sums (rows 32 wave + row of the accumulator register)
+  float* o3 = k.part3 + int64_t(blockIdx.x) * 128 * k.r;
+  float* o4 = k.part4 + int64_t(blockIdx.x) * 128 * k.r;
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int p = nt * 32 + col;
+    if (p >= k.r) continue;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int row = 32 * wave + 8 * (e >> 2) + half * 4 + (e & 3);
+      o3[row * k.r + p] = acc3[nt][e];
+      o4[row * k.r + p] = acc4[nt][e];
+    }
+  }
+}
+
 // Fixed-order sum of split partials: each output element is summed by 4 threads over
 // interleaved splits (float64), then combined in thread order.
 __global__ __launch_bounds__(256) void mttkrp_reduce_kernel(const float* __restrict__ part,
@@ -1175,6 +1363,75 @@ hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& 
     e = hipGetLastError();
   }
   return e;
+}
+
+bool fused4_applies(const ntf_tensor& T, int r) {
+  return T.order == 4 && T.dtype == NTF_BF16 && T.dims[2] == 128 && T.dims[3] == 128 &&
+         r <= 64 && (reinterpret_cast<uintptr_t>(T.data) & 15) == 0 &&
+         T.dims[0] * T.dims[1] < (int64_t(1) << 31);
+}
+
+static int fused4_grid(const ntf_tensor& T, int r, int num_cus, size_t* lds_out) {
+  const int rp = r <= 32 ? 32 : 64;
+  const size_t lds = size_t(128) * kF4Ld * 2 + size_t(2) * rp * kF4Ld * 2 + size_t(8) * rp * 4;
+  const void* fn = rp == 32 ? reinterpret_cast<const void*>(mttkrp_fused4_kernel<1>)
+                            : reinterpret_cast<const void*>(mttkrp_fused4_kernel<2>);
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  if (lds_out) *lds_out = lds;
+  return int(std::max<int64_t>(1, std::min<int64_t>(int64_t(per_cu) * num_cus,
+                                                    T.dims[0] * T.dims[1])));
+}
+
+size_t fused4_workspace_floats(const ntf_tensor& T, int r, int num_cus) {
+  const int64_t nwg = fused4_grid(T, r, num_cus, nullptr);
+  const int64_t I1 = T.dims[0], I2 = T.dims[1];
+  return size_t(align_up(size_t(I1 * I2 * r), 64) + 2 * align_up(size_t(nwg * 128 * r), 64) +
+                align_up(size_t(fold_i_splits(I1, I2, r) * I2 * r), 64));
+}
+
+hipError_t launch_fused4(const ntf_tensor& T, const float* const* A, int r, int num_cus,
+                         float* const* P, float* ws, hipStream_t s) {
+  size_t lds = 0;
+  const int nwg = fused4_grid(T, r, num_cus, &lds);
+  const int64_t I1 = T.dims[0], I2 = T.dims[1];
+  F4Args k{};
+  k.T = static_cast<const uint16_t*>(T.data);
+  k.A1 = A[0];
+  k.A2 = A[1];
+  k.A3 = A[2];
+  k.A4 = A[3];
+  k.W = ws;
+  k.part3 = ws + align_up(size_t(I1 * I2 * r), 64);
+  k.part4 = k.part3 + align_up(size_t(int64_t(nwg) * 128 * r), 64);
+  float* fpart = k.part4 + align_up(size_t(int64_t(nwg) * 128 * r), 64);
+  k.I2 = I2;
+  k.nslab = I1 * I2;
+  k.r = r;
+  if (r <= 32)
+    hipLaunchKernelGGL(mttkrp_fused4_kernel<1>, dim3(nwg), dim3(kThreads), lds, s, k);
+  else
+    hipLaunchKernelGGL(mttkrp_fused4_kernel<2>, dim3(nwg), dim3(kThreads), lds, s, k);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n34 = int64_t(128) * r;
+  const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(ceil_div(n34, 64), 4096)));
+  if (P[2]) {
+    hipLaunchKernelGGL(mttkrp_reduce_kernel, dim3(blocks), dim3(256), 0, s, k.part3,
+                       int64_t(nwg), n34, P[2]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (P[3]) {
+    hipLaunchKernelGGL(mttkrp_reduce_kernel, dim3(blocks), dim3(256), 0, s, k.part4,
+                       int64_t(nwg), n34, P[3]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (P[0] && (e = launch_fold_u(k.W, A[1], I1, I2, r, P[0], s)) != hipSuccess) return e;
+  if (P[1] && (e = launch_fold_i(k.W, A[0], I1, I2, r, fpart, P[1], s)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
 hipError_t launch_fold_u(const float* Y, const float* X, int64_t I, int64_t U, int r, float* P,

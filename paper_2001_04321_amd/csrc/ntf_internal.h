@@ -185,6 +185,13 @@ hipError_t launch_mttkrp(const MttkrpPlan& plan, const void* T, const FactorPtrs
 hipError_t launch_fold_u(const float* Y, const float* X, int64_t I, int64_t U, int r, float* P,
                          hipStream_t s);
 int64_t fold_i_splits(int64_t I, int64_t U, int r);
+// Fused all-mode MTTKRP of a 4-way bf16 tensor with modes 3 and 4 of size 128 and r <= 64:
+// one pass over T; P[n] (NULL: not wanted) receive the four MTTKRPs. `ws` holds
+// fused4_workspace_floats() floats.
+bool fused4_applies(const ntf_tensor& T, int r);
+size_t fused4_workspace_floats(const ntf_tensor& T, int r, int num_cus);
+hipError_t launch_fused4(const ntf_tensor& T, const float* const* A, int r, int num_cus,
+                         float* const* P, float* ws, hipStream_t s);
 // 3-way tensors: whether the mode-1 and mode-2 MTTKRPs share one pass through Y (Y smaller
 // than the tensor and A_3 in one LDS block of the store-Y plan `plan_y`).
 bool use_shared_y(const ntf_tensor& T, int r, const MttkrpPlan& plan_y);

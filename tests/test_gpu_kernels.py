@@ -109,10 +109,14 @@ def test_mttkrp_row_slab_modes(ntf, dims, r, mode):
 @pytest.mark.parametrize("dims,r,dtype,modes", [
     ((70, 90, 110), 24, "f32", (0, 1)), ((70, 90, 110), 24, "bf16", (0, 1, 2)),
     ((70, 90, 110), 24, "f32", (2,)), ((20, 20, 8), 40, "f32", (0, 1, 2)),
-    ((9, 8, 7, 6), 5, "f32", (0, 1, 2, 3)), ((60, 50, 40), 70, "bf16", (0, 1))])
+    ((9, 8, 7, 6), 5, "f32", (0, 1, 2, 3)), ((60, 50, 40), 70, "bf16", (0, 1)),
+    ((5, 7, 128, 128), 40, "bf16", (0, 1, 2, 3)), ((3, 4, 128, 128), 20, "bf16", (0, 1, 2, 3)),
+    ((5, 7, 128, 128), 40, "bf16", (0, 2))])
 def test_mttkrp_multi(ntf, dims, r, dtype, modes):
     """Several modes with the same factors in one call (3-way: the first two modes through
-    Y = T x_3 A_3 when Y is smaller than T; (20, 20, 8) r = 40 is not)."""
+    Y = T x_3 A_3 when Y is smaller than T; (20, 20, 8) r = 40 is not; 4-way bf16 with
+    128 x 128 trailing modes and every mode asked: the fused one-pass kernel, in one and
+    two N tiles)."""
     g = np.random.default_rng(5)
     T = g.random(dims).astype(np.float32)
     A = [g.random((I, r)).astype(np.float32) for I in dims]
@@ -126,6 +130,24 @@ def test_mttkrp_multi(ntf, dims, r, dtype, modes):
         err = rel_fro(to_np(P), oracle.mttkrp(T64, A64, n))
         print(f"multi {dtype} dims={dims} r={r} mode={n} relerr={err:.3e}")
         assert err <= tol, (n, err)
+
+
+def test_mttkrp_multi_full_size_quad128(ntf):
+    """The fused all-mode kernel on the 128^4 bf16 r = 64 workload; rows sampled."""
+    pr = synth.workload("quad128_r64_sparse")
+    Td, T64 = dev_tensor(pr.T, "bf16")
+    A = [a.astype(np.float32) for a in pr.A0]
+    del pr
+    out = ntf.ntf_mttkrp_multi(Td, [dev_f32(a) for a in A], (0, 1, 2, 3))
+    A64 = [a.astype(np.float64) for a in A]
+    g = np.random.default_rng(1)
+    for n in range(4):
+        rows = sorted(set([0, 127] + list(g.integers(0, 128, 3))))
+        err = rel_fro(to_np(out[n])[rows], oracle.mttkrp_rows(T64, A64, n, rows))
+        print(f"fused quad128 mode={n} rows={rows} relerr={err:.3e}")
+        assert err <= 2e-2
+    del Td
+    torch.cuda.empty_cache()
 
 
 FULL = [("cube400_r32_corr", "f32"), ("cube400_r32_corr", "bf16"),
