@@ -253,6 +253,17 @@ def bench_quad128(ntf, torch, iters: int, warmup: int, reps: int, autotune: bool
     mt = time_mttkrp(ntf, torch, Td, A, reps)
     n = int(Td.numel())
     tf = [2.0 * r * n / (t / 1e3) / 1e12 for t in mt]
+    # all four modes in one pass (fused kernel, folds and split sums included)
+    ntf.ntf_mttkrp_multi(Td, A, range(4))
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(reps):
+        ntf.ntf_mttkrp_multi(Td, A, range(4))
+    e1.record()
+    torch.cuda.synchronize()
+    fused_ms = e0.elapsed_time(e1) / reps
+    fused_tf = 4 * 2.0 * r * n / (fused_ms / 1e3) / 1e12
     out = dict(workload="quad128_r64_sparse", dims=list(w["dims"]), rank=r, tensor="bf16",
                iters=iters, iters_per_s=round(iters / (ms / 1e3), 2),
                ms_per_iter=round(ms / iters, 4), final_relerr=relerr,
@@ -261,6 +272,10 @@ def bench_quad128(ntf, torch, iters: int, warmup: int, reps: int, autotune: bool
                mttkrp_ms=[round(t, 4) for t in mt], mttkrp_tflops=[round(x, 2) for x in tf],
                mttkrp_gbs=[round(n * 2 / (t / 1e3) / 1e9, 1) for t in mt],
                mttkrp_mfma_frac=[round(x / BF16_MFMA_PEAK_TFLOPS, 4) for x in tf],
+               fused_all_modes={"ms": round(fused_ms, 4), "tflops": round(fused_tf, 1),
+                                "mfma_frac": round(fused_tf / BF16_MFMA_PEAK_TFLOPS, 4),
+                                "tensor_gbs": round(n * 2 / (fused_ms / 1e3) / 1e9, 1),
+                                "vs_four_calls": round(sum(mt) / fused_ms, 3)},
                stream_gbs=round(stream_gbs(ntf, torch, Td), 1), mttkrp_autotune=tuned or None)
     del Td, A, A0
     torch.cuda.empty_cache()

@@ -742,8 +742,8 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_slab_kernel(SArgs k) {
 // after which P_1 = sum_j A_2[j, p] W[i, j, p] and P_2 = sum_i A_1[i, p] W[i, j, p] are the
 // two folds of W used by the 3-way solver. 4r flops of MFMA per tensor element instead of
 // 8r for four MTTKRPs; T is read once. A workgroup takes slabs gridDim.x apart, holds the
-// slab in LDS (rows padded to 136 elements), prefetches the next one into registers, and
-// writes its P_3 and P_4 sums as split partials that the fixed-order reduction adds.
+// slab in LDS (rows padded to 136 elements), keeps the next two in flight into registers,
+// and writes its P_3 and P_4 sums as split partials that the fixed-order reduction adds.
 struct F4Args {
   const uint16_t* T;
   const float* A1;
@@ -754,6 +754,7 @@ struct F4Args {
   float* part3;  // [nwg][128][r]
   float* part4;  // [nwg][128][r]
   int64_t I2, nslab;
+  FastDiv fd_I2;
   int r;
 };
 
@@ -786,9 +787,9 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_fused4_kernel(F4Args k) {
     s_c[p * kF4Ld + x] = f2bf(p < k.r ? k.A3[x * k.r + p] : 0.f);
   }
 
-  // slab s: thread tid loads 16-byte chunks q = tid + 256 t (row q / 16, 8 elements each)
-  uint4 pf[8];
-  auto load_slab = [&](int64_t s) {
+  // slab s: thread tid loads 16-byte chunks q = tid + 256 t (row q / 16, 8 elements each);
+  // two slabs are in flight per workgroup (two register buffers, used alternately)
+  auto load_slab = [&](uint4 (&pf)[8], int64_t s) {
     const bool ok = s < k.nslab;
     const uint4* src = reinterpret_cast<const uint4*>(k.T + (ok ? s : 0) * 16384);
 #pragma unroll
@@ -804,11 +805,9 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_fused4_kernel(F4Args k) {
       acc4[nt][e] = 0.f;
     }
 
-  int64_t s = blockIdx.x;
-  load_slab(s);
   int64_t prev = -1;
   int par = 0;
-  for (; s < k.nslab; s += stride) {
+  auto step = [&](uint4 (&pf)[8], int64_t s) {
     lds_barrier();  // every wave is done with the previous slab in LDS
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -821,20 +820,18 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_fused4_kernel(F4Args k) {
       const float* w = s_w + (par ^ 1) * 4 * RP;
       k.W[prev * k.r + tid] = ((w[tid] + w[RP + tid]) + w[2 * RP + tid]) + w[3 * RP + tid];
     }
-    load_slab(s + stride);
-    const int64_t i = s / k.I2;
-    const int64_t j = s - i * k.I2;
+    load_slab(pf, s + 2 * stride);
+    const uint32_t i = fdiv(uint32_t(s), k.fd_I2);
+    const uint32_t j = uint32_t(s) - i * uint32_t(k.I2);
     float ab[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int p = nt * 32 + col;
       ab[nt] = p < k.r ? k.A1[i * k.r + p] * k.A2[j * k.r + p] : 0.f;
     }
-    // Z = M A_4 for this wave's rows k = 32 wave + [0, 32)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) z[nt][e] = 0.f;
+    // Z = M A_4 for this wave's rows k = 32 wave + [0, 32) (the first product starts from a
+    // zero accumulator operand)
+    const f32x16 zero16 = {};
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const bf16x8 a =
@@ -843,7 +840,7 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_fused4_kernel(F4Args k) {
       for (int nt = 0; nt < NT; ++nt) {
         const bf16x8 b =
             *reinterpret_cast<const bf16x8*>(&s_d[(nt * 32 + col) * kF4Ld + c * 16 + half * 8]);
-        z[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, z[nt], 0, 0, 0);
+        z[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c == 0 ? zero16 : z[nt], 0, 0, 0);
       }
     }
     // P_3 += ab Z; this wave's share of W = sum_k A_3[k, p] Z[k, p]
@@ -862,10 +859,6 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_fused4_kernel(F4Args k) {
     }
     // U = M^T A_3 for this wave's rows l = 32 wave + [0, 32): transposing LDS reads of the
     // slab give each lane 8 consecutive k of its column l
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) z[nt][e] = 0.f;
     {
       const int g = lane >> 4;
       const int m0 = 16 * (g & 1);
@@ -887,7 +880,7 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_fused4_kernel(F4Args k) {
         for (int nt = 0; nt < NT; ++nt) {
           const bf16x8 b = *reinterpret_cast<const bf16x8*>(
               &s_c[(nt * 32 + col) * kF4Ld + 16 * c + 8 * half]);
-          z[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, b, z[nt], 0, 0, 0);
+          z[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, b, c == 0 ? zero16 : z[nt], 0, 0, 0);
         }
       }
     }
@@ -897,6 +890,15 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_fused4_kernel(F4Args k) {
       for (int e = 0; e < 16; ++e) acc4[nt][e] = fmaf(ab[nt], z[nt][e], acc4[nt][e]);
     prev = s;
     par ^= 1;
+  };
+
+  uint4 pf0[8], pf1[8];
+  int64_t s = blockIdx.x;
+  load_slab(pf0, s);
+  load_slab(pf1, s + stride);
+  for (; s < k.nslab; s += 2 * stride) {
+    step(pf0, s);
+    if (s + stride < k.nslab) step(pf1, s + stride);
   }
   __syncthreads();
   if (prev >= 0 && tid < k.r) {
@@ -1409,6 +1411,7 @@ hipError_t launch_fused4(const ntf_tensor& T, const float* const* A, int r, int 
   k.part4 = k.part3 + align_up(size_t(int64_t(nwg) * 128 * r), 64);
   float* fpart = k.part4 + align_up(size_t(int64_t(nwg) * 128 * r), 64);
   k.I2 = I2;
+  k.fd_I2 = make_fastdiv(uint32_t(I2));
   k.nslab = I1 * I2;
   k.r = r;
   if (r <= 32)
