@@ -167,7 +167,8 @@ ntf_status ntf_mttkrp_multi(ntf_handle* h, const ntf_tensor* T, const float* con
 /* MTTKRP autotuner. Times every kernel shape the planner can take for mode `mode` of a
  * tensor of T's shape, dtype and rank r (row tiles of 32, 64 or 128 rows; the row-slab
  * kernel where it applies), `reps` calls each after one warm-up, with HIP events on
- * `stream`, on the caller's T and A; records the fastest in the handle's tuning table,
+ * `stream`, on the caller's T and A; records the fastest in the handle's tuning table
+ * (the planner's default shape is kept unless another is faster by more than 3 %),
  * which later ntf_mttkrp and ntf_solve calls on the same shape, dtype, mode and rank use
  * (a cached solver graph is rebuilt). P (I_mode x r) receives the MTTKRP from the chosen
  * shape. Synchronizes `stream` (not for use under stream capture). kernel_out (1 row

@@ -1227,14 +1227,17 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus, bool s
 }
 
 int mttkrp_candidates(const ntf_tensor& T, int mode, int r, MttkrpChoice* out, int cap) {
-  // same rules as plan_mttkrp: rank above 64 or a bf16 last mode needs tiles of 2+ waves
+  // the planner's default first (as an explicit choice), then the other shapes; same rules
+  // as plan_mttkrp: rank above 64 or a bf16 last mode needs tiles of 2+ waves
+  const MttkrpPlan def = plan_mttkrp(T, mode, r, 1);
+  const MttkrpChoice d = def.slab ? MttkrpChoice{2, 0} : MttkrpChoice{1, def.wm};
+  int n = 0;
+  if (n < cap) out[n++] = d;
   const bool last = mode == T.order - 1;
   const int wm_min = (n_tiles(r) >= 4 || (T.dtype == NTF_BF16 && last)) ? 2 : 1;
-  int n = 0;
   for (int wm : {4, 2, 1})
-    if (wm >= wm_min && n < cap) out[n++] = MttkrpChoice{1, wm};
-  MttkrpPlan pl = plan_mttkrp(T, mode, r, 1, false, &out[0]);
-  if (slab_lds(pl, T) > 0 && n < cap) out[n++] = MttkrpChoice{2, 0};
+    if (wm >= wm_min && n < cap && !(d.kernel == 1 && d.wm == wm)) out[n++] = MttkrpChoice{1, wm};
+  if (d.kernel != 2 && slab_lds(def, T) > 0 && n < cap) out[n++] = MttkrpChoice{2, 0};
   return n;
 }
 
