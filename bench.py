@@ -137,6 +137,26 @@ def time_hals(ntf, torch, Td, A_dev, reps):
     return out, sweeps
 
 
+def iterations_to_fit(ntf, torch, Td, Tref, A_dev, A0_dev, params, steps: int, fit_ref: float):
+    """First outer iteration whose explicit fit against Tref is within 1e-3 (relative) of the
+    oracle's final fit (checked after every iteration up to 50, then every 10); None if not
+    reached within `steps`."""
+    for a, a0 in zip(A_dev, A0_dev):
+        a.copy_(a0)
+    normT = float(ntf.ntf_norm2(Tref).item()) ** 0.5
+    state = None
+    done = 0
+    while done < steps:
+        k = min(1 if done < 50 else 10, steps - done)
+        state, _ = ntf.ntf_solve(Td, A_dev, k, params=params, state=state,
+                                 resume=state is not None, trace=False)
+        done += k
+        rel = float(ntf.ntf_residual_norm2(Tref, A_dev).item()) ** 0.5 / normT
+        if abs((1.0 - rel) - fit_ref) <= 1e-3 * fit_ref:
+            return done
+    return None
+
+
 def bench_batched(ntf, torch, iters: int):
     """The 256-problem workload (I_n ~ U{32..160}, r ~ U{5..20}, 30 dB) solved for `iters`
     outer iterations in one persistent launch (after one warm-up call that captures it)."""
@@ -360,9 +380,26 @@ def cpu_baseline(pr_T32, A0, budget_s: float):
     t0 = time.perf_counter()
     oracle.her_solve(T64, None, n, state=start)
     dt = time.perf_counter() - t0
+    blas = "unknown"
+    try:
+        from threadpoolctl import threadpool_info
+        blas = ", ".join(sorted({f"{i.get('internal_api')} ({i.get('num_threads')} threads)"
+                                 for i in threadpool_info() if i.get("user_api") == "blas"}))
+    except Exception:
+        pass
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return dict(value=n / dt, unit="iters/s", cores=int(threads), kind="oracle",
                 sample=f"{n} outer iterations of the {WORKLOAD} workload resumed from A_0 "
-                       f"(FP64 NumPy oracle, {dt:.1f} s)")
+                       f"(FP64 NumPy oracle, {dt:.1f} s)",
+                host=dict(cpu_count=os.cpu_count(), model=model, blas=blas))
 
 
 def main(argv=None):
@@ -428,6 +465,12 @@ def main(argv=None):
     params = ntf.HerParams()
     n_elem = int(np.prod(T32.shape))
     r = int(w["r"])
+    golden = golden_fit = None
+    gpath = os.path.join(ROOT, "tests", "golden", "oracle_fits.json")
+    if os.path.exists(gpath):
+        g = json.load(open(gpath)).get(WORKLOAD)
+        if g and g["iters"] == a.steps:
+            golden, golden_fit = g["relerr"], g["fit"]
     tuned = {}
     if not a.no_autotune:
         # the autotuner picks each mode's MTTKRP shape (timed on the workload's own tensor)
@@ -448,13 +491,17 @@ def main(argv=None):
         relerr = res / normT
         sweeps = trace["sweeps"].float().mean().item()
         restarts = int(trace["restart"].sum().item())
+        ttf = None
+        if golden_fit is not None:
+            ttf = iterations_to_fit(ntf, torch, Td, Td32, A_dev, A0_dev, params, a.steps,
+                                    golden_fit)
         mt_ms = time_mttkrp(ntf, torch, Td, A_dev, a.mttkrp_reps)
         hals_ms, hals_sweeps = time_hals(ntf, torch, Td, A_dev, a.hals_reps)
         flops = 2.0 * r * n_elem
         forms[form] = dict(
             iters_per_s=a.steps / (ms / 1e3), ms_per_step=ms / a.steps, wall_s=wall,
             final_relerr=relerr, restarts=restarts, mean_inner_sweeps=sweeps,
-            mttkrp_ms=mt_ms, hals_ms=hals_ms, hals_sweeps=hals_sweeps,
+            mttkrp_ms=mt_ms, hals_ms=hals_ms, hals_sweeps=hals_sweeps, iters_to_fit=ttf,
             mttkrp_tflops=[flops / (t / 1e3) / 1e12 for t in mt_ms],
             mttkrp_gbs=[n_elem * s / (t / 1e3) / 1e9 for t in mt_ms])
         log(f"[bench] {form}: {forms[form]['iters_per_s']:.1f} it/s, relerr {relerr:.6e}, "
@@ -463,12 +510,6 @@ def main(argv=None):
     flags = ntf.ntf_device_flags()
     streams = {"bf16_128MB": stream_gbs(ntf, torch, Td16), "f32_256MB": stream_gbs(ntf, torch, Td32)}
 
-    golden = None
-    gpath = os.path.join(ROOT, "tests", "golden", "oracle_fits.json")
-    if os.path.exists(gpath):
-        g = json.load(open(gpath)).get(WORKLOAD)
-        if g and g["iters"] == a.steps:
-            golden = g["relerr"]
 
     bf = forms["bf16"]
     # MTTKRP: algorithmic bytes = one read of the bf16 tensor per launch (factors and the
@@ -522,6 +563,12 @@ def main(argv=None):
         "mttkrp_gbs": {k: [round(x, 1) for x in v["mttkrp_gbs"]] for k, v in forms.items()},
         "final_relerr": {k: v["final_relerr"] for k, v in forms.items()},
         "oracle_relerr": golden,
+        # first iteration whose fit is within 1e-3 of the oracle's final fit, and the time
+        # that takes at the measured rate
+        "time_to_fit": {k: (None if v["iters_to_fit"] is None else
+                            {"iters": v["iters_to_fit"],
+                             "ms": round(v["iters_to_fit"] * v["ms_per_step"], 3)})
+                        for k, v in forms.items()},
         "restarts": {k: v["restarts"] for k, v in forms.items()},
         "mean_inner_sweeps": {k: round(v["mean_inner_sweeps"], 2) for k, v in forms.items()},
         "mttkrp_autotune": tuned or None,
