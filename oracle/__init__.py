@@ -16,6 +16,7 @@ Modules
 tensor  : Kronecker / Khatri-Rao products, unfoldings, Kruskal reconstruction, the block
           matrix B^(i), MTTKRP, Grams and their Hadamard product, objective, gradient.
 hals    : A-HALS column updates and the inner stopping rule.
+pgd     : projected gradient and accelerated projected gradient block solvers.
 her     : extrapolation, the beta schedule, the restart surrogate F-hat, Algorithm 2 (HER)
           and Algorithm 1 (plain alternating optimization).
 metrics : data-fitting error, relative error / fit, factor error with matching.
@@ -25,6 +26,7 @@ tucker  : the Tucker-compressed objective and its gradient (Appendix A).
 from .tensor import (kron_columns, khatri_rao, unfold, fold, kruskal, block_matrix, mttkrp,
                      mttkrp_rows, gram, hadamard_gram, objective, gradient)
 from .hals import hals_column, hals
+from .pgd import lipschitz, pg_step, pgd, nesterov
 from .her import (HERParams, extrapolate, update_beta, f_hat, her_solve, ao_solve,
                   HERResult)
 from .metrics import residual_norm, relative_error, fit, factor_error
@@ -36,4 +38,5 @@ __all__ = [
     "gram", "hadamard_gram", "objective", "gradient", "hals_column", "hals", "HERParams",
     "extrapolate", "update_beta", "f_hat", "her_solve", "ao_solve", "HERResult",
     "residual_norm", "relative_error", "fit", "factor_error", "cp_loss", "cp_loss_grad",
+    "lipschitz", "pg_step", "pgd", "nesterov",
 ]

@@ -1,0 +1,93 @@
+"""Pins of the oracle's projected-gradient block solvers (oracle/pgd.py) against what the
+mathematics fixes: the Lipschitz constant from the singular values of B, the descent
+property of a 1/L projected gradient step, the r = 1 closed form, the NNLS solution from
+an independent solver, its KKT conditions, and plain BCD with these solvers decreasing F."""
+import numpy as np
+import pytest
+from scipy.optimize import nnls
+
+import oracle
+
+
+def _block(seed, I=30, r=5, m=60):
+    g = np.random.default_rng(seed)
+    B = g.random((m, r))
+    X = g.random((I, m))
+    return X @ B, B.T @ B, B, g.random((I, r))
+
+
+def _obj(W, P, G):
+    return 0.5 * np.sum((W @ G) * W) - np.sum(P * W)
+
+
+def test_lipschitz_is_the_largest_squared_singular_value():
+    _, G, B, _ = _block(0)
+    assert oracle.lipschitz(G) == pytest.approx(np.linalg.svd(B, compute_uv=False)[0] ** 2,
+                                                rel=1e-12)
+
+
+def test_projected_gradient_step_decreases_the_block_objective():
+    P, G, _, W = _block(1)
+    L = oracle.lipschitz(G)
+    f = _obj(W, P, G)
+    for _ in range(30):
+        W = oracle.pg_step(W, P, G, L)
+        assert W.min() >= 0.0
+        f_new = _obj(W, P, G)
+        assert f_new <= f + 1e-12 * abs(f)
+        f = f_new
+
+
+def test_rank_one_closed_form():
+    g = np.random.default_rng(2)
+    P = g.standard_normal((20, 1))
+    G = np.array([[2.5]])
+    W, s, _ = oracle.pgd(g.random((20, 1)), P, G, max_iters=1, tol=0.0)
+    np.testing.assert_allclose(W, np.maximum(0.0, P / 2.5), rtol=1e-13, atol=1e-15)
+    Wn, _, _ = oracle.nesterov(g.random((20, 1)), P, G, max_iters=1, tol=0.0)
+    np.testing.assert_allclose(Wn, W, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("solver,iters", [("pgd", 20000), ("nesterov", 3000)])
+def test_converges_to_the_nnls_solution(solver, iters):
+    P, G, _, W0 = _block(3, I=8, r=4)
+    W, _, _ = getattr(oracle, solver)(W0, P, G, max_iters=iters, tol=0.0)
+    # each row solves min_{w >= 0} 1/2 w^T G w - p^T w = 1/2 ||R w - R^{-T} p||^2 + const
+    R = np.linalg.cholesky(G).T
+    for i in range(P.shape[0]):
+        ref, _ = nnls(R, np.linalg.solve(R.T, P[i]))
+        np.testing.assert_allclose(W[i], ref, rtol=1e-6, atol=1e-8)
+    grad = W @ G - P
+    assert W.min() >= 0.0
+    assert grad.min() >= -1e-6 * np.abs(P).max()
+    assert np.abs(W * grad).max() <= 1e-6 * np.abs(P).max() * np.abs(W).max()
+
+
+def test_first_nesterov_step_is_a_plain_step_and_dead_block_is_zero():
+    P, G, _, W0 = _block(4)
+    W1, _, _ = oracle.pgd(W0, P, G, max_iters=1, tol=0.0)
+    N1, _, _ = oracle.nesterov(W0, P, G, max_iters=1, tol=0.0)
+    np.testing.assert_array_equal(W1, N1)
+    Wz, _, _ = oracle.pgd(W0, np.zeros_like(P), np.zeros_like(G), max_iters=3)
+    assert not Wz.any()
+
+
+def test_stopping_rule_counts():
+    P, G, _, W0 = _block(5)
+    _, s, d = oracle.pgd(W0, P, G, max_iters=7, tol=0.0)
+    assert s == 7 and len(d) == 7
+    _, s, d = oracle.pgd(W0, P, G, max_iters=500, tol=1e-2)
+    assert s < 500 and d[-1] <= 1e-2 * d[0] and all(x > 1e-2 * d[0] for x in d[1:-1])
+
+
+@pytest.mark.parametrize("inner", ["pgd", "nesterov"])
+def test_plain_bcd_with_gradient_blocks_is_monotone(inner):
+    """beta0 = 0: no extrapolation, so Algorithm 2 is plain BCD with a descent block solver
+    and F decreases at every outer iteration; iterates stay nonnegative."""
+    import synth
+    pr = synth.make_problem((12, 10, 9), 3, snr_db=30.0, data_seed=3, init_seed=4)
+    res = oracle.her_solve(pr.T, pr.A0, 15, params=oracle.HERParams(beta0=0.0, inner=inner))
+    f = np.array([res.fhat0] + res.fhat)
+    assert np.all(np.diff(f) <= 1e-12 * f[:-1])
+    assert min(a.min() for a in res.factors) >= 0.0
+    assert not any(res.restart)
