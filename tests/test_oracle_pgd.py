@@ -45,7 +45,7 @@ def test_rank_one_closed_form():
     W, s, _ = oracle.pgd(g.random((20, 1)), P, G, max_iters=1, tol=0.0)
     np.testing.assert_allclose(W, np.maximum(0.0, P / 2.5), rtol=1e-13, atol=1e-15)
     Wn, _, _ = oracle.nesterov(g.random((20, 1)), P, G, max_iters=1, tol=0.0)
-    np.testing.assert_allclose(Wn, W, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(Wn, np.maximum(0.0, P / 2.5), rtol=1e-13, atol=1e-15)
 
 
 @pytest.mark.parametrize("solver,iters", [("pgd", 20000), ("nesterov", 3000)])
