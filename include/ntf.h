@@ -80,8 +80,11 @@ typedef struct ntf_her_params {
   double gamma;        /* growth rate of beta, default 1.05 */
   double gamma_bar;    /* growth rate of beta_bar, default 1.01 */
   double eta;          /* decay rate of beta, default 1.5 */
-  int32_t max_inner;   /* A-HALS sweeps per block at most, default 50 */
-  int32_t reserved;    /* must be 0 */
+  int32_t max_inner;   /* inner steps per block at most (A-HALS sweeps), default 50 */
+  int32_t inner_solver; /* block solver: 0 A-HALS (Sec. 2.1.4, default), 1 projected gradient,
+                           2 accelerated (Nesterov) projected gradient (Sec. 2.2; the
+                           HER-PGD50 / HER-Nesterov50 runs of Sec. 3.1.4: they take exactly
+                           max_inner steps and need inner_tol = 0) */
   double inner_tol;    /* stop when ||W_s - W_{s-1}||_F <= inner_tol ||W_1 - W_0||_F, default 1e-2 */
 } ntf_her_params;
 
@@ -210,6 +213,17 @@ ntf_status ntf_gram(ntf_handle* h, const float* const* A, const int64_t* rows, i
 ntf_status ntf_hals_update(ntf_handle* h, float* W, const float* P, const float* G,
                            int64_t rows, int32_t r, int32_t max_sweeps, double tol,
                            int32_t* sweeps_done, void* stream);
+
+/* Projected-gradient block solver (Sec. 2.2): `steps` steps of
+ * W <- max(0, Y - (Y G - P) / L), L = ||G||_2 (largest eigenvalue of G, by power iteration
+ * in float64 from the all-ones vector: G is entrywise nonnegative for nonnegative factors),
+ * Y = W (accel = 0) or Nesterov's point W_s + ((t_{s-1} - 1) / t_s)(W_s - W_{s-1}) with
+ * t_0 = 1, t_s = (1 + sqrt(1 + 4 t_{s-1}^2)) / 2 (accel = 1). W: rows x r in place (input =
+ * starting point); P: rows x r; G: r x r float32, symmetric. L_out: one device double that
+ * receives L (workspace of the call). r > 128: NTF_EUNSUPPORTED. */
+ntf_status ntf_pgd_update(ntf_handle* h, float* W, const float* P, const float* G,
+                          int64_t rows, int32_t r, int32_t steps, int32_t accel,
+                          double* L_out, void* stream);
 
 /* One HER step of Algorithm 2 on caller buffers.
  *  INIT:        state <- {beta0, 1, *fhat, ...}; `fhat` must point to F(A_0).

@@ -6,7 +6,8 @@ There is no CPU fallback: if libntf.so is missing the import of a call raises.
 
 Functions carry the C names: ntf_norm2, ntf_cast_bf16, ntf_mttkrp, ntf_mttkrp_multi,
 ntf_mttkrp_autotune,
-ntf_tune_export, ntf_tune_import, ntf_gram, ntf_hals_update, ntf_her_step, ntf_error,
+ntf_tune_export, ntf_tune_import, ntf_gram, ntf_hals_update, ntf_pgd_update, ntf_her_step,
+ntf_error,
 ntf_solve, ntf_residual_norm2, ntf_cp_loss, ntf_cp_grad, ntf_solve_batched, plus the
 autograd loss `NTFLoss` / `ntf_loss` (module `autograd`) and a JSON file for the tuning
 table (`save_tuning`, `load_tuning`).
@@ -27,6 +28,7 @@ __all__ = [
     "ntf_residual_norm2", "ntf_device_flags", "new_state", "state_dict", "ntf_cp_loss",
     "ntf_cp_grad", "NTFLoss", "ntf_loss", "ntf_solve_batched", "ntf_mttkrp_autotune",
     "ntf_tune_export", "ntf_tune_import", "save_tuning", "load_tuning", "ntf_mttkrp_multi",
+    "ntf_pgd_update",
 ]
 
 _DTYPES = {torch.float32: _abi.NTF_F32, torch.bfloat16: _abi.NTF_BF16}
@@ -96,18 +98,22 @@ def _h(h):
 
 @dataclass
 class HerParams:
-    """HER parameters (defaults of the paper's experiments) and inner stopping rule."""
+    """HER parameters (defaults of the paper's experiments), the inner stopping rule and the
+    block solver: "ahals" (default), "pgd" or "nesterov" (projected gradient steps; these
+    run exactly max_inner steps and need inner_tol = 0)."""
     beta0: float = 0.5
     gamma: float = 1.05
     gamma_bar: float = 1.01
     eta: float = 1.5
     max_inner: int = 50
     inner_tol: float = 1e-2
+    inner: str = "ahals"
 
     def to_c(self) -> _abi.NtfHerParams:
         p = _abi.NtfHerParams()
         p.beta0, p.gamma, p.gamma_bar, p.eta = self.beta0, self.gamma, self.gamma_bar, self.eta
-        p.max_inner, p.reserved, p.inner_tol = int(self.max_inner), 0, float(self.inner_tol)
+        p.max_inner, p.inner_tol = int(self.max_inner), float(self.inner_tol)
+        p.inner_solver = {"ahals": 0, "pgd": 1, "nesterov": 2}[self.inner]
         return p
 
 
@@ -147,6 +153,17 @@ def ntf_mttkrp(T: torch.Tensor, factors, mode: int, out: torch.Tensor | None = N
     check(lib().ntf_mttkrp(_h(h), C.byref(d), ptrs, r, int(mode), _dev(out, "P", torch.float32),
                            _stream(stream)))
     return out
+
+
+def ntf_pgd_update(W: torch.Tensor, P: torch.Tensor, G: torch.Tensor, steps: int,
+                   accel: bool = False, h=None, stream=None) -> torch.Tensor:
+    """Projected-gradient block solver in place on W; returns L = ||G||_2 (device double)."""
+    L = torch.empty((), dtype=torch.float64, device=W.device)
+    rows, r = int(W.shape[0]), int(W.shape[1])
+    check(lib().ntf_pgd_update(_h(h), _dev(W, "W", torch.float32), _dev(P, "P", torch.float32),
+                               _dev(G, "G", torch.float32), rows, r, int(steps),
+                               1 if accel else 0, L.data_ptr(), _stream(stream)))
+    return L
 
 
 def ntf_mttkrp_multi(T: torch.Tensor, factors, modes, h=None, stream=None) -> dict:

@@ -24,7 +24,7 @@ class NtfTensor(C.Structure):
 
 class NtfHerParams(C.Structure):
     _fields_ = [("beta0", C.c_double), ("gamma", C.c_double), ("gamma_bar", C.c_double),
-                ("eta", C.c_double), ("max_inner", C.c_int32), ("reserved", C.c_int32),
+                ("eta", C.c_double), ("max_inner", C.c_int32), ("inner_solver", C.c_int32),
                 ("inner_tol", C.c_double)]
 
 
@@ -80,6 +80,8 @@ SIGNATURES = {
                                       C.POINTER(C.c_int32), C.POINTER(C.c_float), PTR]),
     "ntf_tune_export": (C.c_int64, [PTR, C.c_char_p, C.c_int64]),
     "ntf_tune_import": (C.c_int, [PTR, C.c_char_p]),
+    "ntf_pgd_update": (C.c_int, [PTR, PTR, PTR, PTR, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                 PTR, PTR]),
     "ntf_mttkrp_multi": (C.c_int, [PTR, C.POINTER(NtfTensor), PTRS, C.c_int32, C.c_int32, PTRS,
                                    PTR]),
 }

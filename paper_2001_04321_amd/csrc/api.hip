@@ -111,7 +111,8 @@ ntf_status check_params(const ntf_her_params* p) {
   NTF_RETURN_IF(p->max_inner < 1 || p->max_inner > kMaxSweeps, NTF_EINVAL,
                 "max_inner must lie in [1, %d]", kMaxSweeps);
   NTF_RETURN_IF(!(p->inner_tol >= 0.0), NTF_EINVAL, "inner_tol must be >= 0");
-  NTF_RETURN_IF(p->reserved != 0, NTF_EINVAL, "reserved field must be 0");
+  NTF_RETURN_IF(p->inner_solver < 0 || p->inner_solver > 2, NTF_EINVAL,
+                "inner_solver %d outside [0, 2]", p->inner_solver);
   return NTF_OK;
 }
 
@@ -515,6 +516,33 @@ ntf_status ntf_hals_update(ntf_handle* h, float* W, const float* P, const float*
   return NTF_OK;
 }
 
+ntf_status ntf_pgd_update(ntf_handle* h, float* W, const float* P, const float* G,
+                          int64_t rows, int32_t r, int32_t steps, int32_t accel,
+                          double* L_out, void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_rank(r);
+  if (st) return st;
+  NTF_RETURN_IF(!W || !P || !G || !L_out, NTF_EINVAL, "W, P, G or L_out is NULL");
+  NTF_RETURN_IF(rows < 1, NTF_EINVAL, "rows < 1");
+  NTF_RETURN_IF(steps < 1 || steps > kMaxSweeps, NTF_EINVAL, "steps outside [1, %d]",
+                kMaxSweeps);
+  NTF_RETURN_IF(accel != 0 && accel != 1, NTF_EINVAL, "accel must be 0 or 1");
+  NTF_RETURN_IF(r > 128, NTF_EUNSUPPORTED, "projected-gradient kernel supports r <= 128");
+  PgdArgs a{};
+  a.W0 = W;
+  a.W = W;
+  a.P = P;
+  a.G = G;
+  a.L = L_out;
+  a.rows = rows;
+  a.r = r;
+  a.steps = steps;
+  a.accel = accel;
+  NTF_HIP(launch_pgd(a, as_stream(stream)));
+  return NTF_OK;
+}
+
 ntf_status ntf_her_step(ntf_handle* h, ntf_her_op op, ntf_her_state* state,
                         const ntf_her_params* params, int32_t nblocks, const int64_t* rows,
                         int32_t r, float* const* A, float* const* A_new, float* const* A_hat,
@@ -631,6 +659,8 @@ ntf_status solve_batched_impl(ntf_handle* h, int32_t nprob, const ntf_problem* p
   NTF_RETURN_IF(iters < 0, NTF_EINVAL, "iters < 0");
   ntf_status st = check_params(params);
   if (st) return st;
+  NTF_RETURN_IF(params->inner_solver != 0, NTF_EUNSUPPORTED,
+                "the batched solver uses A-HALS blocks only (inner_solver 0)");
   std::vector<BatchedProblem> bp(static_cast<size_t>(nprob));
   std::vector<int64_t> cost(static_cast<size_t>(nprob));
   size_t ws_bytes = 0;

@@ -261,6 +261,22 @@ struct HalsArgs {
 };
 hipError_t launch_hals(const HalsArgs& a, int num_cus, hipStream_t s);
 
+// Projected-gradient block solver (k_pgd.hip): L <- ||G||_2 by power iteration, then
+// `steps` projected gradient steps (accel: Nesterov's point), W0 -> W (may alias).
+struct PgdArgs {
+  const float* W0;
+  float* W;
+  const float* P;
+  const float* G;
+  double* L;
+  int64_t rows;
+  int r;
+  int steps;
+  int accel;
+  int32_t* steps_out;  // may be null
+};
+hipError_t launch_pgd(const PgdArgs& a, hipStream_t s);
+
 // Extrapolate-project: out = max(0, a_new + beta (a_new - a_old)), beta = *beta_src.
 hipError_t launch_extrapolate(const float* a_new, const float* a_old, float* out, int64_t n,
                               const double* beta_src, hipStream_t s);

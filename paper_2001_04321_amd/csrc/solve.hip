@@ -63,6 +63,7 @@ struct SolveBufs {
   int32_t* sweeps;
   double* err_part;
   int64_t nerr;
+  double* lip;  // projected-gradient blocks: L of the current block
 };
 
 void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
@@ -102,6 +103,7 @@ void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
   b.sweeps = ar.take<int32_t>(kMaxOrder);
   b.nerr = std::max(error_partial_count(T.dims[N - 1], r), hals_wgs(T.dims[N - 1], r));
   b.err_part = ar.take<double>(size_t(b.nerr));
+  b.lip = ar.take<double>(1);
 }
 
 FactorPtrs factors_for(int n, int N, float* const* A, const SolveBufs& b) {
@@ -149,6 +151,38 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
                                   true, s, nullptr, &hl)) != hipSuccess) {
       return e;
     }
+    if (p.inner_solver != 0) {
+      // projected-gradient block (Sec. 2.2), then the steps the A-HALS epilogue fuses:
+      // extrapolation, Gram partials of A_new and A-hat, the F-hat share of the last block
+      PgdArgs pa{};
+      pa.W0 = A[n];
+      pa.W = b.A_new[n];
+      pa.P = b.P;
+      pa.G = b.G32;
+      pa.L = b.lip;
+      pa.rows = I;
+      pa.r = r;
+      pa.steps = p.max_inner;
+      pa.accel = p.inner_solver == 2 ? 1 : 0;
+      pa.steps_out = b.sweeps + n;
+      if ((e = launch_pgd(pa, s)) != hipSuccess) return e;
+      if ((e = launch_extrapolate(b.A_new[n], A[n], b.A_hat[n], I * r, &b.state->beta, s)) !=
+          hipSuccess)
+        return e;
+      GramJob gj{};
+      gj.nfac = 2;
+      gj.A[0] = b.A_new[n];
+      gj.out[0] = b.gp_new[n];
+      gj.rows[0] = I;
+      gj.A[1] = b.A_hat[n];
+      gj.out[1] = b.gp_hat[n];
+      gj.rows[1] = I;
+      if ((e = launch_gram_partials(gj, r, s)) != hipSuccess) return e;
+      if (n == N - 1 &&
+          (e = launch_error_partials(b.P, b.A_new[n], b.G64, I, r, b.err_part, s)) != hipSuccess)
+        return e;
+      continue;
+    }
     HalsArgs ha{};
     ha.W0 = A[n];
     ha.W = b.A_new[n];
@@ -175,7 +209,7 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
   d.p = p;
   d.normT2 = b.normT2;
   d.partials = b.err_part;
-  d.nparts = hals_wgs(IN, r);
+  d.nparts = p.inner_solver != 0 ? error_partial_count(IN, r) : hals_wgs(IN, r);
   d.trace = trace;
   d.order = N;
   d.sweeps_src = b.sweeps;
@@ -244,8 +278,14 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
   NTF_RETURN_IF(!A, NTF_EINVAL, "factor array is NULL");
   NTF_RETURN_IF(resume && !state, NTF_EINVAL, "resume needs a state");
   const int N = T->order;
+  NTF_RETURN_IF(params->inner_solver != 0 && params->inner_tol != 0.0, NTF_EUNSUPPORTED,
+                "projected-gradient blocks run exactly max_inner steps: inner_tol must be 0");
   for (int n = 0; n < N; ++n) {
     NTF_RETURN_IF(!A[n], NTF_EINVAL, "factor %d is NULL", n);
+    if (params->inner_solver != 0) {
+      NTF_RETURN_IF(r > 128, NTF_EUNSUPPORTED, "projected-gradient kernel supports r <= 128");
+      continue;
+    }
     NTF_RETURN_IF(!hals_supported(T->dims[n], r, h->num_cus), NTF_EUNSUPPORTED,
                   "mode %d: A-HALS kernel supports r <= 128 and at most 256 row workgroups", n);
   }
