@@ -15,7 +15,8 @@ and the FP64 oracle's rate on the host are reported beside it.
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
                     [--no-autograd] [--no-quad] [--copy-probe]
 
-Also reported (not the headline value): the read-only streaming rate at each tensor's
+Also reported (not the headline value): HER with projected-gradient and Nesterov block
+solvers on the same workload, the read-only streaming rate at each tensor's
 footprint (the MTTKRP's practical roof), the 4-way 128^4 bf16 r=64 workload (solver rate,
 per-mode MTTKRP and its fraction of the bf16 MFMA peak), the 256-problem batched workload
 solved in one persistent launch, and the 512^3 r=50 autograd loss with its backward.
@@ -417,6 +418,8 @@ def main(argv=None):
     ap.add_argument("--no-autograd", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the planner's default MTTKRP shapes")
+    ap.add_argument("--no-inner-solvers", action="store_true",
+                    help="skip the projected-gradient block solver runs")
     ap.add_argument("--quad-iters", type=int, default=200)
     ap.add_argument("--no-quad", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -577,6 +580,20 @@ def main(argv=None):
         "cpu_baseline": None,
     }
     line["stream_gbs"] = {k: round(v, 1) for k, v in streams.items()}
+    if not a.no_inner_solvers:
+        # HER with projected-gradient blocks (50 steps each: HER-PGD50, HER-Nesterov50), bf16
+        line["inner_solvers"] = {}
+        for inner in ("pgd", "nesterov"):
+            A_dev = [x.clone() for x in A0_dev]
+            prm = ntf.HerParams(inner=inner, inner_tol=0.0, max_inner=50)
+            log(f"[bench] bf16 with {inner} blocks: {a.steps} outer iterations")
+            ms, _, _, trace = time_solve(ntf, torch, Td16, A_dev, A0_dev, a.steps, a.warmup, prm)
+            res = float(ntf.ntf_residual_norm2(Td32, A_dev).item()) ** 0.5
+            line["inner_solvers"][inner] = {
+                "iters_per_s": round(a.steps / (ms / 1e3), 1),
+                "ms_per_step": round(ms / a.steps, 5), "final_relerr": res / normT,
+                "restarts": int(trace["restart"].sum().item())}
+            del A_dev
     if not a.no_quad:
         log(f"[bench] 4-way: 128^4 bf16, r=64, {a.quad_iters} outer iterations")
         line["quad128"] = bench_quad128(ntf, torch, a.quad_iters, 5, a.mttkrp_reps,
