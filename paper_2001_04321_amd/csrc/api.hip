@@ -529,7 +529,9 @@ ntf_status ntf_pgd_update(ntf_handle* h, float* W, const float* P, const float* 
                 kMaxSweeps);
   NTF_RETURN_IF(accel != 0 && accel != 1, NTF_EINVAL, "accel must be 0 or 1");
   NTF_RETURN_IF(r > 128, NTF_EUNSUPPORTED, "projected-gradient kernel supports r <= 128");
+  if ((st = ensure_workspace(h, size_t(steps) * sizeof(float) + 256))) return st;
   PgdArgs a{};
+  a.coef = reinterpret_cast<float*>(h->ws);
   a.W0 = W;
   a.W = W;
   a.P = P;

@@ -14,7 +14,8 @@
 //
 // L is the largest eigenvalue of the symmetric G. G is entrywise nonnegative (a Hadamard
 // product of Grams of nonnegative factors), so its largest eigenvalue is its Perron root:
-// power iteration from the all-ones vector (float64, fixed count, Rayleigh quotient).
+// power iteration from the all-ones vector (float64, Rayleigh quotient, until it repeats
+// to a few units in the last place or after 100 iterations).
 #include "ntf_internal.h"
 
 namespace ntf {
@@ -23,42 +24,66 @@ namespace {
 constexpr int kPgdThreads = 256;
 constexpr int kPowerIters = 100;
 
-__global__ __launch_bounds__(256) void lipschitz_kernel(const float* __restrict__ G, int r,
-                                                        double* __restrict__ L) {
-  __shared__ double v[kMaxRank], w[kMaxRank], red[256];
+// One wave: G in LDS (G is symmetric, so lane t reads column t, conflict-free), lanes own
+// rows t and t + 64; sums over the wave by butterfly shuffles, then lane 0's value is used
+// by every lane. Stops when the Rayleigh quotient repeats to a few units in the last
+// place, at most kPowerIters. Lane 0 then writes the Nesterov weights of every step.
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return __shfl(x, 0);
+}
+
+__global__ __launch_bounds__(64) void lipschitz_kernel(const float* __restrict__ G, int r,
+                                                       double* __restrict__ L, int steps,
+                                                       float* __restrict__ coef) {
+  extern __shared__ float s_g[];  // r x r
+  __shared__ double s_v[128];
   const int t = threadIdx.x;
-  if (t < r) v[t] = 1.0;
+  for (int e = t; e < r * r; e += 64) s_g[e] = G[e];
+  for (int q = t; q < r; q += 64) s_v[q] = 1.0;
   __syncthreads();
-  double lambda = 0.0;
+  const bool a0 = t < r, a1 = t + 64 < r;
+  double lambda = 0.0, prev = -1.0;
   for (int it = 0; it < kPowerIters; ++it) {
-    double acc = 0.0;
-    if (t < r)
-      for (int q = 0; q < r; ++q) acc += double(G[t * r + q]) * v[q];
-    if (t < r) w[t] = acc;
-    // Rayleigh quotient v.w / v.v and the norm of w (fixed-order sums by thread 0)
-    __syncthreads();
-    if (t == 0) {
-      double vw = 0.0, vv = 0.0, ww = 0.0;
-      for (int q = 0; q < r; ++q) {
-        vw += v[q] * w[q];
-        vv += v[q] * v[q];
-        ww += w[q] * w[q];
-      }
-      red[0] = vv > 0.0 ? vw / vv : 0.0;
-      red[1] = ww > 0.0 ? 1.0 / sqrt(ww) : 0.0;
+    double w0 = 0.0, w1 = 0.0;
+    for (int q = 0; q < r; ++q) {
+      const double vq = s_v[q];
+      if (a0) w0 = fma(double(s_g[q * r + t]), vq, w0);
+      if (a1) w1 = fma(double(s_g[q * r + t + 64]), vq, w1);
     }
+    const double v0 = a0 ? s_v[t] : 0.0, v1 = a1 ? s_v[t + 64] : 0.0;
+    const double vw = wave_sum(v0 * w0 + v1 * w1);
+    const double vv = wave_sum(v0 * v0 + v1 * v1);
+    const double ww = wave_sum(w0 * w0 + w1 * w1);
+    lambda = vv > 0.0 ? vw / vv : 0.0;
+    const double inv = ww > 0.0 ? 1.0 / sqrt(ww) : 0.0;
     __syncthreads();
-    lambda = red[0];
-    if (t < r) v[t] = w[t] * red[1];
+    if (a0) s_v[t] = w0 * inv;
+    if (a1) s_v[t + 64] = w1 * inv;
     __syncthreads();
+    // converged when the quotient repeats to within a few units in the last place
+    if (fabs(lambda - prev) <= 4e-16 * fabs(lambda)) break;
+    prev = lambda;
   }
-  if (t == 0) *L = lambda;
+  if (t == 0) {
+    *L = lambda;
+    // Nesterov weights (t_{s-1} - 1) / t_s of steps s = 1..steps (float64 recurrence)
+    if (coef) {
+      double tk = 1.0;
+      for (int st = 0; st < steps; ++st) {
+        const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tk * tk));
+        coef[st] = float((tk - 1.0) / tn);
+        tk = tn;
+      }
+    }
+  }
 }
 
 template <int RP, bool ACCEL>
 __global__ __launch_bounds__(kPgdThreads) void pgd_kernel(PgdArgs a) {
   constexpr int RB = kPgdThreads / RP;  // rows per workgroup
-  __shared__ float s_y[RB][RP];
+  __shared__ __attribute__((aligned(16))) float s_y[RB][RP];
   const int t = threadIdx.x;
   const int rl = t / RP;
   const int p = t - rl * RP;
@@ -73,19 +98,24 @@ __global__ __launch_bounds__(kPgdThreads) void pgd_kernel(PgdArgs a) {
   const float pv = live ? a.P[row * r + p] : 0.f;
   float w = live ? a.W0[row * r + p] : 0.f;
   float y = w;
-  double tk = 1.0;
   for (int s = 0; s < a.steps; ++s) {
     s_y[rl][p] = y;
     __syncthreads();
-    float acc = 0.f;
+    // (Y G)[row, p]: four interleaved partial sums over 16-byte broadcast reads of the row
+    float acc4[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int q = 0; q < RP; ++q) acc = fmaf(s_y[rl][q], g[q], acc);
+    for (int q = 0; q < RP; q += 4) {
+      const float4 yq = *reinterpret_cast<const float4*>(&s_y[rl][q]);
+      acc4[0] = fmaf(yq.x, g[q], acc4[0]);
+      acc4[1] = fmaf(yq.y, g[q + 1], acc4[1]);
+      acc4[2] = fmaf(yq.z, g[q + 2], acc4[2]);
+      acc4[3] = fmaf(yq.w, g[q + 3], acc4[3]);
+    }
+    const float acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
     __syncthreads();
     const float wn = L > 0.0 ? fmaxf(0.f, y - (acc - pv) * inv_l) : 0.f;
     if (ACCEL) {
-      const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tk * tk));
-      y = wn + float((tk - 1.0) / tn) * (wn - w);
-      tk = tn;
+      y = wn + a.coef[s] * (wn - w);
     } else {
       y = wn;
     }
@@ -109,7 +139,15 @@ hipError_t launch_rp(const PgdArgs& a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_pgd(const PgdArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(lipschitz_kernel, dim3(1), dim3(256), 0, s, a.G, a.r, a.L);
+  static bool attr_done = false;  // r = 128: 64 KB of G plus the vector exceed the default
+  if (!attr_done) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(lipschitz_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    if (e != hipSuccess) return e;
+    attr_done = true;
+  }
+  hipLaunchKernelGGL(lipschitz_kernel, dim3(1), dim3(64), size_t(a.r) * a.r * sizeof(float), s,
+                     a.G, a.r, a.L, a.steps, a.accel ? a.coef : nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (a.r <= 32) return launch_rp<32>(a, s);

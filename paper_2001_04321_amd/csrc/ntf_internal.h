@@ -269,6 +269,7 @@ struct PgdArgs {
   const float* P;
   const float* G;
   double* L;
+  float* coef;  // accel: `steps` floats of workspace (the Nesterov weights)
   int64_t rows;
   int r;
   int steps;

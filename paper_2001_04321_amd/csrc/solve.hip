@@ -64,6 +64,7 @@ struct SolveBufs {
   double* err_part;
   int64_t nerr;
   double* lip;  // projected-gradient blocks: L of the current block
+  float* coef;  // and the Nesterov weights of its steps
 };
 
 void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
@@ -104,6 +105,7 @@ void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
   b.nerr = std::max(error_partial_count(T.dims[N - 1], r), hals_wgs(T.dims[N - 1], r));
   b.err_part = ar.take<double>(size_t(b.nerr));
   b.lip = ar.take<double>(1);
+  b.coef = ar.take<float>(size_t(max_inner));
 }
 
 FactorPtrs factors_for(int n, int N, float* const* A, const SolveBufs& b) {
@@ -160,6 +162,7 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
       pa.P = b.P;
       pa.G = b.G32;
       pa.L = b.lip;
+      pa.coef = b.coef;
       pa.rows = I;
       pa.r = r;
       pa.steps = p.max_inner;

@@ -49,7 +49,7 @@ def test_block_solver_matches_the_oracle(ntf, I, r, accel):
 
 @pytest.mark.parametrize("inner", ["pgd", "nesterov"])
 @pytest.mark.parametrize("dims,r,seed", [((30, 20, 25), 5, 1), ((9, 8, 7, 6), 3, 2),
-                                         ((40, 35, 30), 40, 3)])
+                                         ((40, 35, 30), 40, 3), ((20, 30, 25), 128, 4)])
 def test_solve_with_gradient_blocks_matches_the_oracle(ntf, inner, dims, r, seed):
     pr = synth.make_problem(dims, r, snr_db=30.0, data_seed=seed, init_seed=seed + 50)
     T32 = pr.T.astype(np.float32)
