@@ -403,6 +403,33 @@ def cpu_baseline(pr_T32, A0, budget_s: float):
                 host=dict(cpu_count=os.cpu_count(), model=model, blas=blas))
 
 
+def cpu_baseline_c1_one_thread(budget_s: float = 4.0):
+    """The oracle on the 50^3 r = 10 workload with one BLAS thread (bounded sample)."""
+    import numpy as np
+
+    import oracle
+    import synth
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:
+        return None
+    pr = synth.workload("cube50_r10")
+    T64 = pr.T.astype(np.float32).astype(np.float64)
+    start = dict(factors=[a.astype(np.float32).astype(np.float64) for a in pr.A0], beta=0.5,
+                 beta_bar=1.0, fhat=float("inf"))
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oracle.her_solve(T64, None, 2, state=start)
+        t1 = (time.perf_counter() - t0) / 2
+        n = max(2, min(200, int(budget_s / max(t1, 1e-4))))
+        t0 = time.perf_counter()
+        oracle.her_solve(T64, None, n, state=start)
+        dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="iters/s", cores=1, kind="oracle",
+                sample=f"{n} outer iterations of the cube50_r10 workload resumed from A_0 "
+                       f"(FP64 NumPy oracle, one BLAS thread, {dt:.1f} s)")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -611,6 +638,7 @@ def main(argv=None):
     if not a.no_cpu_baseline:
         log(f"[bench] cpu baseline (oracle, ~{a.cpu_budget:.0f}s)")
         line["cpu_baseline"] = cpu_baseline(T32, A0, a.cpu_budget)
+        line["cpu_baseline_cube50_one_thread"] = cpu_baseline_c1_one_thread()
     print(json.dumps(line), flush=True)
 
 
