@@ -14,8 +14,8 @@
 //
 // L is the largest eigenvalue of the symmetric G. G is entrywise nonnegative (a Hadamard
 // product of Grams of nonnegative factors), so its largest eigenvalue is its Perron root:
-// power iteration from the all-ones vector (float64, Rayleigh quotient, until it repeats
-// to a few units in the last place or after 100 iterations).
+// power iteration from the all-ones vector (float64, Rayleigh quotient, until it moves by
+// less than 1e-12 relative or after 100 iterations).
 #include "ntf_internal.h"
 
 namespace ntf {
@@ -25,13 +25,29 @@ constexpr int kPgdThreads = 256;
 constexpr int kPowerIters = 100;
 
 // One wave: G in LDS (G is symmetric, so lane t reads column t, conflict-free), lanes own
-// rows t and t + 64; sums over the wave by butterfly shuffles, then lane 0's value is used
-// by every lane. Stops when the Rayleigh quotient repeats to a few units in the last
-// place, at most kPowerIters. Lane 0 then writes the Nesterov weights of every step.
+// rows t and t + 64; sums over the wave by DPP (the same value on every lane). The Rayleigh quotient is formed every fourth iteration; the iteration
+// stops when it moves by less than 1e-12 relative, at most kPowerIters. Lane 0 then
+// writes the Nesterov weights of every step.
+// Sum over the 64 lanes with DPP moves (shuffles through LDS would cost a round trip per
+// step): inclusive sums within each row of 16 lanes (row_shr 1, 2, 4, 8), then the row
+// totals carried by row_bcast 15 and 31, so lane 63 ends with the total, in a fixed order.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWS, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return __shfl(x, 0);
+  x += dpp_d<0x111, 0xF>(x);  // row_shr:1
+  x += dpp_d<0x112, 0xF>(x);  // row_shr:2
+  x += dpp_d<0x114, 0xF>(x);  // row_shr:4
+  x += dpp_d<0x118, 0xF>(x);  // row_shr:8
+  x += dpp_d<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_d<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), 63);
+  return __hiloint2double(hi, lo);
 }
 
 __global__ __launch_bounds__(64) void lipschitz_kernel(const float* __restrict__ G, int r,
@@ -40,31 +56,61 @@ __global__ __launch_bounds__(64) void lipschitz_kernel(const float* __restrict__
   extern __shared__ float s_g[];  // r x r
   __shared__ double s_v[128];
   const int t = threadIdx.x;
-  for (int e = t; e < r * r; e += 64) s_g[e] = G[e];
+  // G into LDS, eight loads in flight per lane (clamped indices, no branch per load)
+  const int rr = r * r;
+  for (int e0 = t; e0 < rr; e0 += 64 * 8) {
+    float gv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) gv[u] = G[min(e0 + 64 * u, rr - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (e0 + 64 * u < rr) s_g[e0 + 64 * u] = gv[u];
+  }
   for (int q = t; q < r; q += 64) s_v[q] = 1.0;
   __syncthreads();
   const bool a0 = t < r, a1 = t + 64 < r;
   double lambda = 0.0, prev = -1.0;
-  for (int it = 0; it < kPowerIters; ++it) {
-    double w0 = 0.0, w1 = 0.0;
-    for (int q = 0; q < r; ++q) {
-      const double vq = s_v[q];
-      if (a0) w0 = fma(double(s_g[q * r + t]), vq, w0);
-      if (a1) w1 = fma(double(s_g[q * r + t + 64]), vq, w1);
+  for (int it = 1; it <= kPowerIters; ++it) {
+    // (G v)[t] and (G v)[t + 64]: four interleaved partial sums so that the LDS reads of
+    // several q are in flight together (rows past r read row 0 and are not used)
+    const int t1 = a1 ? t + 64 : 0;
+    double p0[4] = {0.0, 0.0, 0.0, 0.0}, p1[4] = {0.0, 0.0, 0.0, 0.0};
+    int q = 0;
+    for (; q + 4 <= r; q += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double vq = s_v[q + u];
+        p0[u] = fma(double(s_g[(q + u) * r + (a0 ? t : 0)]), vq, p0[u]);
+        p1[u] = fma(double(s_g[(q + u) * r + t1]), vq, p1[u]);
+      }
     }
-    const double v0 = a0 ? s_v[t] : 0.0, v1 = a1 ? s_v[t + 64] : 0.0;
-    const double vw = wave_sum(v0 * w0 + v1 * w1);
-    const double vv = wave_sum(v0 * v0 + v1 * v1);
+    for (; q < r; ++q) {
+      const double vq = s_v[q];
+      p0[0] = fma(double(s_g[q * r + (a0 ? t : 0)]), vq, p0[0]);
+      p1[0] = fma(double(s_g[q * r + t1]), vq, p1[0]);
+    }
+    const double w0 = a0 ? (p0[0] + p0[1]) + (p0[2] + p0[3]) : 0.0;
+    const double w1 = a1 ? (p1[0] + p1[1]) + (p1[2] + p1[3]) : 0.0;
+    // the Rayleigh quotient (two more sums) every fourth iteration and at the last
+    const bool check = (it & 3) == 0 || it == kPowerIters;
+    if (check) {
+      const double v0 = a0 ? s_v[t] : 0.0, v1 = a1 ? s_v[t + 64] : 0.0;
+      const double vw = wave_sum(v0 * w0 + v1 * w1);
+      const double vv = wave_sum(v0 * v0 + v1 * v1);
+      lambda = vv > 0.0 ? vw / vv : 0.0;
+    }
     const double ww = wave_sum(w0 * w0 + w1 * w1);
-    lambda = vv > 0.0 ? vw / vv : 0.0;
     const double inv = ww > 0.0 ? 1.0 / sqrt(ww) : 0.0;
     __syncthreads();
     if (a0) s_v[t] = w0 * inv;
     if (a1) s_v[t + 64] = w1 * inv;
     __syncthreads();
-    // converged when the quotient repeats to within a few units in the last place
-    if (fabs(lambda - prev) <= 4e-16 * fabs(lambda)) break;
-    prev = lambda;
+    if (check) {
+      // converged when the quotient moves by less than 1e-12 relative in four iterations
+      // (far below the float32 rounding of the steps it scales)
+      if (fabs(lambda - prev) <= 1e-12 * fabs(lambda)) break;
+      prev = lambda;
+    }
   }
   if (t == 0) {
     *L = lambda;
