@@ -136,13 +136,19 @@ __global__ __launch_bounds__(kPgdThreads) void pgd_kernel(PgdArgs a) {
   const int64_t row = int64_t(blockIdx.x) * RB + rl;
   const bool live = row < a.rows && p < a.r;
   const int r = a.r;
+  // column p of G: loads at clamped indices, then a select (a conditional load per entry
+  // would become a branch that waits for each load in turn)
   float g[RP];
 #pragma unroll
-  for (int q = 0; q < RP; ++q) g[q] = (q < r && p < r) ? a.G[q * r + p] : 0.f;
+  for (int q = 0; q < RP; ++q) g[q] = a.G[min(q, r - 1) * r + min(p, r - 1)];
+#pragma unroll
+  for (int q = 0; q < RP; ++q) g[q] = (q < r && p < r) ? g[q] : 0.f;
   const double L = *a.L;
   const float inv_l = L > 0.0 ? float(1.0 / L) : 0.f;
-  const float pv = live ? a.P[row * r + p] : 0.f;
-  float w = live ? a.W0[row * r + p] : 0.f;
+  const int64_t ix = live ? row * r + p : 0;
+  const float pv0 = a.P[ix], w00 = a.W0[ix];
+  const float pv = live ? pv0 : 0.f;
+  float w = live ? w00 : 0.f;
   float y = w;
   for (int s = 0; s < a.steps; ++s) {
     s_y[rl][p] = y;
