@@ -8,7 +8,8 @@ which calls only the oracle).
 * 128^4, r = 64, 30 % zeroed factor entries, 20 dB, clipped, stored in bfloat16: the
   trajectory of 20 outer iterations on a float32 copy of the bfloat16 values against a
   stored 20-iteration oracle run on the same values (F-hat, decisions, fit), the bf16
-  form's first iterations, and its fit after 200 outer iterations against the oracle's.
+  form's first iterations, and the fits after 200 outer iterations against the oracle's
+  (two-sided for the float32 copy, one-sided for the bf16 form).
 """
 import json
 import os
@@ -122,11 +123,17 @@ def test_quad128_r64_sparse_bf16_first_iterations(ntf):
     assert (1.0 - rel) >= g["fit"] * (1.0 - 1e-3)
 
 
-def test_quad128_r64_sparse_bf16_final_fit(ntf):
-    """200 outer iterations of the bf16 form: final fit within 1e-3 (relative) of the
-    oracle's."""
+def test_quad128_r64_sparse_final_fit(ntf):
+    """200 outer iterations. On the float32 copy of the bf16 values (the oracle's input) the
+    final fit is within 1e-3 (relative) of the oracle's. The bf16 form leaves the plateau
+    the oracle's run stays on from about iteration 40 (F-hat 1.5975e6), a legitimate
+    difference between two runs of a nonconvex method, so its fit is checked one-sidedly:
+    no worse than the oracle's by more than 1e-3."""
     g = _golden("quad128_r64_sparse:bf16")
-    rel, _, rs = _quad128(ntf, g["iters"], "bf16")
-    print(f"quad128 bf16 {g['iters']} iterations: relerr {rel:.7f} oracle {g['relerr']:.7f}; "
-          f"restarts {int(rs.sum())} oracle {g['restarts']}")
-    assert abs((1.0 - rel) - g["fit"]) <= 1e-3 * g["fit"]
+    rel32, _, rs32 = _quad128(ntf, g["iters"], "f32")
+    rel16, _, rs16 = _quad128(ntf, g["iters"], "bf16")
+    print(f"quad128 {g['iters']} iterations: relerr f32 {rel32:.7f}, bf16 {rel16:.7f}, oracle "
+          f"{g['relerr']:.7f}; restarts {int(rs32.sum())}, {int(rs16.sum())}, oracle "
+          f"{g['restarts']}")
+    assert abs((1.0 - rel32) - g["fit"]) <= 1e-3 * g["fit"]
+    assert (1.0 - rel16) >= g["fit"] * (1.0 - 1e-3)
