@@ -76,17 +76,27 @@ __global__ __launch_bounds__(64) void lipschitz_kernel(const float* __restrict__
     const int t1 = a1 ? t + 64 : 0;
     double p0[4] = {0.0, 0.0, 0.0, 0.0}, p1[4] = {0.0, 0.0, 0.0, 0.0};
     int q = 0;
+    const int t0 = a0 ? t : 0;
     for (; q + 4 <= r; q += 4) {
+      // all eight LDS reads of G first, so that they are in flight together
+      float g0[4], g1[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const double vq = s_v[q + u];
-        p0[u] = fma(double(s_g[(q + u) * r + (a0 ? t : 0)]), vq, p0[u]);
-        p1[u] = fma(double(s_g[(q + u) * r + t1]), vq, p1[u]);
+        g0[u] = s_g[(q + u) * r + t0];
+        g1[u] = s_g[(q + u) * r + t1];
+      }
+      double vq[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) vq[u] = s_v[q + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        p0[u] = fma(double(g0[u]), vq[u], p0[u]);
+        p1[u] = fma(double(g1[u]), vq[u], p1[u]);
       }
     }
     for (; q < r; ++q) {
       const double vq = s_v[q];
-      p0[0] = fma(double(s_g[q * r + (a0 ? t : 0)]), vq, p0[0]);
+      p0[0] = fma(double(s_g[q * r + t0]), vq, p0[0]);
       p1[0] = fma(double(s_g[q * r + t1]), vq, p1[0]);
     }
     const double w0 = a0 ? (p0[0] + p0[1]) + (p0[2] + p0[3]) : 0.0;
