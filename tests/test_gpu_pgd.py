@@ -90,3 +90,27 @@ def test_gradient_blocks_reject_a_tolerance_and_the_batched_solver(ntf):
         ntf.ntf_solve(Td, A, 2, params=ntf.HerParams(inner="pgd"))
     with pytest.raises(ntf.NtfError, match="A-HALS"):
         ntf.ntf_solve_batched([Td], [A], 2, params=ntf.HerParams(inner="pgd", inner_tol=0.0))
+
+
+def test_gradient_blocks_beyond_the_ahals_row_limit(ntf):
+    """A block of 13000 rows (more than the A-HALS kernel's resident limit of 12288 at r <= 32):
+    A-HALS blocks are refused, projected-gradient blocks (rows are independent) are not."""
+    pr = synth.make_problem((13000, 8, 6), 4, snr_db=30.0, data_seed=8, init_seed=9)
+    T32 = pr.T.astype(np.float32)
+    A0 = [a.astype(np.float32) for a in pr.A0]
+    Td, T64 = dev_tensor(T32, "f32")
+    A = [dev_f32(a) for a in A0]
+    with pytest.raises(ntf.NtfError, match="A-HALS"):
+        ntf.ntf_solve(Td, [a.clone() for a in A], 1)
+    iters = 5
+    params = ntf.HerParams(inner="pgd", inner_tol=0.0, max_inner=50)
+    _, tr = ntf.ntf_solve(Td, A, iters, params=params)
+    torch.cuda.synchronize()
+    ref = oracle.her_solve(T64, [a.astype(np.float64) for a in A0], iters,
+                           params=oracle.HERParams(inner="pgd", inner_tol=0.0, max_inner=50))
+    half_norm2 = 0.5 * float(np.sum(T64 * T64))
+    fh = tr["fhat"].cpu().numpy()
+    for k in range(iters):
+        assert abs(fh[k] - ref.fhat[k]) <= 1e-4 * abs(ref.fhat[k]) + 1e-6 * half_norm2, k
+    f_gpu = oracle.fit(T64, [to_np(a) for a in A])
+    assert abs(f_gpu - oracle.fit(T64, ref.factors)) <= 1e-3 * oracle.fit(T64, ref.factors)
