@@ -226,6 +226,39 @@ def test_hals_fixed_sweeps(ntf, dims, r, n, sweeps):
     assert W_gpu.min() >= 0
 
 
+@pytest.mark.parametrize("rows,r", [(12288, 32), (3072, 128), (3072, 33)])
+def test_hals_largest_covered_blocks(ntf, rows, r):
+    """The largest blocks the A-HALS kernel covers (256 resident workgroups), with the
+    stopping rule at its default tolerance, against the oracle; one row more is refused."""
+    g = np.random.default_rng(rows + r)
+    # B^(n) has many rows in a real block (a Khatri-Rao product), so G = B^T B is far from
+    # singular; a tall B keeps G's conditioning in that range (cond about 1e2-1e3)
+    B = g.random((4000, r))
+    P = (g.random((rows, 4000)).astype(np.float32) @ B.astype(np.float32)).astype(np.float32)
+    G = (B.T @ B).astype(np.float32)
+    W0 = g.random((rows, r)).astype(np.float32)
+    Wd = dev_f32(W0)
+    sw = ntf.ntf_hals_update(Wd, dev_f32(P), dev_f32(G), max_sweeps=10, tol=1e-2)
+    W_ref, s_ref, _ = oracle.hals(W0.astype(np.float64), P.astype(np.float64),
+                                  G.astype(np.float64), max_sweeps=10, tol=1e-2)
+    W_np32 = _hals_f32(W0, P, G, s_ref)
+    err_gpu, err_np = rel_fro(to_np(Wd), W_ref), rel_fro(W_np32, W_ref)
+    print(f"hals rows={rows} r={r} sweeps={int(sw.item())}/{s_ref} gpu={err_gpu:.3e} "
+          f"np32={err_np:.3e}")
+    assert int(sw.item()) == s_ref
+    # The kernel keeps z = q - W current by rank-one updates (equal to the literal update in
+    # exact arithmetic) and re-forms z every 4 sweeps, so up to 4r float32 updates accumulate
+    # between refreshes: a forward error of about sqrt(4r) u cond(G) on top of the literal
+    # float32 sweeps' (u = 2^-24).
+    ev = np.linalg.eigvalsh(G.astype(np.float64))
+    bound = 4 * err_np + np.sqrt(4 * r) * 2.0 ** -24 * (ev[-1] / ev[0])
+    assert err_gpu <= bound, (err_gpu, bound)
+    with pytest.raises(ntf.NtfError, match="EUNSUPPORTED"):
+        ntf.ntf_hals_update(dev_f32(np.zeros((rows + 1, r), np.float32)),
+                            dev_f32(np.zeros((rows + 1, r), np.float32)), dev_f32(G),
+                            max_sweeps=2, tol=0.0)
+
+
 def test_hals_stopping_rule_matches_oracle(ntf):
     # seed chosen so that no sweep's delta ratio lies within 1% of the 1e-2 threshold
     pr = synth.make_problem((300, 40, 50), 16, snr_db=30.0, data_seed=29, init_seed=30)
