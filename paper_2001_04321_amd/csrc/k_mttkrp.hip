@@ -933,13 +933,14 @@ __global__ __launch_bounds__(256) void mttkrp_reduce_kernel(const float* __restr
     const int64_t e = e0 + o;
     double acc = 0.0;
     if (e < n) {
-      // splits g, g + 4, ... in order; eight loads in flight (clamped, no branch per load)
-      for (int64_t q0 = g; q0 < splits; q0 += 32) {
-        float v[8];
+      // splits g, g + 4, ... in order; sixteen loads in flight (clamped, no branch per load)
+      for (int64_t q0 = g; q0 < splits; q0 += 64) {
+        float v[16];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) v[t] = part[std::min<int64_t>(q0 + 4 * t, splits - 1) * n + e];
+        for (int t = 0; t < 16; ++t)
+          v[t] = part[std::min<int64_t>(q0 + 4 * t, splits - 1) * n + e];
 #pragma unroll
-        for (int t = 0; t < 8; ++t)
+        for (int t = 0; t < 16; ++t)
           if (q0 + 4 * t < splits) acc += double(v[t]);
       }
     }
