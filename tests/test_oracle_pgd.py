@@ -91,3 +91,52 @@ def test_plain_bcd_with_gradient_blocks_is_monotone(inner):
     assert np.all(np.diff(f) <= 1e-12 * f[:-1])
     assert min(a.min() for a in res.factors) >= 0.0
     assert not any(res.restart)
+
+
+# Momentum weights (t_{s-1} - 1) / t_s of the accelerated projected gradient with t_0 = 1,
+# t_s = (1 + sqrt(1 + 4 t_{s-1}^2)) / 2 (Sec. 2.2, the reading of Nesterov-type
+# acceleration): t_1 = (1 + sqrt 5) / 2 = 1.6180339887..., t_2 = 2.1935270853...,
+# t_3 = 2.7497913401..., so the weights of the first four extrapolations are
+# 0, 0.2817535251..., 0.4340427828..., 0.5310638054... (worked out by hand once and stored
+# as numbers, not recomputed from the recurrence).
+_NESTEROV_WEIGHTS = (0.0, 0.28175352512532087, 0.434042782780302, 0.5310638054044795)
+
+
+def _diag_accelerated_closed_form(w0, p, g, L, weights):
+    """Accelerated projected gradient on a diagonal G with the projection inactive: every
+    entry follows x_{s+1} = (1 - g/L) y_s + p/L, y_s = x_s + c_s (x_s - x_{s-1}), y_0 = x_0."""
+    a = 1.0 - g / L
+    x_prev, x = None, w0.copy()
+    y = x.copy()
+    out = []
+    for c in weights:
+        x_new = a * y + p / L
+        out.append(x_new)
+        x_prev, x = x, x_new
+        y = x + c * (x - x_prev)
+    return out
+
+
+def test_nesterov_momentum_weights_closed_form():
+    """Four accelerated steps on a diagonal G (projection inactive) equal the closed form with
+    the stored weights; the two plausible slips of the recurrence, the weight
+    (t_s - 1) / t_s and t advanced before the extrapolation, both miss it."""
+    g = np.array([4.0, 1.0, 2.5, 0.6])
+    G = np.diag(g)
+    P = np.array([[8.0, 3.0, 5.0, 1.5], [4.0, 2.0, 9.0, 0.7]])
+    W0 = np.array([[1.0, 0.5, 0.2, 0.3], [0.1, 2.0, 1.0, 0.05]])
+    L = 4.0
+    assert oracle.lipschitz(G) == L
+    ref = _diag_accelerated_closed_form(W0, P, g, L, _NESTEROV_WEIGHTS)
+    assert min(x.min() for x in ref) > 0.0  # projection inactive throughout
+    for steps in (1, 2, 3, 4):
+        W, s, _ = oracle.nesterov(W0, P, G, max_iters=steps, tol=0.0)
+        assert s == steps
+        np.testing.assert_allclose(W, ref[steps - 1], rtol=1e-14, atol=1e-14)
+    # the mutated recurrences give visibly different iterates at step 3 or 4
+    t = [1.0, 1.618033988749895, 2.193527085331054, 2.749791340120445, 3.2948796779470473]
+    slip_weight = [(t[s + 1] - 1.0) / t[s + 1] for s in range(4)]
+    slip_order = [(t[s + 1] - 1.0) / t[s + 2] for s in range(3)] + [0.0]
+    for wrong in (slip_weight, slip_order):
+        bad = _diag_accelerated_closed_form(W0, P, g, L, wrong)
+        assert np.abs(bad[3] - ref[3]).max() > 1e-3
