@@ -23,6 +23,12 @@
 // bfloat16: the wave stages a 64 x 32 tile in LDS in memory order and reads it back with
 // ds_read_b64_tr_b16, which returns 4 consecutive v of one i per lane.
 //
+// Precision of the bfloat16 form: only the stored tensor is bfloat16. The float32 factor
+// block A_v is kept in LDS as two bfloat16 halves (hi + lo, 16 significant bits) and each
+// fragment takes two matrix-core products, so P carries the rounding of T and float32
+// accumulation, not a second rounding of the factors. The kernel is bound by the tensor
+// stream, with the matrix cores mostly idle, so the second product costs no time.
+//
 // Work split: grid = (row tiles of 32*WM rows, splits of the (v-block, u) sequence). WK
 // waves share a row tile and take interleaved 64-element (bf16) / 32-element (f32) chunks
 // of v; their accumulators are summed once at the end. Splits write partial tiles that
@@ -111,10 +117,120 @@ __device__ __forceinline__ uint4 bload16(__amdgpu_buffer_rsrc_t rs, uint32_t byt
   return make_uint4(uint32_t(v.x), uint32_t(v.y), uint32_t(v.z), uint32_t(v.w));
 }
 
+// float32 -> bfloat16 bits, round to nearest even (NaN stays a quiet NaN); branch-free
 __device__ __forceinline__ uint16_t f2bf(float f) {
   const uint32_t b = __float_as_uint(f);
-  if ((b & 0x7fffffffu) > 0x7f800000u) return uint16_t((b >> 16) | 0x40u);
-  return uint16_t((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+  const uint32_t rne = (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+  const uint32_t nan = (b >> 16) | 0x40u;
+  return uint16_t((b & 0x7fffffffu) > 0x7f800000u ? nan : rne);
+}
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
+  return __uint_as_float(uint32_t(b) << 16);
+}
+
+// Stage rows [v0, v0 + vb) of a float32 factor A (I_v x r, row-major) into LDS as the sum
+// of two bf16 values, hi = RNE(x) and lo = RNE(x - hi) (x - hi is exact in float32; hi + lo
+// carries 16 significant bits), transposed: hi[p * ldb + kk], lo at element offset lo_off
+// (zero beyond I_v and r). A thread takes groups of 8 consecutive kk by 4 consecutive p:
+// the group's loads are all issued before any is used (addresses clamped into A, values
+// selected; no branch per load), then it is written as eight 16-byte stores. vb and ldb are
+// multiples of 8; kThreads threads take part. vec: r == RP and A 16-byte aligned (one
+// 16-byte load per row of a group).
+__device__ __forceinline__ void stage_av_hilo(uint16_t* s, int lo_off, int ldb,
+                                              const float* __restrict__ A, int r, int RP,
+                                              int64_t v0, int vb, int64_t Iv, int tid,
+                                              bool vec) {
+  const int np4 = RP / 4;
+  const int n = (vb / 8) * np4;
+  for (int e = tid; e < n; e += kThreads) {
+    const int g8 = e / np4;
+    const int p = (e - g8 * np4) * 4;
+    float x[8][4];
+    if (vec) {
+      float4 t[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t v = v0 + g8 * 8 + j;
+        t[j] = *reinterpret_cast<const float4*>(A + (v < Iv ? v : 0) * r + p);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const bool ok = v0 + g8 * 8 + j < Iv;
+        x[j][0] = ok ? t[j].x : 0.f;
+        x[j][1] = ok ? t[j].y : 0.f;
+        x[j][2] = ok ? t[j].z : 0.f;
+        x[j][3] = ok ? t[j].w : 0.f;
+      }
+    } else {
+      float t[8][4];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t v = v0 + g8 * 8 + j;
+          const bool ok = v < Iv && p + q < r;
+          t[j][q] = A[(ok ? v * r + p + q : 0)];
+        }
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool ok = v0 + g8 * 8 + j < Iv && p + q < r;
+          x[j][q] = ok ? t[j][q] : 0.f;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      union {
+        uint16_t h[8];
+        uint4 v;
+      } hi, lo;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        hi.h[j] = f2bf(x[j][q]);
+        lo.h[j] = f2bf(x[j][q] - bf16_bits_to_f32(hi.h[j]));
+      }
+      *reinterpret_cast<uint4*>(&s[(p + q) * ldb + g8 * 8]) = hi.v;
+      *reinterpret_cast<uint4*>(&s[lo_off + (p + q) * ldb + g8 * 8]) = lo.v;
+    }
+  }
+}
+
+// One work item of a bf16 tensor against an A_v block staged as hi and lo halves:
+// y[nt] += T_frag(t) * (B_hi + B_lo)(t, nt) for the four 8-element K steps t of the item
+// (the lane's T fragment reg[t], B rows col + 32 nt, K offset kk0 + 8 t). NT <= 2: the
+// B fragments are read from LDS in batches of eight, then their products issue back to back
+// (one LDS round trip per batch, not one per product); wider tiles have NT independent
+// products per fragment of T to cover the reads.
+template <int NT>
+__device__ __forceinline__ void mfma_hilo_item(f32x16 (&y)[NT], const uint4 (&reg)[4],
+                                               const uint16_t* s_av, int lo_off, int ldb,
+                                               int kk0, int col) {
+  constexpr int TB = NT >= 4 ? 1 : 4 / NT;
+#pragma unroll
+  for (int t0 = 0; t0 < 4; t0 += TB) {
+    bf16x8 bh[TB][NT], bl[TB][NT];
+#pragma unroll
+    for (int tt = 0; tt < TB; ++tt) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int bo = (nt * 32 + col) * ldb + kk0 + (t0 + tt) * 8;
+        bh[tt][nt] = *reinterpret_cast<const bf16x8*>(&s_av[bo]);
+        bl[tt][nt] = *reinterpret_cast<const bf16x8*>(&s_av[lo_off + bo]);
+      }
+    }
+    if constexpr (NT <= 2) __builtin_amdgcn_sched_barrier(0);  // reads ahead of products
+#pragma unroll
+    for (int tt = 0; tt < TB; ++tt) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&reg[t0 + tt]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        y[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh[tt][nt], y[nt], 0, 0, 0);
+        y[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl[tt][nt], y[nt], 0, 0, 0);
+      }
+    }
+  }
 }
 
 // X[u][p] = prod over the u modes of A_l[u_l, p].
@@ -158,8 +274,10 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_kernel(KArgs k) {
 
   const int vb = k.vb;
   const int ldb = BF16 ? vb + 8 : RP;
-  const size_t av_bytes = align_up(size_t(BF16 ? RP * ldb * 2 : vb * RP * 4), 16);
+  // bf16: the A_v block as hi and lo halves, s_av[p][kk] and s_av[RP * ldb + p * ldb + kk]
+  const size_t av_bytes = align_up(size_t(BF16 ? 2 * RP * ldb * 2 : vb * RP * 4), 16);
   TE* s_av = reinterpret_cast<TE*>(smem);
+  const int lo_off = RP * ldb;  // bf16: element offset of the lo half
   float* s_x = reinterpret_cast<float*>(smem + av_bytes);
   uint16_t* s_stage =
       reinterpret_cast<uint16_t*>(smem + av_bytes + align_up(size_t(k.ub) * RP * 4, 16));
@@ -287,16 +405,8 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_kernel(KArgs k) {
 
   auto compute_item = [&](const uint4 (&reg)[4], int kc) {
     if (BF16 && !LAST) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&reg[t]);
-        const int kk = kc * KCH + half * 32 + t * 8;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&s_av[(nt * 32 + col) * ldb + kk]);
-          y[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, y[nt], 0, 0, 0);
-        }
-      }
+      mfma_hilo_item<NT>(y, reg, reinterpret_cast<const uint16_t*>(s_av), lo_off, ldb,
+                         kc * KCH + half * 32, col);
     } else if (BF16 && LAST) {
       // stage the tile in memory order; transposing reads give K-contiguous fragments
       const int c8 = (lane & 3) * 8;
@@ -308,23 +418,40 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_kernel(KArgs k) {
       const int src = lane & 15;
       const int jj = src >> 2;
       const int s4 = (src & 3) * 4;
+      // NT <= 2: the fragments of TB K steps (T from the stage, B hi and lo) are read
+      // together, then their products issue back to back
+      constexpr int TB = NT >= 4 ? 1 : 4 / NT;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int kq = 16 * t + 8 * (g >> 1);
+      for (int t0 = 0; t0 < 4; t0 += TB) {
         union {
           i16x4 h[2];
           bf16x8 v;
-        } a;
-        a.h[0] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-            (lds_i16x4*)(&stage[(kq + jj) * kStageLd + m0 + s4]));
-        a.h[1] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-            (lds_i16x4*)(&stage[(kq + 4 + jj) * kStageLd + m0 + s4]));
-        const int kk = kc * KCH + 16 * t + 8 * half;
+        } a[TB];
+        bf16x8 bh[TB][NT], bl[TB][NT];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&s_av[(nt * 32 + col) * ldb + kk]);
-          y[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, b, y[nt], 0, 0, 0);
+        for (int tt = 0; tt < TB; ++tt) {
+          const int t = t0 + tt;
+          const int kq = 16 * t + 8 * (g >> 1);
+          a[tt].h[0] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+              (lds_i16x4*)(&stage[(kq + jj) * kStageLd + m0 + s4]));
+          a[tt].h[1] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+              (lds_i16x4*)(&stage[(kq + 4 + jj) * kStageLd + m0 + s4]));
+          const int kk = kc * KCH + 16 * t + 8 * half;
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const int bo = (nt * 32 + col) * ldb + kk;
+            bh[tt][nt] = *reinterpret_cast<const bf16x8*>(&s_av[bo]);
+            bl[tt][nt] = *reinterpret_cast<const bf16x8*>(&s_av[lo_off + bo]);
+          }
         }
+        if constexpr (NT <= 2) __builtin_amdgcn_sched_barrier(0);  // reads ahead of products
+#pragma unroll
+        for (int tt = 0; tt < TB; ++tt)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            y[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[tt].v, bh[tt][nt], y[nt], 0, 0, 0);
+            y[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[tt].v, bl[tt][nt], y[nt], 0, 0, 0);
+          }
       }
     } else {
       const float* rf = reinterpret_cast<const float*>(reg);
@@ -380,39 +507,9 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_kernel(KArgs k) {
     if (vbi != cur_vb) {
       lds_barrier();
       const int nv = int(std::min<int64_t>(vb, k.Iv - v0));
-      if (BF16 && k.av_vec) {
-        // r == RP and A_v 16-byte aligned: the block is contiguous; 16-byte loads, eight
-        // in flight per thread, converted and written transposed (s_av[p][kk])
-        const int n4 = vb * RP / 4;
-        const float4* src = reinterpret_cast<const float4*>(k.Av + v0 * RP);
-        uint16_t* d = reinterpret_cast<uint16_t*>(s_av);
-        for (int b0 = tid; b0 < n4; b0 += kThreads * 8) {
-          float4 t[8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int e4 = b0 + j * kThreads;
-            t[j] = (e4 < n4 && (e4 * 4) / RP < nv) ? src[e4] : make_float4(0.f, 0.f, 0.f, 0.f);
-          }
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int e4 = b0 + j * kThreads;
-            if (e4 >= n4) continue;
-            const int kk = (e4 * 4) / RP;
-            const int p = e4 * 4 - kk * RP;
-            d[(p + 0) * ldb + kk] = f2bf(t[j].x);
-            d[(p + 1) * ldb + kk] = f2bf(t[j].y);
-            d[(p + 2) * ldb + kk] = f2bf(t[j].z);
-            d[(p + 3) * ldb + kk] = f2bf(t[j].w);
-          }
-        }
-      } else if (BF16) {
-        for (int e = tid; e < vb * RP; e += kThreads) {
-          const int kk = e / RP;
-          const int p = e - kk * RP;
-          const int64_t v = v0 + kk;
-          reinterpret_cast<uint16_t*>(s_av)[p * ldb + kk] =
-              f2bf((p < k.r && v < k.Iv) ? k.Av[v * k.r + p] : 0.f);
-        }
+      if (BF16) {
+        stage_av_hilo(reinterpret_cast<uint16_t*>(s_av), lo_off, ldb, k.Av, k.r, RP, v0, vb,
+                      k.Iv, tid, k.av_vec != 0);
       } else if (k.av_vec) {
         // r == RP and A_v 16-byte aligned: the block is contiguous; 16-byte loads, eight
         // in flight per thread
@@ -565,6 +662,7 @@ struct SArgs {
   FastDiv fd_Rp;
   int64_t I_in, nb_in, nbatch, S;
   int r, vb;
+  int av_vec;                  // A_v rows are RP floats (r == RP) and 16-byte aligned
   int nh;
   HadamardLaunch had;
 };
@@ -582,8 +680,9 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_slab_kernel(SArgs k) {
   constexpr int NW = kThreads / 64;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int ldb = k.vb + 8;
-  uint16_t* s_av = reinterpret_cast<uint16_t*>(smem);
-  float* s_ain = reinterpret_cast<float*>(smem + align_up(size_t(RP) * ldb * 2, 16));
+  uint16_t* s_av = reinterpret_cast<uint16_t*>(smem);  // A_v hi half; the lo half follows
+  const int lo_off = RP * ldb;
+  float* s_ain = reinterpret_cast<float*>(smem + align_up(size_t(2) * RP * ldb * 2, 16));
   float* s_red = s_ain + k.I_in * RP;
 
   const int tid = threadIdx.x;
@@ -637,12 +736,9 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_slab_kernel(SArgs k) {
 #pragma unroll
   for (int d = 0; d < PD - 1; ++d) prefetch(buf[d]);
 
-  // A_v (bf16, s_av[p][v]) and A_in (float32, s_ain[j][p]) into LDS, zero-padded
-  for (int e = tid; e < k.vb * RP; e += kThreads) {
-    const int kk = e / RP;
-    const int p = e - kk * RP;
-    s_av[p * ldb + kk] = f2bf((p < k.r && kk < k.Iv) ? k.Av[int64_t(kk) * k.r + p] : 0.f);
-  }
+  // A_v (bf16 hi and lo halves, s_av[p][v]) and A_in (float32, s_ain[j][p]) into LDS,
+  // zero-padded
+  stage_av_hilo(s_av, lo_off, ldb, k.Av, k.r, RP, 0, k.vb, k.Iv, tid, k.av_vec != 0);
   for (int64_t e = tid; e < k.I_in * RP; e += kThreads) {
     const int64_t j = e / RP;
     const int p = int(e - j * RP);
@@ -669,16 +765,7 @@ __global__ __launch_bounds__(kThreads, 2) void mttkrp_slab_kernel(SArgs k) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) y[nt][e] = 0.f;
         }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const bf16x8 av = *reinterpret_cast<const bf16x8*>(&buf[d][t]);
-          const int kk = cc * KCH + half * 32 + t * 8;
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt) {
-            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&s_av[(nt * 32 + col) * ldb + kk]);
-            y[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, y[nt], 0, 0, 0);
-          }
-        }
+        mfma_hilo_item<NT>(y, buf[d], s_av, lo_off, ldb, cc * KCH + half * 32, col);
         if (cc == nkc - 1) {
           // fold the batch: acc[u, p] += C[p] * A_in[j(u), p] * Z[u, p]
           const int64_t b = b_beg + wave + NW * cm;
@@ -759,10 +846,6 @@ struct F4Args {
 };
 
 constexpr int kF4Ld = 136;  // LDS row stride (elements) of the slab and the factor blocks
-
-__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
-  return __uint_as_float(uint32_t(b) << 16);
-}
 
 template <int NT>
 __global__ __launch_bounds__(kThreads, 2) void mttkrp_fused4_kernel(F4Args k) {
@@ -1076,7 +1159,7 @@ int n_tiles(int r) {
 }
 
 size_t lds_bytes(bool bf16, bool last, int rp, int vb, int ub) {
-  const size_t av = bf16 ? size_t(rp) * (vb + 8) * 2 : size_t(vb) * rp * 4;
+  const size_t av = bf16 ? size_t(2) * rp * (vb + 8) * 2 : size_t(vb) * rp * 4;
   size_t b = align_up(av, 16) + align_up(size_t(ub) * rp * 4, 16);
   if (bf16 && last) b += size_t(4) * 64 * kStageLd * 2;
   return b;
@@ -1110,7 +1193,7 @@ static size_t slab_lds(const MttkrpPlan& pl, const ntf_tensor& T) {
   const int64_t I_in = T.dims[inner];
   if (I_in < 16) return 0;
   const int64_t vb = ceil_div(pl.Iv, int64_t(64)) * 64;
-  const size_t lds = align_up(size_t(pl.rpad) * (vb + 8) * 2, 16) + size_t(I_in) * pl.rpad * 4 +
+  const size_t lds = align_up(size_t(2) * pl.rpad * (vb + 8) * 2, 16) + size_t(I_in) * pl.rpad * 4 +
                      size_t(kThreads / 64) * pl.rpad * 4;
   return lds > 72 * 1024 ? 0 : lds;
 }
@@ -1191,7 +1274,7 @@ MttkrpPlan plan_mttkrp(const ntf_tensor& T, int mode, int r, int num_cus, bool s
   pl.wk = 4 / pl.wm;
   // v-block: all of I_v when its A_v block fits 64 KB of LDS
   const int kch = bf16 ? 64 : 32;
-  const int64_t per_k = bf16 ? int64_t(pl.rpad) * 2 : int64_t(pl.rpad) * 4;
+  const int64_t per_k = int64_t(pl.rpad) * 4;  // bf16: hi and lo halves
   int64_t vbmax = (64 * 1024) / per_k - (bf16 ? 8 : 0);
   vbmax = std::max<int64_t>(kch, vbmax / kch * kch);
   const int64_t iv_pad = ceil_div(pl.Iv, kch) * kch;
@@ -1288,6 +1371,7 @@ static hipError_t launch_slab(const MttkrpPlan& pl, const void* T, const FactorP
   k.S = pl.splits;
   k.r = pl.r;
   k.vb = pl.vb;
+  k.av_vec = (pl.r == pl.rpad && (reinterpret_cast<uintptr_t>(k.Av) & 15) == 0) ? 1 : 0;
   const bool split = pl.splits > 1;
   k.out = split ? partials : P;
   SlabFn fn = select_slab(pl.variant);

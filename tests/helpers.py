@@ -23,6 +23,18 @@ def rel_fro(x, ref) -> float:
     return float(np.linalg.norm((x - ref).ravel()) / (den if den > 0 else 1.0))
 
 
+def elementwise_err(x, ref, scale) -> float:
+    """max |x - ref| / scale over the elements (scale: the sum of the absolute terms of
+    each element, e.g. the MTTKRP of |T| with |A|; zero-scale elements must match exactly)."""
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.abs(np.asarray(scale, dtype=np.float64))
+    d = np.abs(x - ref)
+    if np.any(d[scale == 0] != 0):
+        return float("inf")
+    return float(np.max(np.where(scale > 0, d / np.where(scale > 0, scale, 1.0), 0.0)))
+
+
 def dev_f32(x):
     import torch
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()

@@ -2,7 +2,13 @@
 identical inputs (the float32 / bfloat16 values the GPU sees, upcast to float64).
 
 Tolerances (relative Frobenius unless stated):
-  MTTKRP float32 <= 1e-5, bfloat16 <= 2e-2; Gram float64 <= 1e-13, float32 <= 1e-6;
+  MTTKRP <= 1e-5 for both forms (the oracle sees the values the tensor holds: the bf16 form
+  rounds only the stored tensor, the factors enter the matrix cores as bf16 hi + lo
+  halves), and elementwise |P - P_ref| <= 2e-5 times the sum of the absolute terms of that
+  element (float32 accumulation over up to a few hundred sequential adds, and the hi + lo
+  split's 2^-18 relative remainder per factor value); the fused all-mode 4-way kernel, whose
+  factor blocks are bf16 only, <= 2e-2 (the north-star bound for the reduced-precision path);
+  Gram float64 <= 1e-13, float32 <= 1e-6;
   A-HALS (fixed sweeps) <= 4x the error of a plain numpy float32 run of the same sweeps;
   extrapolation bit-exact (both sides evaluate the same float64 expression, then round);
   F-hat |diff| <= 1e-12 ||T||^2; ||T||^2 <= 1e-13; bf16 cast bit-exact.
@@ -12,7 +18,7 @@ import pytest
 
 import oracle
 import synth
-from tests.helpers import dev_f32, dev_tensor, ensure_built, rel_fro, to_np
+from tests.helpers import dev_f32, dev_tensor, elementwise_err, ensure_built, rel_fro, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -52,13 +58,14 @@ def test_mttkrp_matches_oracle(ntf, dims, r, dtype):
     Td, T64 = dev_tensor(T, dtype)
     Ad = [dev_f32(a) for a in A]
     A64 = [a.astype(np.float64) for a in A]
-    tol = 1e-5 if dtype == "f32" else 2e-2
     for n in range(len(dims)):
         P = to_np(ntf.ntf_mttkrp(Td, Ad, n))
         ref = oracle.mttkrp(T64, A64, n)
         err = rel_fro(P, ref)
-        print(f"mttkrp {dtype} dims={dims} r={r} mode={n} relerr={err:.3e}")
-        assert err <= tol, (n, err)
+        ew = elementwise_err(P, ref, ref)
+        print(f"mttkrp {dtype} dims={dims} r={r} mode={n} relerr={err:.3e} elementwise={ew:.3e}")
+        assert err <= 1e-5, (n, err)
+        assert ew <= 2e-5, (n, ew)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
@@ -77,7 +84,9 @@ def test_mttkrp_signed_data_and_determinism(ntf, dtype):
         # signed data cancels: compare against the scale of the terms, not of the sum
         scale = oracle.mttkrp(np.abs(T64), [a.astype(np.float64) for a in A], n)
         err = np.abs(to_np(P1) - ref).max() / np.abs(scale).max()
-        assert err <= (1e-6 if dtype == "f32" else 1e-2)
+        print(f"signed {dtype} mode={n} max error / max scale {err:.3e}")
+        assert err <= 1e-6
+        assert elementwise_err(to_np(P1), ref, scale) <= 2e-5
 
 
 # bf16 tensors whose row stride (in the mode under test) is a multiple of 1 MiB: that
@@ -102,8 +111,10 @@ def test_mttkrp_row_slab_modes(ntf, dims, r, mode):
     assert torch.equal(P1, P2)
     ref = oracle.mttkrp(T64, A64, mode)
     err = rel_fro(to_np(P1), ref)
-    print(f"slab dims={dims} r={r} mode={mode} relerr={err:.3e}")
-    assert err <= 2e-2
+    ew = elementwise_err(to_np(P1), ref, ref)
+    print(f"slab dims={dims} r={r} mode={mode} relerr={err:.3e} elementwise={ew:.3e}")
+    assert err <= 1e-5
+    assert ew <= 2e-5
 
 
 @pytest.mark.parametrize("dims,r,dtype,modes", [
@@ -133,7 +144,8 @@ def test_mttkrp_multi(ntf, dims, r, dtype, modes):
 
 
 def test_mttkrp_multi_full_size_quad128(ntf):
-    """The fused all-mode kernel on the 128^4 bf16 r = 64 workload; rows sampled."""
+    """The fused all-mode kernel on the 128^4 bf16 r = 64 workload; one row in every
+    32-row tile of each mode."""
     pr = synth.workload("quad128_r64_sparse")
     Td, T64 = dev_tensor(pr.T, "bf16")
     A = [a.astype(np.float32) for a in pr.A0]
@@ -142,7 +154,7 @@ def test_mttkrp_multi_full_size_quad128(ntf):
     A64 = [a.astype(np.float64) for a in A]
     g = np.random.default_rng(1)
     for n in range(4):
-        rows = sorted(set([0, 127] + list(g.integers(0, 128, 3))))
+        rows = tile_rows(128, g)
         err = rel_fro(to_np(out[n])[rows], oracle.mttkrp_rows(T64, A64, n, rows))
         print(f"fused quad128 mode={n} rows={rows} relerr={err:.3e}")
         assert err <= 2e-2
@@ -154,23 +166,36 @@ FULL = [("cube400_r32_corr", "f32"), ("cube400_r32_corr", "bf16"),
         ("quad128_r64_sparse", "bf16"), ("cube512_r50", "f32")]
 
 
+def tile_rows(I, g, tile=32):
+    """One random row in every 32-row tile, plus the first and the last row."""
+    rows = {0, I - 1}
+    for t0 in range(0, I, tile):
+        rows.add(int(g.integers(t0, min(I, t0 + tile))))
+    return sorted(rows)
+
+
 @pytest.mark.parametrize("name,dtype", FULL)
-def test_mttkrp_full_size_sampled_rows(ntf, name, dtype):
-    """Full workload sizes, in the launch configuration the solver uses; rows sampled."""
+def test_mttkrp_full_size(ntf, name, dtype):
+    """Full workload sizes, in the launch configuration the solver uses. 400^3: every row
+    (the oracle's full MTTKRP is one library product); 128^4 and 512^3: one row in every
+    32-row tile and both ends. Relative Frobenius <= 1e-5 and the elementwise bound."""
     pr = synth.workload(name)
     Td, T64 = dev_tensor(pr.T, dtype)
     A = [a.astype(np.float32) for a in pr.A0]
+    del pr
     Ad = [dev_f32(a) for a in A]
     A64 = [a.astype(np.float64) for a in A]
-    tol = 1e-5 if dtype == "f32" else 2e-2
     g = np.random.default_rng(0)
+    full = T64.shape[0] == 400
     for n in range(T64.ndim):
         P = to_np(ntf.ntf_mttkrp(Td, Ad, n))
-        rows = sorted(set([0, T64.shape[n] - 1] + list(g.integers(0, T64.shape[n], 4))))
-        ref = oracle.mttkrp_rows(T64, A64, n, rows)
+        rows = list(range(T64.shape[n])) if full else tile_rows(T64.shape[n], g)
+        ref = oracle.mttkrp(T64, A64, n) if full else oracle.mttkrp_rows(T64, A64, n, rows)
         err = rel_fro(P[rows], ref)
-        print(f"{name} {dtype} mode={n} rows={rows} relerr={err:.3e}")
-        assert err <= tol
+        ew = elementwise_err(P[rows], ref, ref)  # T >= 0 and A >= 0: the terms are >= 0
+        print(f"{name} {dtype} mode={n} rows={len(rows)} relerr={err:.3e} elementwise={ew:.3e}")
+        assert err <= 1e-5
+        assert ew <= 2e-5
     del Td
     torch.cuda.empty_cache()
 

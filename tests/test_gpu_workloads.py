@@ -8,8 +8,8 @@ which calls only the oracle).
 * 128^4, r = 64, 30 % zeroed factor entries, 20 dB, clipped, stored in bfloat16: the
   trajectory of 20 outer iterations on a float32 copy of the bfloat16 values against a
   stored 20-iteration oracle run on the same values (F-hat, decisions, fit), the bf16
-  form's first iterations, and the fits after 200 outer iterations against the oracle's
-  (two-sided for the float32 copy, one-sided for the bf16 form).
+  form's first iterations, and both forms' fits after 200 outer iterations against the
+  oracle's (two-sided).
 """
 import json
 import os
@@ -108,27 +108,25 @@ def test_quad128_r64_sparse_trajectory(ntf):
 
 
 def test_quad128_r64_sparse_bf16_first_iterations(ntf):
-    """20 outer iterations of the bf16 form: the first F-hat values within 2 % (the bf16
-    rounding of the MTTKRP becomes a few per cent of F-hat through its cancellation at
-    20 dB), and a fit no worse than the oracle's. Later iterations can legitimately part
-    from the oracle's trajectory (here the oracle's run lingers on a plateau that the bf16
-    run leaves), so the fits after 20 iterations are compared one-sidedly."""
+    """20 outer iterations of the bf16 form. Its MTTKRP rounds only the stored tensor, whose
+    values are the oracle's input, so the first F-hat values agree with the oracle's to
+    1e-5 F-hat_0 (float32 accumulation), and the fit after 20 iterations is within 1e-3 of
+    the oracle's (two-sided)."""
     g = _golden("quad128_r64_sparse:bf16:20")
     rel, fh, rs = _quad128(ntf, g["iters"], "bf16")
+    dev = np.abs(fh - np.asarray(g["fhat"]))
     print(f"quad128 bf16 20 iterations: relerr {rel:.7f} oracle {g['relerr']:.7f}; restarts "
-          f"{int(rs.sum())} oracle {g['restarts']}")
+          f"{int(rs.sum())} oracle {g['restarts']}; F-hat deviation per iteration / F-hat_0 "
+          f"{np.array2string(dev / g['fhat0'], precision=2)}")
     for k in range(3):
-        assert fh[k] == pytest.approx(g["fhat"][k], rel=2e-2), k
+        assert dev[k] <= 1e-5 * g["fhat0"], k
         assert not rs[k]
-    assert (1.0 - rel) >= g["fit"] * (1.0 - 1e-3)
+    assert abs((1.0 - rel) - g["fit"]) <= 1e-3 * g["fit"]
 
 
 def test_quad128_r64_sparse_final_fit(ntf):
-    """200 outer iterations. On the float32 copy of the bf16 values (the oracle's input) the
-    final fit is within 1e-3 (relative) of the oracle's. The bf16 form leaves the plateau
-    the oracle's run stays on from about iteration 40 (F-hat 1.5975e6), a legitimate
-    difference between two runs of a nonconvex method, so its fit is checked one-sidedly:
-    no worse than the oracle's by more than 1e-3."""
+    """200 outer iterations, the float32 copy of the bf16 values (the oracle's input) and
+    the bf16 form: both final fits within 1e-3 (relative) of the oracle's (R17)."""
     g = _golden("quad128_r64_sparse:bf16")
     rel32, _, rs32 = _quad128(ntf, g["iters"], "f32")
     rel16, _, rs16 = _quad128(ntf, g["iters"], "bf16")
@@ -136,4 +134,4 @@ def test_quad128_r64_sparse_final_fit(ntf):
           f"{g['relerr']:.7f}; restarts {int(rs32.sum())}, {int(rs16.sum())}, oracle "
           f"{g['restarts']}")
     assert abs((1.0 - rel32) - g["fit"]) <= 1e-3 * g["fit"]
-    assert (1.0 - rel16) >= g["fit"] * (1.0 - 1e-3)
+    assert abs((1.0 - rel16) - g["fit"]) <= 1e-3 * g["fit"]
