@@ -152,6 +152,18 @@ ntf_status ntf_cast_bf16(ntf_handle* h, const float* src, uint16_t* dst, int64_t
 ntf_status ntf_mttkrp(ntf_handle* h, const ntf_tensor* T, const float* const* A, int32_t r,
                       int32_t mode, float* P, void* stream);
 
+/* ntf_mttkrp for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): same arguments, same
+ * kernels, same launch shapes and the same bits in P. The split partials live in a static
+ * device array of 16 MiB per device (resolved when the handle is created) instead of the
+ * handle's workspace; no call allocates. A mode whose partials would exceed it (splits x
+ * I_mode x r floats, e.g. beyond 4M floats) returns NTF_EUNSUPPORTED with nothing written;
+ * ntf_mttkrp covers it. Calls on one device share the array: calls that overlap on one
+ * GPU (different streams, or different handles of the same device) race; calls ordered on
+ * one stream do not (each writes every partial it reads). */
+ntf_status ntf_mttkrp_noalloc(ntf_handle* h, const ntf_tensor* T, const float* const* A,
+                              int32_t r, int32_t mode, float* P, void* stream);
+
 /* The MTTKRPs of every mode n with bit n of `mask` set, all with the same factors (the
  * partial derivatives of the objective for every block at one point, Sec. 2, eq.
  * def:grad), in as few passes over T as the shapes allow: for a 3-way tensor the first

@@ -4,7 +4,8 @@ Every function here marshals torch tensors (device memory, current stream) into 
 declared in include/ntf.h and calls it; all arithmetic runs in the library's HIP kernels.
 There is no CPU fallback: if libntf.so is missing the import of a call raises.
 
-Functions carry the C names: ntf_norm2, ntf_cast_bf16, ntf_mttkrp, ntf_mttkrp_multi,
+Functions carry the C names: ntf_norm2, ntf_cast_bf16, ntf_mttkrp, ntf_mttkrp_noalloc,
+ntf_mttkrp_multi,
 ntf_mttkrp_autotune,
 ntf_tune_export, ntf_tune_import, ntf_gram, ntf_hals_update, ntf_pgd_update, ntf_her_step,
 ntf_error,
@@ -28,7 +29,7 @@ __all__ = [
     "ntf_residual_norm2", "ntf_device_flags", "new_state", "state_dict", "ntf_cp_loss",
     "ntf_cp_grad", "NTFLoss", "ntf_loss", "ntf_solve_batched", "ntf_mttkrp_autotune",
     "ntf_tune_export", "ntf_tune_import", "save_tuning", "load_tuning", "ntf_mttkrp_multi",
-    "ntf_pgd_update",
+    "ntf_pgd_update", "ntf_mttkrp_noalloc",
 ]
 
 _DTYPES = {torch.float32: _abi.NTF_F32, torch.bfloat16: _abi.NTF_BF16}
@@ -143,15 +144,63 @@ def ntf_cast_bf16(x: torch.Tensor, h=None, stream=None) -> torch.Tensor:
     return out
 
 
-def ntf_mttkrp(T: torch.Tensor, factors, mode: int, out: torch.Tensor | None = None, h=None,
-               stream=None) -> torch.Tensor:
-    r = int(factors[(mode + 1) % T.dim()].shape[1])
-    out = torch.empty((T.shape[mode], r), dtype=torch.float32, device=T.device) if out is None else out
+def _check_shape(t: torch.Tensor, shape, name: str) -> None:
+    if tuple(t.shape) != tuple(int(x) for x in shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _check_factors(T: torch.Tensor, factors, skip=()) -> int:
+    """The factor list matches T (one I_l x r float32 factor per mode, on T's device; modes
+    in `skip` may be None) and the common rank r, which is returned. The C ABI receives raw
+    pointers, so shapes can only be checked here."""
+    factors = list(factors)
+    if len(factors) != T.dim():
+        raise ValueError(f"{len(factors)} factors for a {T.dim()}-way tensor")
+    r = None
+    for l, A in enumerate(factors):
+        if A is None:
+            if l in skip:
+                continue
+            raise ValueError(f"factor {l} is None")
+        if A.dim() != 2:
+            raise ValueError(f"factor {l} must be a matrix (I_{l} x r), got {A.dim()} dims")
+        if r is None:
+            r = int(A.shape[1])
+        _check_shape(A, (T.shape[l], r), f"factor {l}")
+        if A.device != T.device:
+            raise ValueError(f"factor {l} is on {A.device}, the tensor on {T.device}")
+    if r is None:
+        raise ValueError("no factor given")
+    return r
+
+
+def _mttkrp_args(T, factors, mode, out):
+    if not 0 <= int(mode) < T.dim():
+        raise ValueError(f"mode {mode} outside [0, {T.dim()})")
+    r = _check_factors(T, factors, skip=(int(mode),))
+    if out is None:
+        out = torch.empty((T.shape[mode], r), dtype=torch.float32, device=T.device)
+    _check_shape(out, (T.shape[mode], r), "out")
     d = _tensor_desc(T)
     ptrs = ptr_array([(_dev(A, f"A[{l}]", torch.float32) if (A is not None and l != mode) else None)
                       for l, A in enumerate(factors)])
+    return r, out, d, ptrs
+
+
+def ntf_mttkrp(T: torch.Tensor, factors, mode: int, out: torch.Tensor | None = None, h=None,
+               stream=None) -> torch.Tensor:
+    r, out, d, ptrs = _mttkrp_args(T, factors, mode, out)
     check(lib().ntf_mttkrp(_h(h), C.byref(d), ptrs, r, int(mode), _dev(out, "P", torch.float32),
                            _stream(stream)))
+    return out
+
+
+def ntf_mttkrp_noalloc(T: torch.Tensor, factors, mode: int, out: torch.Tensor, h=None,
+                       stream=None) -> torch.Tensor:
+    """ntf_mttkrp without any device allocation in the library (the caller passes `out`)."""
+    r, out, d, ptrs = _mttkrp_args(T, factors, mode, out)
+    check(lib().ntf_mttkrp_noalloc(_h(h), C.byref(d), ptrs, r, int(mode),
+                                   _dev(out, "P", torch.float32), _stream(stream)))
     return out
 
 

@@ -60,6 +60,8 @@ SIGNATURES = {
     "ntf_norm2": (C.c_int, [PTR, C.POINTER(NtfTensor), PTR, PTR]),
     "ntf_cast_bf16": (C.c_int, [PTR, PTR, PTR, C.c_int64, PTR]),
     "ntf_mttkrp": (C.c_int, [PTR, C.POINTER(NtfTensor), PTRS, C.c_int32, C.c_int32, PTR, PTR]),
+    "ntf_mttkrp_noalloc": (C.c_int, [PTR, C.POINTER(NtfTensor), PTRS, C.c_int32, C.c_int32, PTR,
+                                     PTR]),
     "ntf_gram": (C.c_int, [PTR, PTRS, I64S, C.c_int32, C.c_int32, C.c_int32, PTR, PTR, PTR]),
     "ntf_hals_update": (C.c_int, [PTR, PTR, PTR, PTR, C.c_int64, C.c_int32, C.c_int32,
                                   C.c_double, PTR, PTR]),

@@ -17,20 +17,6 @@ namespace ntf {
 namespace {
 thread_local char g_err[1024] = "";
 
-// Makes the handle's device current for the duration of a call, then restores it.
-struct DeviceGuard {
-  int old = -1;
-  bool ok = true;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&old) != hipSuccess) old = -1;
-    if (old != dev) ok = hipSetDevice(dev) == hipSuccess;
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
-  }
-};
-
 inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 }  // namespace
@@ -162,6 +148,14 @@ ntf_status ntf_handle_create(ntf_handle** out, int device) {
   h->device = device;
   h->num_cus = prop.multiProcessorCount;
   h->lds_per_block = prop.sharedMemPerBlock;
+  // the scratch-free entry point's device array: its address on this device, once
+  {
+    const ntf_status st = noalloc_scratch_attach(device);
+    if (st != NTF_OK) {
+      delete h;
+      return st;
+    }
+  }
   if (hipMalloc(&h->dev_flags, sizeof(uint32_t)) != hipSuccess) {
     delete h;
     set_error("flag allocation failed");

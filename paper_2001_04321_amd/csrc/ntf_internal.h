@@ -122,6 +122,24 @@ void release_solve_graph(ntf_handle* h);
 // it has to grow, invalidating cached graphs).
 ntf_status ensure_workspace(ntf_handle* h, size_t bytes);
 
+// Makes a device current for the duration of a call, then restores the previous one.
+struct DeviceGuard {
+  int old = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old) != hipSuccess) old = -1;
+    if (old != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+  }
+};
+
+// Resolve (once per device, with that device current) the device address of the
+// scratch-free MTTKRP's static scratch array; called when a handle is created.
+ntf_status noalloc_scratch_attach(int device);
+
 // Validation helpers shared by the entry points (set the thread-local error message).
 ntf_status check_tensor(const ntf_tensor* T);
 ntf_status check_rank(int32_t r);
