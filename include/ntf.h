@@ -92,7 +92,8 @@ typedef struct ntf_her_params {
 typedef struct ntf_her_state {
   double beta;         /* extrapolation weight used by the next extrapolation step */
   double beta_bar;     /* upper bound of beta */
-  double fhat_prev;    /* F-hat of the last completed iteration (F(A_0) after INIT) */
+  double fhat_prev;    /* F-hat of the last completed iteration (F(A_0) after INIT); a
+                          non-finite F-hat restarts and leaves the last finite value here */
   double fhat;         /* F-hat_k of the last DECIDE */
   int64_t k;           /* completed outer iterations since INIT */
   int32_t restart;     /* 1 if the last DECIDE restarted, else 0 */
@@ -128,8 +129,18 @@ const char* ntf_last_error(void);
 const char* ntf_status_string(ntf_status s);
 /* Library version string. */
 const char* ntf_version(void);
-/* Synchronize `stream`, then read and clear the handle's device flag word (NTF_FLAG_*). */
+/* Synchronize `stream`, then read and clear the handle's device flag word (NTF_FLAG_*).
+ * The calls below are asynchronous and return NTF_OK once enqueued; conditions found on
+ * the device while they run (a bounded wait that gave up, a non-finite F-hat) are
+ * reported here, never by the enqueueing call. */
 ntf_status ntf_device_flags(ntf_handle* h, void* stream, uint32_t* flags_out);
+/* Time after which a bounded cross-workgroup wait of the A-HALS kernel (its stopping rule,
+ * Sec. 4.1, is decided across workgroups) gives up: the kernel then finishes its sweep
+ * loop at once, writes its current iterate and raises NTF_FLAG_WAIT_TIMEOUT. Default 2 s,
+ * far above any legitimate wait; seconds in [0, 60]. 0 makes every wait that is not
+ * already satisfied give up, which lets tests force the time-out path from the host.
+ * Takes effect for later calls (a cached solver graph is rebuilt). */
+ntf_status ntf_handle_set_wait_limit(ntf_handle* h, double seconds);
 
 /* ------------------------------------------------------------------ hot-path steps --- */
 

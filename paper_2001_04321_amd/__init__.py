@@ -29,7 +29,7 @@ __all__ = [
     "ntf_residual_norm2", "ntf_device_flags", "new_state", "state_dict", "ntf_cp_loss",
     "ntf_cp_grad", "NTFLoss", "ntf_loss", "ntf_solve_batched", "ntf_mttkrp_autotune",
     "ntf_tune_export", "ntf_tune_import", "save_tuning", "load_tuning", "ntf_mttkrp_multi",
-    "ntf_pgd_update", "ntf_mttkrp_noalloc",
+    "ntf_pgd_update", "ntf_mttkrp_noalloc", "ntf_handle_set_wait_limit",
 ]
 
 _DTYPES = {torch.float32: _abi.NTF_F32, torch.bfloat16: _abi.NTF_BF16}
@@ -208,7 +208,11 @@ def ntf_pgd_update(W: torch.Tensor, P: torch.Tensor, G: torch.Tensor, steps: int
                    accel: bool = False, h=None, stream=None) -> torch.Tensor:
     """Projected-gradient block solver in place on W; returns L = ||G||_2 (device double)."""
     L = torch.empty((), dtype=torch.float64, device=W.device)
+    if W.dim() != 2:
+        raise ValueError(f"W must be a matrix (I x r), got shape {tuple(W.shape)}")
     rows, r = int(W.shape[0]), int(W.shape[1])
+    _check_shape(P, (rows, r), "P")
+    _check_shape(G, (r, r), "G")
     check(lib().ntf_pgd_update(_h(h), _dev(W, "W", torch.float32), _dev(P, "P", torch.float32),
                                _dev(G, "G", torch.float32), rows, r, int(steps),
                                1 if accel else 0, L.data_ptr(), _stream(stream)))
@@ -220,7 +224,10 @@ def ntf_mttkrp_multi(T: torch.Tensor, factors, modes, h=None, stream=None) -> di
     modes share one pass over T."""
     N = T.dim()
     modes = sorted(set(int(m) for m in modes))
-    r = int(next(f for f in factors if f is not None).shape[1])
+    if not modes or modes[0] < 0 or modes[-1] >= N:
+        raise ValueError(f"modes {modes} must be a non-empty subset of [0, {N})")
+    skip = (modes[0],) if len(modes) == 1 else ()
+    r = _check_factors(T, factors, skip=skip)
     out = {n: torch.empty((T.shape[n], r), dtype=torch.float32, device=T.device) for n in modes}
     d = _tensor_desc(T)
     ptrs = ptr_array([(_dev(A, f"A[{l}]", torch.float32) if A is not None else None)
@@ -238,11 +245,7 @@ def ntf_mttkrp_autotune(T: torch.Tensor, factors, mode: int, reps: int = 5,
     Returns (out, {"kernel": 1 row tiles | 2 row slab, "wm": waves along rows, "ms": ...}).
     Synchronizes the stream.
     """
-    r = int(factors[(mode + 1) % T.dim()].shape[1])
-    out = torch.empty((T.shape[mode], r), dtype=torch.float32, device=T.device) if out is None else out
-    d = _tensor_desc(T)
-    ptrs = ptr_array([(_dev(A, f"A[{l}]", torch.float32) if (A is not None and l != mode) else None)
-                      for l, A in enumerate(factors)])
+    r, out, d, ptrs = _mttkrp_args(T, factors, mode, out)
     kern, wm, ms = C.c_int32(), C.c_int32(), C.c_float()
     check(lib().ntf_mttkrp_autotune(_h(h), C.byref(d), ptrs, r, int(mode),
                                     _dev(out, "P", torch.float32), int(reps), C.byref(kern),
@@ -285,7 +288,14 @@ def load_tuning(path: str, h=None) -> None:
 
 def ntf_gram(factors, exclude: int = -1, want32: bool = True, want64: bool = True, h=None,
              stream=None):
+    factors = list(factors)
+    if not factors or not -1 <= int(exclude) < len(factors):
+        raise ValueError(f"exclude {exclude} outside [-1, {len(factors)})")
     r = int(factors[0].shape[1]) if exclude != 0 else int(factors[-1].shape[1])
+    for l, A in enumerate(factors):
+        if A.dim() != 2 or int(A.shape[1]) != r:
+            raise ValueError(f"factor {l} has shape {tuple(A.shape)}; every factor needs r = {r} "
+                             "columns")
     dev = factors[0].device
     G32 = torch.empty((r, r), dtype=torch.float32, device=dev) if want32 else None
     G64 = torch.empty((r, r), dtype=torch.float64, device=dev) if want64 else None
@@ -301,7 +311,13 @@ def ntf_hals_update(W: torch.Tensor, P: torch.Tensor, G: torch.Tensor, max_sweep
                     tol: float = 1e-2, sweeps: torch.Tensor | None = None, h=None, stream=None):
     """In-place A-HALS on W; returns a device int32 tensor with the sweeps done."""
     sweeps = torch.zeros((), dtype=torch.int32, device=W.device) if sweeps is None else sweeps
+    if W.dim() != 2:
+        raise ValueError(f"W must be a matrix (I x r), got shape {tuple(W.shape)}")
     rows, r = W.shape
+    _check_shape(P, (rows, r), "P")
+    _check_shape(G, (r, r), "G")
+    if sweeps.numel() < 1:
+        raise ValueError("sweeps must hold one int32")
     check(lib().ntf_hals_update(_h(h), _dev(W, "W", torch.float32), _dev(P, "P", torch.float32),
                                 _dev(G, "G", torch.float32), rows, r, int(max_sweeps),
                                 float(tol), _dev(sweeps, "sweeps", torch.int32),
@@ -315,6 +331,15 @@ def ntf_her_step(op: int, state: torch.Tensor, params: HerParams | None = None, 
     p = (params or HerParams()).to_c()
     nb = len(A)
     r = int(A[0].shape[1]) if nb else 1
+    if nb and (len(A_new) != nb or len(A_hat) != nb):
+        raise ValueError("A, A_new and A_hat need one entry per block")
+    for b in range(nb):
+        for nm, X in (("A", A[b]), ("A_new", A_new[b]), ("A_hat", A_hat[b])):
+            _check_shape(X, (A[b].shape[0], r), f"{nm}[{b}]")
+    if nb and not 0 <= int(block) < nb:
+        raise ValueError(f"block {block} outside [0, {nb})")
+    if state.numel() < C.sizeof(_abi.NtfHerState):
+        raise ValueError("state buffer is smaller than one ntf_her_state")
     rows = i64_array([a.shape[0] for a in A]) if nb else None
     pa = ptr_array([_dev(a, "A", torch.float32) for a in A]) if nb else None
     pn = ptr_array([_dev(a, "A_new", torch.float32) for a in A_new]) if nb else None
@@ -329,6 +354,8 @@ def ntf_error(normT2: torch.Tensor, P: torch.Tensor, A: torch.Tensor, G64: torch
               out: torch.Tensor | None = None, h=None, stream=None) -> torch.Tensor:
     out = torch.empty((), dtype=torch.float64, device=P.device) if out is None else out
     rows, r = A.shape
+    _check_shape(P, (rows, r), "P")
+    _check_shape(G64, (r, r), "G64")
     check(lib().ntf_error(_h(h), _dev(normT2, "normT2", torch.float64),
                           _dev(P, "P", torch.float32), _dev(A, "A", torch.float32),
                           _dev(G64, "G", torch.float64), rows, r, _dev(out, "fhat", torch.float64),
@@ -341,6 +368,8 @@ def ntf_cp_loss(normT2: torch.Tensor, P: torch.Tensor, A: torch.Tensor, G64: tor
     """||T - [[A]]||^2 by the float64 Gram trick from one mode's P, A and G (no 1/2)."""
     out = torch.empty((), dtype=torch.float64, device=P.device) if out is None else out
     rows, r = A.shape
+    _check_shape(P, (rows, r), "P")
+    _check_shape(G64, (r, r), "G64")
     check(lib().ntf_cp_loss(_h(h), _dev(normT2, "normT2", torch.float64),
                             _dev(P, "P", torch.float32), _dev(A, "A", torch.float32),
                             _dev(G64, "G", torch.float64), rows, r,
@@ -354,6 +383,9 @@ def ntf_cp_grad(A: torch.Tensor, P: torch.Tensor, G64: torch.Tensor,
     """alpha * scale * (A G - P): the loss gradient for one factor (scale: device double)."""
     out = torch.empty_like(A) if out is None else out
     rows, r = A.shape
+    _check_shape(P, (rows, r), "P")
+    _check_shape(G64, (r, r), "G64")
+    _check_shape(out, (rows, r), "out")
     check(lib().ntf_cp_grad(_h(h), _dev(A, "A", torch.float32), _dev(P, "P", torch.float32),
                             _dev(G64, "G", torch.float64), rows, r,
                             _dev(scale, "scale", torch.float64) if scale is not None else None,
@@ -363,9 +395,10 @@ def ntf_cp_grad(A: torch.Tensor, P: torch.Tensor, G64: torch.Tensor,
 
 def ntf_residual_norm2(T: torch.Tensor, factors, h=None, stream=None) -> torch.Tensor:
     out = torch.empty((), dtype=torch.float64, device=T.device)
+    r = _check_factors(T, factors)
     d = _tensor_desc(T)
     ptrs = ptr_array([_dev(A, f"A[{l}]", torch.float32) for l, A in enumerate(factors)])
-    check(lib().ntf_residual_norm2(_h(h), C.byref(d), ptrs, int(factors[0].shape[1]),
+    check(lib().ntf_residual_norm2(_h(h), C.byref(d), ptrs, r,
                                    out.data_ptr(), _stream(stream)))
     return out
 
@@ -379,10 +412,12 @@ def ntf_solve(T: torch.Tensor, factors, iters: int, params: HerParams | None = N
     """
     p = (params or HerParams()).to_c()
     N = T.dim()
-    r = int(factors[0].shape[1])
+    r = _check_factors(T, factors)
     dev = T.device
     if state is None:
         state = new_state(dev)
+    if state.numel() < C.sizeof(_abi.NtfHerState):
+        raise ValueError("state buffer is smaller than one ntf_her_state")
     tr = None
     ctr = None
     if trace and iters > 0:
@@ -427,10 +462,14 @@ def ntf_solve_batched(tensors, factors, iters: int, params: HerParams | None = N
                   restart=torch.zeros((B, iters), dtype=torch.int32, device=dev),
                   sweeps=torch.zeros((B, iters, 3), dtype=torch.int32, device=dev))
     arr = (_abi.NtfProblem * B)()
+    if states.numel() < B * ss:
+        raise ValueError(f"states holds {states.numel()} bytes, {B} problems need {B * ss}")
     for b, (T, A) in enumerate(zip(tensors, factors)):
+        if T.dim() != 3:
+            raise ValueError(f"problem {b}: the batched solver takes 3-way tensors")
         q = arr[b]
         q.T = _tensor_desc(T)
-        q.r = int(A[0].shape[1])
+        q.r = _check_factors(T, A)
         q.reserved = 0
         for n in range(3):
             q.A[n] = _dev(A[n], f"A[{b}][{n}]", torch.float32)
@@ -453,6 +492,11 @@ def ntf_device_flags(h=None, stream=None) -> int:
     v = C.c_uint32()
     check(lib().ntf_device_flags(_h(h), _stream(stream), C.byref(v)))
     return int(v.value)
+
+
+def ntf_handle_set_wait_limit(seconds: float, h=None) -> None:
+    """Time after which the A-HALS kernel's cross-workgroup waits give up (default 2 s)."""
+    check(lib().ntf_handle_set_wait_limit(_h(h), float(seconds)))
 
 
 from .autograd import NTFLoss, ntf_loss  # noqa: E402

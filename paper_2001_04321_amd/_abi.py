@@ -57,6 +57,7 @@ SIGNATURES = {
     "ntf_status_string": (C.c_char_p, [C.c_int]),
     "ntf_version": (C.c_char_p, []),
     "ntf_device_flags": (C.c_int, [PTR, PTR, C.POINTER(C.c_uint32)]),
+    "ntf_handle_set_wait_limit": (C.c_int, [PTR, C.c_double]),
     "ntf_norm2": (C.c_int, [PTR, C.POINTER(NtfTensor), PTR, PTR]),
     "ntf_cast_bf16": (C.c_int, [PTR, PTR, PTR, C.c_int64, PTR]),
     "ntf_mttkrp": (C.c_int, [PTR, C.POINTER(NtfTensor), PTRS, C.c_int32, C.c_int32, PTR, PTR]),

@@ -199,6 +199,21 @@ ntf_status ntf_device_flags(ntf_handle* h, void* stream, uint32_t* flags_out) {
   return NTF_OK;
 }
 
+ntf_status ntf_handle_set_wait_limit(ntf_handle* h, double seconds) {
+  clear_error();
+  NTF_RETURN_IF(!h, NTF_EINVAL, "handle is NULL");
+  NTF_RETURN_IF(!(seconds >= 0.0 && seconds <= 60.0), NTF_EINVAL,
+                "wait limit %g s outside [0, 60]", seconds);
+  if (h->wait_limit_s != seconds) {
+    DeviceGuard guard(h->device);
+    NTF_RETURN_IF(!guard.ok, NTF_EDEVICE, "cannot select device %d", h->device);
+    NTF_HIP(hipDeviceSynchronize());
+    release_solve_graph(h);  // its A-HALS launches carry the old limit
+    h->wait_limit_s = seconds;
+  }
+  return NTF_OK;
+}
+
 ntf_status ntf_norm2(ntf_handle* h, const ntf_tensor* T, double* out, void* stream) {
   clear_error();
   NTF_GUARD(h);
@@ -495,6 +510,7 @@ ntf_status ntf_hals_update(ntf_handle* h, float* W, const float* P, const float*
   double* slots = reinterpret_cast<double*>(h->ws);
   NTF_HIP(launch_fill_sentinel(slots, nslots, s));
   HalsArgs a{};
+  a.wait_limit_s = h->wait_limit_s;
   a.W0 = W;
   a.W = W;
   a.P = P;

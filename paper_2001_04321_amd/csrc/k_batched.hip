@@ -437,7 +437,7 @@ __device__ void solve_problem(const BArgs& a, const BProb& pb, float* lds, doubl
       }
       s_sc[0] = b;
       s_sc[1] = bb;
-      s_sc[2] = fh;
+      if (finite) s_sc[2] = fh;  // a non-finite F-hat is no reference for the next test
       s_sc[3] += 1.0;
       if (restart) s_sc[4] += 1.0;
       for (int n = 0; n < 3; ++n) s_id[n] = restart ? nw[n] : ht[n];

@@ -847,7 +847,8 @@ hipError_t launch_hals(const HalsArgs& h, int num_cus, hipStream_t s) {
   a.gp_hat = h.gp_hat;
   a.err_part = h.err_part;
   a.nwg = int(hals_wgs(h.rows, h.r));
-  // wall_clock64 runs at the device's wall-clock rate; 2 s is far above any legitimate wait
+  // wall_clock64 runs at the device's wall-clock rate; the default 2 s is far above any
+  // legitimate wait
   static const int rate_khz = [] {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -855,7 +856,7 @@ hipError_t launch_hals(const HalsArgs& h, int num_cus, hipStream_t s) {
       v = 100000;
     return v;
   }();
-  a.timeout_ticks = uint64_t(rate_khz) * 1000ull * 2ull;
+  a.timeout_ticks = uint64_t(double(rate_khz) * 1000.0 * std::max(0.0, h.wait_limit_s));
   (void)num_cus;
   HFn fn = hals_fn(h.r, hals_rows_interleaved(h.r, h.rows));
   a.lag = hals_lag(h.r, h.rows);

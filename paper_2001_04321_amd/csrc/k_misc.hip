@@ -233,7 +233,9 @@ __global__ __launch_bounds__(256) void her_decide_kernel(DecideArgs a) {
   }
   st->restart = restart ? 1 : 0;
   st->nrestarts += restart ? 1 : 0;
-  st->fhat_prev = f;
+  // a non-finite F-hat is not a reference for the next test (f > NaN is false, which
+  // would accept the next extrapolation unconditionally): the last finite value stays
+  if (finite) st->fhat_prev = f;
   st->fhat = f;
   st->k += 1;
   const int64_t it = st->it;

@@ -100,6 +100,7 @@ struct ntf_handle {
   uint64_t ws_generation = 0;  // bumped on every reallocation
   uint32_t* dev_flags = nullptr;
   hipStream_t capture_stream = nullptr;
+  double wait_limit_s = 2.0;   // A-HALS cross-workgroup waits (ntf_handle_set_wait_limit)
   ntf::SolveGraph* graph = nullptr;
   // batched solver: its own workspace, pinned descriptor staging, cached graph
   char* bws = nullptr;
@@ -276,6 +277,7 @@ struct HalsArgs {
   double* gp_new;        // Gram partials of W, hals_wgs(rows, r) x r x r
   double* gp_hat;        // Gram partials of A_hat
   double* err_part;      // per-workgroup share of 2 <P, W> - <G64, W^T W>
+  double wait_limit_s = 2.0;  // bounded cross-workgroup waits give up after this long
 };
 hipError_t launch_hals(const HalsArgs& a, int num_cus, hipStream_t s);
 

@@ -187,6 +187,7 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
       continue;
     }
     HalsArgs ha{};
+    ha.wait_limit_s = h->wait_limit_s;
     ha.W0 = A[n];
     ha.W = b.A_new[n];
     ha.P = b.P;

@@ -66,6 +66,8 @@ def test_null_handle_is_rejected_without_device_work(lib):
         lambda: lib.ntf_mttkrp_autotune(None, C.byref(T), None, 4, 0, None, 3, None, None,
                                         None, None),
         lambda: lib.ntf_tune_import(None, b"f32:4x4x4:mode0:r4 1 4\n"),
+        lambda: lib.ntf_mttkrp_noalloc(None, C.byref(T), None, 4, 0, None, None),
+        lambda: lib.ntf_handle_set_wait_limit(None, 1.0),
     ]
     for call in calls:
         assert call() == _abi.NTF_EINVAL
@@ -76,3 +78,55 @@ def test_null_handle_is_rejected_without_device_work(lib):
 def test_handle_create_rejects_bad_pointer(lib):
     from paper_2001_04321_amd import _abi
     assert lib.ntf_handle_create(None, 0) == _abi.NTF_EINVAL
+
+
+# The binding is the only layer that sees shapes (the ABI takes raw pointers), so it checks
+# them before any call; CPU tensors suffice because the checks run before the device ones.
+def _cpu(*shape):
+    import torch
+    return torch.zeros(shape, dtype=torch.float32)
+
+
+@pytest.mark.parametrize("case", ["short list", "transposed", "other rank", "bad mode",
+                                  "bad out"])
+def test_binding_rejects_mismatched_factor_shapes(case):
+    import paper_2001_04321_amd as ntf
+    T = _cpu(5, 6, 7)
+    A = [_cpu(5, 3), _cpu(6, 3), _cpu(7, 3)]
+    mode, out = 0, None
+    if case == "short list":
+        A = A[:2]
+    elif case == "transposed":
+        A[1] = _cpu(3, 6)
+    elif case == "other rank":
+        A[2] = _cpu(7, 4)
+    elif case == "bad mode":
+        mode = 3
+    elif case == "bad out":
+        out = _cpu(6, 3)
+    with pytest.raises(ValueError):
+        ntf.ntf_mttkrp(T, A, mode, out=out)
+    with pytest.raises(ValueError):
+        ntf.ntf_mttkrp_noalloc(T, A, mode, out if out is not None else _cpu(5, 3))
+    if case in ("short list", "transposed", "other rank"):
+        with pytest.raises(ValueError):
+            ntf.ntf_solve(T, A, 3)
+        with pytest.raises(ValueError):
+            ntf.ntf_residual_norm2(T, A)
+
+
+def test_binding_rejects_mismatched_block_shapes():
+    import paper_2001_04321_amd as ntf
+    W, P, G = _cpu(10, 4), _cpu(10, 4), _cpu(4, 4)
+    with pytest.raises(ValueError):
+        ntf.ntf_hals_update(W, _cpu(10, 5), G)
+    with pytest.raises(ValueError):
+        ntf.ntf_hals_update(W, P, _cpu(5, 5))
+    with pytest.raises(ValueError):
+        ntf.ntf_pgd_update(W, _cpu(9, 4), G, 5)
+    with pytest.raises(ValueError):
+        ntf.ntf_error(_cpu(), P, W, _cpu(3, 3).double())
+    with pytest.raises(ValueError):
+        ntf.ntf_cp_grad(W, P, _cpu(4, 3).double())
+    with pytest.raises(ValueError):
+        ntf.ntf_gram([_cpu(10, 4), _cpu(8, 3)])
