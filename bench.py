@@ -13,7 +13,8 @@ MTTKRP throughput, final relative errors (explicit residual against the float32 
 and the FP64 oracle's rate on the host are reported beside it.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
-                    [--no-autograd] [--no-quad] [--copy-probe]
+                    [--no-autograd] [--no-quad] [--no-accuracy] [--copy-probe]
+                    [--profile TARGET]
 
 Also reported (not the headline value): HER with projected-gradient and Nesterov block
 solvers on the same workload, the read-only streaming rate at each tensor's
@@ -35,6 +36,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+CLOCK_HZ = 2.4e9
+CHAIN_CYCLES = 16  # one A-HALS column step (the max and one dependent multiply-add)
 WORKLOAD = "cube400_r32_corr"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cube400_r32.json")
 
@@ -107,6 +110,23 @@ def time_mttkrp(ntf, torch, Td, A_dev, reps):
         torch.cuda.synchronize()
         out.append(e0.elapsed_time(e1) / reps)
     return out
+
+
+def solver_mttkrp_ms(ntf, torch, Td, A_dev, reps):
+    """The tensor passes of one outer iteration of the 3-way solver: Y = T x_3 A_3 with the
+    two folds that give the first two modes' MTTKRPs (one ntf_mttkrp_multi call over modes
+    0 and 1) and the last mode's MTTKRP; ms per iteration (HIP events on the stream)."""
+    ntf.ntf_mttkrp_multi(Td, A_dev, (0, 1))
+    P = ntf.ntf_mttkrp(Td, A_dev, 2)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(reps):
+        ntf.ntf_mttkrp_multi(Td, A_dev, (0, 1))
+        ntf.ntf_mttkrp(Td, A_dev, 2, out=P)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
 
 
 def time_hals(ntf, torch, Td, A_dev, reps):
@@ -312,11 +332,14 @@ def copy_probe(torch, nbytes: int = 256 << 20):
     torch.cuda.synchronize()
 
 
-def traffic_from_counters(fetch_csv: str, write_csv: str, out_path: str, command: str):
+def traffic_from_counters(fetch_csv: str, write_csv: str, out_path: str, command: str,
+                          kinds=("mttkrp", "hals")):
     """Per-launch HBM traffic of the MTTKRP and A-HALS kernels from two rocprofv3 --pmc
     runs of this script with --copy-probe (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch),
     each scaled by what the counter reads for the 256 MB copy (bytes it must move / KiB
-    counted). Writes the JSON that `traffic_for` reads."""
+    counted). Updates the entries `kinds` of the JSON that `traffic_for` reads (the MTTKRP
+    entry comes from a `--profile mttkrp-cube400` run: standalone bf16 calls only, no
+    solver launches of the same kernel)."""
     import csv
     import statistics
 
@@ -342,20 +365,65 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, out_path: str, command
     f_copy = max(pick(fetch, is_copy))
     w_copy = max(pick(write, is_copy))
     f_scale, w_scale = nbytes / f_copy, nbytes / w_copy
-    out = {"copy_probe": {"bytes": nbytes, "fetch_kib": f_copy, "write_kib": w_copy,
-                          "fetch_scale": f_scale, "write_scale": w_scale},
-           "command": command}
-    for kind, key in (("mttkrp", lambda k: "mttkrp_kernel<true" in k),
-                      ("hals", lambda k: "hals_kernel" in k)):
-        fv, wv = pick(fetch, key), pick(write, key)
+    try:
+        with open(out_path) as f:
+            out = json.load(f)
+    except (OSError, ValueError):
+        out = {}
+    out.pop("copy_probe", None)
+    out.pop("command", None)
+    keys = {"mttkrp": lambda k: "mttkrp_kernel<true" in k, "hals": lambda k: "hals_kernel" in k}
+    for kind in kinds:
+        fv, wv = pick(fetch, keys[kind]), pick(write, keys[kind])
         if not fv or not wv:
             continue
         fb, wb = statistics.mean(fv) * f_scale, statistics.mean(wv) * w_scale
         out[kind] = {"fetch_bytes": round(fb), "write_bytes": round(wb),
                      "bytes_per_launch": round(fb + wb), "dispatches": len(fv),
-                     "source_digest": _source_digest(KERNEL_SOURCES[kind])}
+                     "source_digest": _source_digest(KERNEL_SOURCES[kind]),
+                     "command": command,
+                     "copy_probe": {"bytes": nbytes, "fetch_kib": f_copy, "write_kib": w_copy,
+                                    "fetch_scale": f_scale, "write_scale": w_scale}}
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
+    return out
+
+
+PROFILE_TARGETS = ("mttkrp-cube400", "mttkrp-quad128", "fused4-quad128", "solve-cube400")
+
+
+def profile_calls(ntf, torch, target: str, reps: int):
+    """Only the calls a counter run needs, on the named workload (planner's default MTTKRP
+    shapes): `mttkrp-cube400` reps ntf_mttkrp calls per mode on the 400^3 tensor as bf16 and
+    as float32, `mttkrp-quad128` the same on the 128^4 bf16 tensor, `fused4-quad128` reps
+    four-mode ntf_mttkrp_multi calls on the 128^4 bf16 tensor, `solve-cube400` reps outer
+    iterations of the bf16 solver."""
+    import numpy as np
+
+    import synth
+    name = "cube400_r32_corr" if target.endswith("cube400") else "quad128_r64_sparse"
+    pr = synth.workload(name)
+    T32 = torch.from_numpy(pr.T.astype(np.float32)).cuda()
+    A = [torch.from_numpy(a.astype(np.float32)).cuda() for a in pr.A0]
+    del pr
+    T16 = ntf.ntf_cast_bf16(T32)
+    forms = [T16, T32] if target == "mttkrp-cube400" else [T16]
+    if name != "cube400_r32_corr":
+        del T32
+    out = {"target": target, "workload": name, "reps": reps}
+    if target.startswith("mttkrp"):
+        for Td in forms:
+            for n in range(Td.dim()):
+                P = ntf.ntf_mttkrp(Td, A, n)
+                for _ in range(reps):
+                    ntf.ntf_mttkrp(Td, A, n, out=P)
+    elif target.startswith("fused4"):
+        for _ in range(reps):
+            ntf.ntf_mttkrp_multi(T16, A, range(4))
+    else:
+        ntf.ntf_solve(T16, A, reps, trace=False)
+    torch.cuda.synchronize()
+    out["device_flags"] = ntf.ntf_device_flags()
     return out
 
 
@@ -454,10 +522,17 @@ def main(argv=None):
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two counter runs and exit")
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
+    ap.add_argument("--traffic-kind", choices=("mttkrp", "hals"), action="append",
+                    help="which entries --traffic-from updates (default both)")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the untimed accuracy runs at the oracle's iteration count")
+    ap.add_argument("--profile", choices=PROFILE_TARGETS,
+                    help="make only the calls of one counter run and exit")
     a = ap.parse_args(argv)
     if a.traffic_from:
         print(json.dumps(traffic_from_counters(a.traffic_from[0], a.traffic_from[1],
-                                               TRAFFIC_FILE, a.traffic_command), indent=1))
+                                               TRAFFIC_FILE, a.traffic_command,
+                                               a.traffic_kind or ("mttkrp", "hals")), indent=1))
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the batched and "
@@ -476,6 +551,12 @@ def main(argv=None):
         build.build(verbose=False)
 
     torch.cuda.set_device(0)
+    if a.profile:
+        res = profile_calls(ntf, torch, a.profile, a.mttkrp_reps)
+        if a.copy_probe:
+            copy_probe(torch)
+        print(json.dumps(res), flush=True)
+        return
     w = synth.WORKLOADS[WORKLOAD]
     log(f"[bench] generating {WORKLOAD} {w['dims']} r={w['r']}")
     pr = synth.workload(WORKLOAD)
@@ -495,12 +576,14 @@ def main(argv=None):
     params = ntf.HerParams()
     n_elem = int(np.prod(T32.shape))
     r = int(w["r"])
-    golden = golden_fit = None
+    # the oracle's stored run of this workload (its own iteration count, 500): the accuracy
+    # of each form is measured at that count whatever --steps is
+    golden = golden_fit = golden_iters = None
     gpath = os.path.join(ROOT, "tests", "golden", "oracle_fits.json")
     if os.path.exists(gpath):
         g = json.load(open(gpath)).get(WORKLOAD)
-        if g and g["iters"] == a.steps:
-            golden, golden_fit = g["relerr"], g["fit"]
+        if g:
+            golden, golden_fit, golden_iters = g["relerr"], g["fit"], int(g["iters"])
     tuned = {}
     if not a.no_autotune:
         # the autotuner picks each mode's MTTKRP shape (timed on the workload's own tensor)
@@ -521,10 +604,21 @@ def main(argv=None):
         relerr = res / normT
         sweeps = trace["sweeps"].float().mean().item()
         restarts = int(trace["restart"].sum().item())
-        ttf = None
-        if golden_fit is not None:
-            ttf = iterations_to_fit(ntf, torch, Td, Td32, A_dev, A0_dev, params, a.steps,
+        ttf = acc_relerr = acc_restarts = None
+        if golden_fit is not None and not a.no_accuracy:
+            # accuracy at the oracle's iteration count (untimed unless it is the timed run)
+            if a.steps == golden_iters:
+                acc_relerr, acc_restarts = relerr, restarts
+            else:
+                A_acc = [x.clone() for x in A0_dev]
+                _, tr_acc = ntf.ntf_solve(Td, A_acc, golden_iters, params=params, trace=True)
+                acc_relerr = float(ntf.ntf_residual_norm2(Td32, A_acc).item()) ** 0.5 / normT
+                acc_restarts = int(tr_acc["restart"].sum().item())
+                del A_acc
+            A_fit = [x.clone() for x in A0_dev]
+            ttf = iterations_to_fit(ntf, torch, Td, Td32, A_fit, A0_dev, params, golden_iters,
                                     golden_fit)
+            del A_fit
         mt_ms = time_mttkrp(ntf, torch, Td, A_dev, a.mttkrp_reps)
         hals_ms, hals_sweeps = time_hals(ntf, torch, Td, A_dev, a.hals_reps)
         flops = 2.0 * r * n_elem
@@ -532,6 +626,8 @@ def main(argv=None):
             iters_per_s=a.steps / (ms / 1e3), ms_per_step=ms / a.steps, wall_s=wall,
             final_relerr=relerr, restarts=restarts, mean_inner_sweeps=sweeps,
             mttkrp_ms=mt_ms, hals_ms=hals_ms, hals_sweeps=hals_sweeps, iters_to_fit=ttf,
+            acc_relerr=acc_relerr, acc_restarts=acc_restarts,
+            solver_mttkrp_ms=solver_mttkrp_ms(ntf, torch, Td, A_dev, a.mttkrp_reps),
             mttkrp_tflops=[flops / (t / 1e3) / 1e12 for t in mt_ms],
             mttkrp_gbs=[n_elem * s / (t / 1e3) / 1e9 for t in mt_ms])
         log(f"[bench] {form}: {forms[form]['iters_per_s']:.1f} it/s, relerr {relerr:.6e}, "
@@ -554,15 +650,27 @@ def main(argv=None):
                "stream_gbs": round(streams["bf16_128MB"], 1),
                "frac_of_stream": round(achieved / streams["bf16_128MB"], 4),
                "mfma_frac": round(2.0 * r * n_elem / (t_mt / 1e3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4),
-               "step_share": round(sum(bf["mttkrp_ms"]) / bf["ms_per_step"], 3)}
-    # A-HALS: algorithmic flops = 2 r^2 per row per sweep (r multiply-adds per column);
-    # fp32 vector peak (the kernel is bound by its column-to-column dependency chain)
+               # the solver's own tensor passes (Y with two folds, and the last mode) per
+               # outer iteration, against the step time
+               "solver_ms_per_iter": round(bf["solver_mttkrp_ms"], 4),
+               "step_share": round(bf["solver_mttkrp_ms"] / bf["ms_per_step"], 3)}
+    # A-HALS: algorithmic flops = 2 r^2 per row per sweep (r multiply-adds per column). Its
+    # roof is the column chain, not the fp32 vector peak: r column steps per sweep, each a
+    # dependent pair of VALU instructions whose step takes CHAIN_CYCLES cycles at 2.4 GHz
+    # (measured in isolation on one wave), so the chain-bound rate for a block of I rows is
+    # 2 r^2 I flops per r * CHAIN_CYCLES / 2.4e9 s
     hals_dims = w["dims"]
     hflops = [2.0 * r * r * I * sw for I, sw in zip(hals_dims, bf["hals_sweeps"])]
     t_h = sum(bf["hals_ms"]) / len(bf["hals_ms"])
     h_ach = sum(hflops) / len(hflops) / (t_h / 1e3) / 1e12
-    hals_roof = {"bound": "alu", "achieved": round(h_ach, 4), "peak": FP32_VALU_PEAK_TFLOPS,
-                 "unit": "TFLOP/s", "frac": round(h_ach / FP32_VALU_PEAK_TFLOPS, 5),
+    chain_peak = sum(2.0 * r * r * I / (r * CHAIN_CYCLES / CLOCK_HZ) for I in hals_dims) / \
+        len(hals_dims) / 1e12
+    hals_roof = {"bound": "alu", "achieved": round(h_ach, 4), "peak": round(chain_peak, 4),
+                 "unit": "TFLOP/s", "frac": round(h_ach / chain_peak, 4),
+                 "peak_basis": f"column chain: {CHAIN_CYCLES} cycles per column step at "
+                               f"{CLOCK_HZ / 1e9:.1f} GHz, r column steps per sweep; the fp32 "
+                               f"vector peak would be {FP32_VALU_PEAK_TFLOPS} TFLOP/s "
+                               f"(frac {h_ach / FP32_VALU_PEAK_TFLOPS:.5f})",
                  "traffic": traffic_for("hals"),
                  "kernel": "hals_kernel (one ntf_hals_update call at 50 sweeps at most, "
                            "tol 1e-2), mean over the 3 modes",
@@ -593,6 +701,15 @@ def main(argv=None):
         "mttkrp_gbs": {k: [round(x, 1) for x in v["mttkrp_gbs"]] for k, v in forms.items()},
         "final_relerr": {k: v["final_relerr"] for k, v in forms.items()},
         "oracle_relerr": golden,
+        # each form's explicit relative error after the oracle's iteration count (the timed
+        # run's if --steps equals it, else an untimed run), and whether its fit lies within
+        # 1e-3 (relative) of the oracle's fit
+        "accuracy": None if golden is None or a.no_accuracy else {
+            "iters": golden_iters, "oracle_relerr": golden,
+            "relerr": {k: v["acc_relerr"] for k, v in forms.items()},
+            "fit_within_1e-3": {k: abs((1.0 - v["acc_relerr"]) - golden_fit) <= 1e-3 * golden_fit
+                                for k, v in forms.items()},
+            "restarts": {k: v["acc_restarts"] for k, v in forms.items()}},
         # first iteration whose fit is within 1e-3 of the oracle's final fit, and the time
         # that takes at the measured rate
         "time_to_fit": {k: (None if v["iters_to_fit"] is None else
