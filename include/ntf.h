@@ -84,7 +84,8 @@ typedef struct ntf_her_params {
   int32_t inner_solver; /* block solver: 0 A-HALS (Sec. 2.1.4, default), 1 projected gradient,
                            2 accelerated (Nesterov) projected gradient (Sec. 2.2; the
                            HER-PGD50 / HER-Nesterov50 runs of Sec. 3.1.4: they take exactly
-                           max_inner steps and need inner_tol = 0) */
+                           max_inner steps and need inner_tol = 0), 3 ADMM (Sec. 2.1.2,
+                           HER-ADMM; the stopping rule applies, max_inner <= 64) */
   double inner_tol;    /* stop when ||W_s - W_{s-1}||_F <= inner_tol ||W_1 - W_0||_F, default 1e-2 */
 } ntf_her_params;
 
@@ -247,6 +248,19 @@ ntf_status ntf_hals_update(ntf_handle* h, float* W, const float* P, const float*
 ntf_status ntf_pgd_update(ntf_handle* h, float* W, const float* P, const float* G,
                           int64_t rows, int32_t r, int32_t steps, int32_t accel,
                           double* L_out, void* stream);
+
+/* ADMM block solver (Sec. 2.1.2: AO-ADMM solves each NNLS block with a few ADMM steps).
+ * Scaled ADMM on the splitting W = Z with rho = trace(G) / r, U_0 = 0 and Z_0 = W:
+ * W_s = (P + rho (Z_{s-1} - U_{s-1})) (G + rho I)^-1, Z_s = max(0, W_s + U_{s-1}),
+ * U_s = U_{s-1} + W_s - Z_s; the block's result is Z_s, with the inner stopping rule of
+ * Sec. 4.1 (stop after step s >= 2 when ||Z_s - Z_{s-1}||_F <= tol ||Z_1 - Z_0||_F, or at
+ * s = 1 if Z_1 = Z_0, at most max_steps). W: rows x r in place; P: rows x r; G: r x r
+ * float32, symmetric positive semidefinite (G = 0 gives W = 0). steps_done: one device
+ * int32 (may be NULL). (G + rho I)^-1 is formed in float64 by the library. r > 128 or
+ * max_steps > 64: NTF_EUNSUPPORTED. */
+ntf_status ntf_admm_update(ntf_handle* h, float* W, const float* P, const float* G,
+                           int64_t rows, int32_t r, int32_t max_steps, double tol,
+                           int32_t* steps_done, void* stream);
 
 /* One HER step of Algorithm 2 on caller buffers.
  *  INIT:        state <- {beta0, 1, *fhat, ...}; `fhat` must point to F(A_0).

@@ -18,6 +18,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from .admm import admm
 from .hals import hals
 from .pgd import nesterov, pgd
 from .tensor import hadamard_gram, mttkrp, objective, gram
@@ -34,18 +35,22 @@ class HERParams:
     max_inner: int = 50
     inner_tol: float = 1e-2
     # block solver: "ahals" (Sec. 2.1.4), "pgd" or "nesterov" (projected gradient steps,
-    # Sec. 2.2; HER-PGD50 / HER-Nesterov50 of Sec. 3.1.4)
+    # Sec. 2.2; HER-PGD50 / HER-Nesterov50 of Sec. 3.1.4), "admm" (ADMM steps, Sec. 2.1.2;
+    # HER-ADMM)
     inner: str = "ahals"
 
     def validate(self) -> None:
-        if self.inner not in ("ahals", "pgd", "nesterov"):
-            raise ValueError("inner must be 'ahals', 'pgd' or 'nesterov'")
+        if self.inner not in SOLVERS:
+            raise ValueError(f"inner must be one of {sorted(SOLVERS)}")
         if not (0.0 <= self.beta0 < 1.0):
             raise ValueError("beta0 must lie in [0, 1)")
         if not (1.0 <= self.gamma_bar <= self.gamma <= self.eta):
             raise ValueError("need 1 <= gamma_bar <= gamma <= eta")
         if self.max_inner < 1 or self.inner_tol < 0.0:
             raise ValueError("max_inner >= 1 and inner_tol >= 0 required")
+
+
+SOLVERS = {"ahals": hals, "pgd": pgd, "nesterov": nesterov, "admm": admm}
 
 
 def extrapolate(A_new: np.ndarray, A_old: np.ndarray, beta: float) -> np.ndarray:
@@ -95,8 +100,8 @@ class HERResult:
 
 def her_solve(T: np.ndarray, A0, iters: int, params: HERParams = HERParams(),
               state: dict | None = None, hook=None) -> HERResult:
-    """Algorithm 2 (HER) with A-HALS (or, by `params.inner`, projected gradient steps) as the
-    block solver, for `iters` outer iterations.
+    """Algorithm 2 (HER) with A-HALS (or, by `params.inner`, projected gradient or ADMM
+    steps) as the block solver, for `iters` outer iterations.
 
     Iteration k, block n = 1..N (eq. NNLS_her_exact): the block problem uses the
     extrapolated blocks of this iteration for l < n and of the previous iteration for
@@ -133,7 +138,7 @@ def her_solve(T: np.ndarray, A0, iters: int, params: HERParams = HERParams(),
             # A_hat holds A-hat_k^(l) for l < n and A-hat_{k-1}^(l) for l > n.
             G = hadamard_gram(A_hat, n)
             P = mttkrp(T, A_hat, n)
-            solver = {"ahals": hals, "pgd": pgd, "nesterov": nesterov}[params.inner]
+            solver = SOLVERS[params.inner]
             W, s, _ = solver(A[n], P, G, params.max_inner, params.inner_tol)
             sweeps_k.append(s)
             A_new[n] = W

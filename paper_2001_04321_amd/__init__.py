@@ -7,7 +7,8 @@ There is no CPU fallback: if libntf.so is missing the import of a call raises.
 Functions carry the C names: ntf_norm2, ntf_cast_bf16, ntf_mttkrp, ntf_mttkrp_noalloc,
 ntf_mttkrp_multi,
 ntf_mttkrp_autotune,
-ntf_tune_export, ntf_tune_import, ntf_gram, ntf_hals_update, ntf_pgd_update, ntf_her_step,
+ntf_tune_export, ntf_tune_import, ntf_gram, ntf_hals_update, ntf_pgd_update,
+ntf_admm_update, ntf_her_step,
 ntf_error,
 ntf_solve, ntf_residual_norm2, ntf_cp_loss, ntf_cp_grad, ntf_solve_batched, plus the
 autograd loss `NTFLoss` / `ntf_loss` (module `autograd`) and a JSON file for the tuning
@@ -29,7 +30,7 @@ __all__ = [
     "ntf_residual_norm2", "ntf_device_flags", "new_state", "state_dict", "ntf_cp_loss",
     "ntf_cp_grad", "NTFLoss", "ntf_loss", "ntf_solve_batched", "ntf_mttkrp_autotune",
     "ntf_tune_export", "ntf_tune_import", "save_tuning", "load_tuning", "ntf_mttkrp_multi",
-    "ntf_pgd_update", "ntf_mttkrp_noalloc", "ntf_handle_set_wait_limit",
+    "ntf_pgd_update", "ntf_mttkrp_noalloc", "ntf_handle_set_wait_limit", "ntf_admm_update",
 ]
 
 _DTYPES = {torch.float32: _abi.NTF_F32, torch.bfloat16: _abi.NTF_BF16}
@@ -101,7 +102,8 @@ def _h(h):
 class HerParams:
     """HER parameters (defaults of the paper's experiments), the inner stopping rule and the
     block solver: "ahals" (default), "pgd" or "nesterov" (projected gradient steps; these
-    run exactly max_inner steps and need inner_tol = 0)."""
+    run exactly max_inner steps and need inner_tol = 0), "admm" (ADMM steps with the
+    stopping rule, max_inner <= 64)."""
     beta0: float = 0.5
     gamma: float = 1.05
     gamma_bar: float = 1.01
@@ -114,7 +116,7 @@ class HerParams:
         p = _abi.NtfHerParams()
         p.beta0, p.gamma, p.gamma_bar, p.eta = self.beta0, self.gamma, self.gamma_bar, self.eta
         p.max_inner, p.inner_tol = int(self.max_inner), float(self.inner_tol)
-        p.inner_solver = {"ahals": 0, "pgd": 1, "nesterov": 2}[self.inner]
+        p.inner_solver = {"ahals": 0, "pgd": 1, "nesterov": 2, "admm": 3}[self.inner]
         return p
 
 
@@ -217,6 +219,22 @@ def ntf_pgd_update(W: torch.Tensor, P: torch.Tensor, G: torch.Tensor, steps: int
                                _dev(G, "G", torch.float32), rows, r, int(steps),
                                1 if accel else 0, L.data_ptr(), _stream(stream)))
     return L
+
+
+def ntf_admm_update(W: torch.Tensor, P: torch.Tensor, G: torch.Tensor, max_steps: int = 50,
+                    tol: float = 1e-2, steps: torch.Tensor | None = None, h=None,
+                    stream=None) -> torch.Tensor:
+    """ADMM block solver in place on W; returns a device int32 tensor with the steps done."""
+    steps = torch.zeros((), dtype=torch.int32, device=W.device) if steps is None else steps
+    if W.dim() != 2:
+        raise ValueError(f"W must be a matrix (I x r), got shape {tuple(W.shape)}")
+    rows, r = W.shape
+    _check_shape(P, (rows, r), "P")
+    _check_shape(G, (r, r), "G")
+    check(lib().ntf_admm_update(_h(h), _dev(W, "W", torch.float32), _dev(P, "P", torch.float32),
+                                _dev(G, "G", torch.float32), rows, r, int(max_steps),
+                                float(tol), _dev(steps, "steps", torch.int32), _stream(stream)))
+    return steps
 
 
 def ntf_mttkrp_multi(T: torch.Tensor, factors, modes, h=None, stream=None) -> dict:

@@ -85,6 +85,8 @@ SIGNATURES = {
     "ntf_tune_import": (C.c_int, [PTR, C.c_char_p]),
     "ntf_pgd_update": (C.c_int, [PTR, PTR, PTR, PTR, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                  PTR, PTR]),
+    "ntf_admm_update": (C.c_int, [PTR, PTR, PTR, PTR, C.c_int64, C.c_int32, C.c_int32,
+                                  C.c_double, PTR, PTR]),
     "ntf_mttkrp_multi": (C.c_int, [PTR, C.POINTER(NtfTensor), PTRS, C.c_int32, C.c_int32, PTRS,
                                    PTR]),
 }

@@ -97,8 +97,8 @@ ntf_status check_params(const ntf_her_params* p) {
   NTF_RETURN_IF(p->max_inner < 1 || p->max_inner > kMaxSweeps, NTF_EINVAL,
                 "max_inner must lie in [1, %d]", kMaxSweeps);
   NTF_RETURN_IF(!(p->inner_tol >= 0.0), NTF_EINVAL, "inner_tol must be >= 0");
-  NTF_RETURN_IF(p->inner_solver < 0 || p->inner_solver > 2, NTF_EINVAL,
-                "inner_solver %d outside [0, 2]", p->inner_solver);
+  NTF_RETURN_IF(p->inner_solver < 0 || p->inner_solver > 3, NTF_EINVAL,
+                "inner_solver %d outside [0, 3]", p->inner_solver);
   return NTF_OK;
 }
 
@@ -552,6 +552,43 @@ ntf_status ntf_pgd_update(ntf_handle* h, float* W, const float* P, const float* 
   a.steps = steps;
   a.accel = accel;
   NTF_HIP(launch_pgd(a, as_stream(stream)));
+  return NTF_OK;
+}
+
+ntf_status ntf_admm_update(ntf_handle* h, float* W, const float* P, const float* G,
+                           int64_t rows, int32_t r, int32_t max_steps, double tol,
+                           int32_t* steps_done, void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_rank(r);
+  if (st) return st;
+  NTF_RETURN_IF(!W || !P || !G, NTF_EINVAL, "W, P or G is NULL");
+  NTF_RETURN_IF(rows < 1, NTF_EINVAL, "rows < 1");
+  NTF_RETURN_IF(max_steps < 1 || max_steps > kMaxSweeps, NTF_EINVAL,
+                "max_steps outside [1, %d]", kMaxSweeps);
+  NTF_RETURN_IF(!(tol >= 0.0), NTF_EINVAL, "tol must be >= 0");
+  NTF_RETURN_IF(r > 128, NTF_EUNSUPPORTED, "ADMM kernel supports r <= 128");
+  NTF_RETURN_IF(max_steps > kAdmmMaxSteps, NTF_EUNSUPPORTED,
+                "ADMM kernel runs at most %d steps per block", kAdmmMaxSteps);
+  const int64_t nwg = admm_workgroups(rows, r);
+  const size_t kb = align_up(size_t(r) * r * sizeof(float), 256);
+  const size_t pb = align_up(size_t(max_steps) * nwg * sizeof(double), 256);
+  if ((st = ensure_workspace(h, kb + pb + 512))) return st;
+  AdmmArgs a{};
+  a.K = reinterpret_cast<float*>(h->ws);
+  a.part = reinterpret_cast<double*>(h->ws + kb);
+  a.rho = reinterpret_cast<float*>(h->ws + kb + pb);
+  a.steps_dev = reinterpret_cast<int32_t*>(h->ws + kb + pb + 256);
+  a.W0 = W;
+  a.W = W;
+  a.P = P;
+  a.G = G;
+  a.rows = rows;
+  a.r = r;
+  a.max_steps = max_steps;
+  a.tol = tol;
+  a.steps_out = steps_done;
+  NTF_HIP(launch_admm(a, as_stream(stream)));
   return NTF_OK;
 }
 

@@ -298,6 +298,29 @@ struct PgdArgs {
 };
 hipError_t launch_pgd(const PgdArgs& a, hipStream_t s);
 
+// ADMM block solver (k_admm.hip): K = (G + rho I)^-1 with rho = trace(G) / r, then ADMM
+// steps from W0 with the inner stopping rule (at most max_steps <= kAdmmMaxSteps), result
+// into W (may alias W0). Workspace: K (r x r floats), rho (1 float), part
+// (max_steps x admm_workgroups(rows, r) doubles), steps_dev (1 int).
+constexpr int kAdmmMaxSteps = 64;
+struct AdmmArgs {
+  const float* W0;
+  float* W;
+  const float* P;
+  const float* G;
+  float* K;
+  float* rho;
+  double* part;
+  int32_t* steps_dev;
+  int64_t rows;
+  int r;
+  int max_steps;
+  double tol;
+  int32_t* steps_out;  // may be null
+};
+int64_t admm_workgroups(int64_t rows, int r);
+hipError_t launch_admm(const AdmmArgs& a, hipStream_t s);
+
 // Extrapolate-project: out = max(0, a_new + beta (a_new - a_old)), beta = *beta_src.
 hipError_t launch_extrapolate(const float* a_new, const float* a_old, float* out, int64_t n,
                               const double* beta_src, hipStream_t s);

@@ -65,6 +65,10 @@ struct SolveBufs {
   int64_t nerr;
   double* lip;  // projected-gradient blocks: L of the current block
   float* coef;  // and the Nesterov weights of its steps
+  float* admm_k;        // ADMM blocks: (G + rho I)^-1, rho, per-step shares, stop step
+  float* admm_rho;
+  double* admm_part;
+  int32_t* admm_steps;
 };
 
 void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
@@ -106,6 +110,11 @@ void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
   b.err_part = ar.take<double>(size_t(b.nerr));
   b.lip = ar.take<double>(1);
   b.coef = ar.take<float>(size_t(max_inner));
+  b.admm_k = ar.take<float>(rr);
+  b.admm_rho = ar.take<float>(1);
+  b.admm_part = ar.take<double>(size_t(std::min(max_inner, kAdmmMaxSteps)) *
+                                size_t(admm_workgroups(maxI, r)));
+  b.admm_steps = ar.take<int32_t>(1);
 }
 
 FactorPtrs factors_for(int n, int N, float* const* A, const SolveBufs& b) {
@@ -154,21 +163,40 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
       return e;
     }
     if (p.inner_solver != 0) {
-      // projected-gradient block (Sec. 2.2), then the steps the A-HALS epilogue fuses:
-      // extrapolation, Gram partials of A_new and A-hat, the F-hat share of the last block
-      PgdArgs pa{};
-      pa.W0 = A[n];
-      pa.W = b.A_new[n];
-      pa.P = b.P;
-      pa.G = b.G32;
-      pa.L = b.lip;
-      pa.coef = b.coef;
-      pa.rows = I;
-      pa.r = r;
-      pa.steps = p.max_inner;
-      pa.accel = p.inner_solver == 2 ? 1 : 0;
-      pa.steps_out = b.sweeps + n;
-      if ((e = launch_pgd(pa, s)) != hipSuccess) return e;
+      // projected-gradient (Sec. 2.2) or ADMM (Sec. 2.1.2) block, then the steps the A-HALS
+      // epilogue fuses: extrapolation, Gram partials of A_new and A-hat, the F-hat share
+      // of the last block
+      if (p.inner_solver == 3) {
+        AdmmArgs aa{};
+        aa.W0 = A[n];
+        aa.W = b.A_new[n];
+        aa.P = b.P;
+        aa.G = b.G32;
+        aa.K = b.admm_k;
+        aa.rho = b.admm_rho;
+        aa.part = b.admm_part;
+        aa.steps_dev = b.admm_steps;
+        aa.rows = I;
+        aa.r = r;
+        aa.max_steps = p.max_inner;
+        aa.tol = p.inner_tol;
+        aa.steps_out = b.sweeps + n;
+        if ((e = launch_admm(aa, s)) != hipSuccess) return e;
+      } else {
+        PgdArgs pa{};
+        pa.W0 = A[n];
+        pa.W = b.A_new[n];
+        pa.P = b.P;
+        pa.G = b.G32;
+        pa.L = b.lip;
+        pa.coef = b.coef;
+        pa.rows = I;
+        pa.r = r;
+        pa.steps = p.max_inner;
+        pa.accel = p.inner_solver == 2 ? 1 : 0;
+        pa.steps_out = b.sweeps + n;
+        if ((e = launch_pgd(pa, s)) != hipSuccess) return e;
+      }
       if ((e = launch_extrapolate(b.A_new[n], A[n], b.A_hat[n], I * r, &b.state->beta, s)) !=
           hipSuccess)
         return e;
@@ -282,12 +310,16 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
   NTF_RETURN_IF(!A, NTF_EINVAL, "factor array is NULL");
   NTF_RETURN_IF(resume && !state, NTF_EINVAL, "resume needs a state");
   const int N = T->order;
-  NTF_RETURN_IF(params->inner_solver != 0 && params->inner_tol != 0.0, NTF_EUNSUPPORTED,
+  NTF_RETURN_IF((params->inner_solver == 1 || params->inner_solver == 2) &&
+                    params->inner_tol != 0.0,
+                NTF_EUNSUPPORTED,
                 "projected-gradient blocks run exactly max_inner steps: inner_tol must be 0");
+  NTF_RETURN_IF(params->inner_solver == 3 && params->max_inner > kAdmmMaxSteps,
+                NTF_EUNSUPPORTED, "ADMM blocks run at most %d steps", kAdmmMaxSteps);
   for (int n = 0; n < N; ++n) {
     NTF_RETURN_IF(!A[n], NTF_EINVAL, "factor %d is NULL", n);
     if (params->inner_solver != 0) {
-      NTF_RETURN_IF(r > 128, NTF_EUNSUPPORTED, "projected-gradient kernel supports r <= 128");
+      NTF_RETURN_IF(r > 128, NTF_EUNSUPPORTED, "projected-gradient and ADMM kernels support r <= 128");
       continue;
     }
     NTF_RETURN_IF(!hals_supported(T->dims[n], r, h->num_cus), NTF_EUNSUPPORTED,

@@ -53,3 +53,4 @@ def dev_tensor(T, dtype: str):
 
 def to_np(t):
     return t.detach().cpu().double().numpy()
+
