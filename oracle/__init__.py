@@ -18,6 +18,7 @@ tensor  : Kronecker / Khatri-Rao products, unfoldings, Kruskal reconstruction, t
 hals    : A-HALS column updates and the inner stopping rule.
 pgd     : projected gradient and accelerated projected gradient block solvers.
 admm    : the ADMM block solver (AO-ADMM / HER-ADMM).
+comparators : APG, iBPG and Bro's extrapolation in the block-wise HER structure.
 her     : extrapolation, the beta schedule, the restart surrogate F-hat, Algorithm 2 (HER)
           and Algorithm 1 (plain alternating optimization).
 metrics : data-fitting error, relative error / fit, factor error with matching.
@@ -29,6 +30,7 @@ from .tensor import (kron_columns, khatri_rao, unfold, fold, kruskal, block_matr
 from .hals import hals_column, hals
 from .pgd import lipschitz, pg_step, pgd, nesterov
 from .admm import admm, admm_rho
+from .comparators import apg_solve, ibpg_solve, ibpg_block, bro_solve, bro_omega, bro_h, t_next
 from .her import (HERParams, extrapolate, update_beta, f_hat, her_solve, ao_solve,
                   HERResult)
 from .metrics import residual_norm, relative_error, fit, factor_error
@@ -40,5 +42,6 @@ __all__ = [
     "gram", "hadamard_gram", "objective", "gradient", "hals_column", "hals", "HERParams",
     "extrapolate", "update_beta", "f_hat", "her_solve", "ao_solve", "HERResult",
     "residual_norm", "relative_error", "fit", "factor_error", "cp_loss", "cp_loss_grad",
-    "lipschitz", "pg_step", "pgd", "nesterov", "admm", "admm_rho",
+    "lipschitz", "pg_step", "pgd", "nesterov", "admm", "admm_rho", "apg_solve", "ibpg_solve",
+    "ibpg_block", "bro_solve", "bro_omega", "bro_h", "t_next",
 ]
