@@ -516,6 +516,8 @@ def main(argv=None):
     ap.add_argument("--no-inner-solvers", action="store_true",
                     help="skip the projected-gradient block solver runs")
     ap.add_argument("--quad-iters", type=int, default=200)
+    ap.add_argument("--comp-iters", type=int, default=100,
+                    help="outer iterations of the APG and iBPG comparison runs")
     ap.add_argument("--no-quad", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MB device copy (reference for traffic counters)")
@@ -725,18 +727,44 @@ def main(argv=None):
     }
     line["stream_gbs"] = {k: round(v, 1) for k, v in streams.items()}
     if not a.no_inner_solvers:
-        # HER with projected-gradient blocks (50 steps each: HER-PGD50, HER-Nesterov50), bf16
+        # HER with projected-gradient blocks (50 steps each: HER-PGD50, HER-Nesterov50) and
+        # ADMM blocks (HER-ADMM), and Bro's extrapolation with A-HALS blocks, bf16
         line["inner_solvers"] = {}
-        for inner in ("pgd", "nesterov"):
+        variants = {"pgd": ntf.HerParams(inner="pgd", inner_tol=0.0, max_inner=50),
+                    "nesterov": ntf.HerParams(inner="nesterov", inner_tol=0.0, max_inner=50),
+                    "admm": ntf.HerParams(inner="admm"),
+                    "bro_ahals": ntf.HerParams(scheme="bro")}
+        for inner, prm in variants.items():
             A_dev = [x.clone() for x in A0_dev]
-            prm = ntf.HerParams(inner=inner, inner_tol=0.0, max_inner=50)
-            log(f"[bench] bf16 with {inner} blocks: {a.steps} outer iterations")
+            log(f"[bench] bf16 with {inner}: {a.steps} outer iterations")
             ms, _, _, trace = time_solve(ntf, torch, Td16, A_dev, A0_dev, a.steps, a.warmup, prm)
             res = float(ntf.ntf_residual_norm2(Td32, A_dev).item()) ** 0.5
             line["inner_solvers"][inner] = {
                 "iters_per_s": round(a.steps / (ms / 1e3), 1),
                 "ms_per_step": round(ms / a.steps, 5), "final_relerr": res / normT,
-                "restarts": int(trace["restart"].sum().item())}
+                "restarts": int(trace["restart"].sum().item()),
+                "mean_inner_steps": round(trace["sweeps"].float().mean().item(), 2)}
+            del A_dev
+        # the paper's comparison methods with extrapolation inside the block update
+        # (synchronous calls: APG reads F back once per iteration for its restart)
+        line["comparators"] = {}
+        for name, run in (("apg", lambda A: ntf.ntf_solve_apg(Td16, A, a.comp_iters)),
+                          ("ibpg", lambda A: ntf.ntf_solve_ibpg(Td16, A, a.comp_iters,
+                                                                inner_steps=50))):
+            A_dev = [x.clone() for x in A0_dev]
+            run(A_dev)  # warm-up
+            A_dev = [x.clone() for x in A0_dev]
+            torch.cuda.synchronize()
+            log(f"[bench] bf16 {name}: {a.comp_iters} outer iterations")
+            t0 = time.perf_counter()
+            out = run(A_dev)
+            dt = time.perf_counter() - t0
+            res = float(ntf.ntf_residual_norm2(Td32, A_dev).item()) ** 0.5
+            entry = {"iters": a.comp_iters, "iters_per_s": round(a.comp_iters / dt, 1),
+                     "final_relerr": res / normT}
+            if name == "apg":
+                entry["restarts"] = int(out[1].sum())
+            line["comparators"][name] = entry
             del A_dev
     if not a.no_quad:
         log(f"[bench] 4-way: 128^4 bf16, r=64, {a.quad_iters} outer iterations")

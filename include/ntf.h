@@ -87,6 +87,14 @@ typedef struct ntf_her_params {
                            max_inner steps and need inner_tol = 0), 3 ADMM (Sec. 2.1.2,
                            HER-ADMM; the stopping rule applies, max_inner <= 64) */
   double inner_tol;    /* stop when ||W_s - W_{s-1}||_F <= inner_tol ||W_1 - W_0||_F, default 1e-2 */
+  int32_t scheme;      /* extrapolation between block updates: 0 HER (Algorithm 2, default);
+                          1 Bro's sequence in the block-wise form of Sec. 3.3: the same
+                          structure (each block extrapolated right after its update, the
+                          extrapolated sequence abandoned when F-hat increases) with
+                          beta_k = omega_k = k^(1/h) - 1 (0 for k < 5), h = 3 raised by one
+                          every fifth increase, and no projection of the extrapolated
+                          point; beta0, gamma, gamma_bar and eta are then unused */
+  int32_t reserved;    /* 0 */
 } ntf_her_params;
 
 /* HER scalar state, kept in DEVICE memory (Algorithm 2: beta_k, beta_bar_k, F-hat_k). */
@@ -261,6 +269,33 @@ ntf_status ntf_pgd_update(ntf_handle* h, float* W, const float* P, const float* 
 ntf_status ntf_admm_update(ntf_handle* h, float* W, const float* P, const float* G,
                            int64_t rows, int32_t r, int32_t max_steps, double tol,
                            int32_t* steps_done, void* stream);
+
+/* APG (Sec. 2.2.1; the Appendix's pseudocode), the comparison method with extrapolation
+ * inside each block update: outer iteration k, block i (the other blocks at their latest
+ * values): w = min(w_hat_{k-1}, delta_w sqrt(L_{k-2} / L_{k-1})) with
+ * w_hat_{k-1} = (t_{k-1} - 1) / t_k, t_0 = 1, t_k = (1 + sqrt(1 + 4 t_{k-1}^2)) / 2 and
+ * L = ||G||_2 of the block problem; A-hat = A_{k-1} + w (A_{k-1} - A_{k-2}) (A_{-1} = A_0,
+ * not projected); A_k = max(0, A-hat - (A-hat G - P) / L). When F(A_k) > F(A_{k-1}) the
+ * iteration is redone from A_{k-1} without extrapolation. A: in: A_0, out: A_iters.
+ * objective (host, iters doubles, may be NULL): F(A_k) (with the 1/2 of eq. objFun);
+ * restarts (host, iters int32, may be NULL). delta_w in [0, 1) (the paper leaves it open;
+ * 0.9999 is the usual choice). Synchronous: the host reads F(A_k) back once per iteration
+ * to decide the restart; returns after the last iteration. r <= 128. */
+ntf_status ntf_solve_apg(ntf_handle* h, const ntf_tensor* T, int32_t r, float* const* A,
+                         int32_t iters, double delta_w, double* objective, int32_t* restarts,
+                         void* stream);
+
+/* iBPG (Sec. 2.2.2; the Appendix's pseudocode): outer iteration k, block i: w as for APG,
+ * then `inner_steps` updates of the block with two points,
+ * Y1 = A_cur + w (A_cur - A_prev) (gradient), Y2 = A_cur + beta w (A_cur - A_prev)
+ * (inertia), A_prev <- A_cur, A_cur <- max(0, Y2 - (Y1 G - P) / L); no restart. The inner
+ * rule "until some criteria" is read as exactly inner_steps updates. A_{-1} = A_0.
+ * A: in: A_0, out: the last A_cur. objective (host, iters doubles, may be NULL): F after each
+ * outer iteration. delta_w in [0, 1) (the pseudocode's 0.99), beta >= 0 (its 1.01).
+ * Synchronous. r <= 128. */
+ntf_status ntf_solve_ibpg(ntf_handle* h, const ntf_tensor* T, int32_t r, float* const* A,
+                          int32_t iters, int32_t inner_steps, double delta_w, double beta,
+                          double* objective, void* stream);
 
 /* One HER step of Algorithm 2 on caller buffers.
  *  INIT:        state <- {beta0, 1, *fhat, ...}; `fhat` must point to F(A_0).

@@ -10,7 +10,8 @@ ntf_mttkrp_autotune,
 ntf_tune_export, ntf_tune_import, ntf_gram, ntf_hals_update, ntf_pgd_update,
 ntf_admm_update, ntf_her_step,
 ntf_error,
-ntf_solve, ntf_residual_norm2, ntf_cp_loss, ntf_cp_grad, ntf_solve_batched, plus the
+ntf_solve, ntf_solve_apg, ntf_solve_ibpg, ntf_residual_norm2, ntf_cp_loss, ntf_cp_grad,
+ntf_solve_batched, plus the
 autograd loss `NTFLoss` / `ntf_loss` (module `autograd`) and a JSON file for the tuning
 table (`save_tuning`, `load_tuning`).
 """
@@ -31,6 +32,7 @@ __all__ = [
     "ntf_cp_grad", "NTFLoss", "ntf_loss", "ntf_solve_batched", "ntf_mttkrp_autotune",
     "ntf_tune_export", "ntf_tune_import", "save_tuning", "load_tuning", "ntf_mttkrp_multi",
     "ntf_pgd_update", "ntf_mttkrp_noalloc", "ntf_handle_set_wait_limit", "ntf_admm_update",
+    "ntf_solve_apg", "ntf_solve_ibpg",
 ]
 
 _DTYPES = {torch.float32: _abi.NTF_F32, torch.bfloat16: _abi.NTF_BF16}
@@ -103,7 +105,8 @@ class HerParams:
     """HER parameters (defaults of the paper's experiments), the inner stopping rule and the
     block solver: "ahals" (default), "pgd" or "nesterov" (projected gradient steps; these
     run exactly max_inner steps and need inner_tol = 0), "admm" (ADMM steps with the
-    stopping rule, max_inner <= 64)."""
+    stopping rule, max_inner <= 64); the extrapolation scheme: "her" (Algorithm 2) or "bro"
+    (Bro's sequence in the block-wise form of Sec. 3.3, no projection)."""
     beta0: float = 0.5
     gamma: float = 1.05
     gamma_bar: float = 1.01
@@ -111,12 +114,14 @@ class HerParams:
     max_inner: int = 50
     inner_tol: float = 1e-2
     inner: str = "ahals"
+    scheme: str = "her"
 
     def to_c(self) -> _abi.NtfHerParams:
         p = _abi.NtfHerParams()
         p.beta0, p.gamma, p.gamma_bar, p.eta = self.beta0, self.gamma, self.gamma_bar, self.eta
         p.max_inner, p.inner_tol = int(self.max_inner), float(self.inner_tol)
         p.inner_solver = {"ahals": 0, "pgd": 1, "nesterov": 2, "admm": 3}[self.inner]
+        p.scheme = {"her": 0, "bro": 1}[self.scheme]
         return p
 
 
@@ -453,6 +458,35 @@ def ntf_solve(T: torch.Tensor, factors, iters: int, params: HerParams | None = N
                           _dev(state, "state"), 1 if resume else 0,
                           C.byref(ctr) if ctr is not None else None, _stream(stream)))
     return state, tr
+
+
+def ntf_solve_apg(T: torch.Tensor, factors, iters: int, delta_w: float = 0.9999, h=None,
+                  stream=None):
+    """APG (the paper's comparison method, Sec. 2.2.1) in place on `factors`; synchronous.
+    Returns (objective per iteration, restart flags) as numpy arrays."""
+    import numpy as np
+    r = _check_factors(T, factors)
+    d = _tensor_desc(T)
+    ptrs = ptr_array([_dev(A, f"A[{l}]", torch.float32) for l, A in enumerate(factors)])
+    obj = np.zeros(max(iters, 1), dtype=np.float64)
+    rst = np.zeros(max(iters, 1), dtype=np.int32)
+    check(lib().ntf_solve_apg(_h(h), C.byref(d), r, ptrs, int(iters), float(delta_w),
+                              obj.ctypes.data, rst.ctypes.data, _stream(stream)))
+    return obj[:iters], rst[:iters].astype(bool)
+
+
+def ntf_solve_ibpg(T: torch.Tensor, factors, iters: int, inner_steps: int = 50,
+                   delta_w: float = 0.99, beta: float = 1.01, h=None, stream=None):
+    """iBPG (the paper's comparison method, Sec. 2.2.2) in place on `factors`; synchronous.
+    Returns the objective after each outer iteration (numpy)."""
+    import numpy as np
+    r = _check_factors(T, factors)
+    d = _tensor_desc(T)
+    ptrs = ptr_array([_dev(A, f"A[{l}]", torch.float32) for l, A in enumerate(factors)])
+    obj = np.zeros(max(iters, 1), dtype=np.float64)
+    check(lib().ntf_solve_ibpg(_h(h), C.byref(d), r, ptrs, int(iters), int(inner_steps),
+                               float(delta_w), float(beta), obj.ctypes.data, _stream(stream)))
+    return obj[:iters]
 
 
 def ntf_solve_batched(tensors, factors, iters: int, params: HerParams | None = None,

@@ -25,7 +25,7 @@ class NtfTensor(C.Structure):
 class NtfHerParams(C.Structure):
     _fields_ = [("beta0", C.c_double), ("gamma", C.c_double), ("gamma_bar", C.c_double),
                 ("eta", C.c_double), ("max_inner", C.c_int32), ("inner_solver", C.c_int32),
-                ("inner_tol", C.c_double)]
+                ("inner_tol", C.c_double), ("scheme", C.c_int32), ("reserved", C.c_int32)]
 
 
 class NtfHerState(C.Structure):
@@ -85,6 +85,10 @@ SIGNATURES = {
     "ntf_tune_import": (C.c_int, [PTR, C.c_char_p]),
     "ntf_pgd_update": (C.c_int, [PTR, PTR, PTR, PTR, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                  PTR, PTR]),
+    "ntf_solve_apg": (C.c_int, [PTR, C.POINTER(NtfTensor), C.c_int32, PTRS, C.c_int32,
+                                C.c_double, PTR, PTR, PTR]),
+    "ntf_solve_ibpg": (C.c_int, [PTR, C.POINTER(NtfTensor), C.c_int32, PTRS, C.c_int32,
+                                 C.c_int32, C.c_double, C.c_double, PTR, PTR]),
     "ntf_admm_update": (C.c_int, [PTR, PTR, PTR, PTR, C.c_int64, C.c_int32, C.c_int32,
                                   C.c_double, PTR, PTR]),
     "ntf_mttkrp_multi": (C.c_int, [PTR, C.POINTER(NtfTensor), PTRS, C.c_int32, C.c_int32, PTRS,

@@ -99,6 +99,8 @@ ntf_status check_params(const ntf_her_params* p) {
   NTF_RETURN_IF(!(p->inner_tol >= 0.0), NTF_EINVAL, "inner_tol must be >= 0");
   NTF_RETURN_IF(p->inner_solver < 0 || p->inner_solver > 3, NTF_EINVAL,
                 "inner_solver %d outside [0, 3]", p->inner_solver);
+  NTF_RETURN_IF(p->scheme != 0 && p->scheme != 1, NTF_EINVAL, "scheme %d outside [0, 1]",
+                p->scheme);
   return NTF_OK;
 }
 
@@ -618,8 +620,9 @@ ntf_status ntf_her_step(ntf_handle* h, ntf_her_op op, ntf_her_state* state,
     NTF_RETURN_IF(!A[block] || !A_new[block] || !A_hat[block], NTF_EINVAL,
                   "block %d has a NULL buffer", block);
     NTF_RETURN_IF(rows[block] < 1, NTF_EINVAL, "rows[%d] < 1", block);
+    // projected (eq. extproj_her) unless params name Bro's scheme (Sec. 3.3)
     NTF_HIP(launch_extrapolate(A_new[block], A[block], A_hat[block], rows[block] * r,
-                               &state->beta, s));
+                               &state->beta, s, !(params && params->scheme == 1)));
     return NTF_OK;
   }
   NTF_RETURN_IF(op != NTF_HER_DECIDE, NTF_EINVAL, "unknown op %d", int(op));
@@ -710,6 +713,8 @@ ntf_status solve_batched_impl(ntf_handle* h, int32_t nprob, const ntf_problem* p
   if (st) return st;
   NTF_RETURN_IF(params->inner_solver != 0, NTF_EUNSUPPORTED,
                 "the batched solver uses A-HALS blocks only (inner_solver 0)");
+  NTF_RETURN_IF(params->scheme != 0, NTF_EUNSUPPORTED,
+                "the batched solver uses HER's extrapolation only (scheme 0)");
   std::vector<BatchedProblem> bp(static_cast<size_t>(nprob));
   std::vector<int64_t> cost(static_cast<size_t>(nprob));
   size_t ws_bytes = 0;

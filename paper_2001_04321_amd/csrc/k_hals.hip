@@ -57,6 +57,7 @@ struct HKArgs {
   uint32_t* flags;
   float* A_hat;
   const double* beta_src;
+  int project;
   double* gp_new;
   double* gp_hat;
   double* err_part;
@@ -704,7 +705,7 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
         if (a.A_hat) {
           const double x = w[q][c];
           const double y = x + beta * (x - double(w0[q][c]));
-          const float xh = float(y > 0.0 ? y : 0.0);
+          const float xh = float((y > 0.0 || !a.project) ? y : 0.0);
           a.A_hat[gidx] = xh;
           s_rows2[lrow[q] * r + j] = xh;
         }
@@ -843,6 +844,7 @@ hipError_t launch_hals(const HalsArgs& h, int num_cus, hipStream_t s) {
   a.flags = h.flags;
   a.A_hat = h.A_hat;
   a.beta_src = h.beta_src;
+  a.project = h.project ? 1 : 0;
   a.gp_new = h.gp_new;
   a.gp_hat = h.gp_hat;
   a.err_part = h.err_part;

@@ -109,14 +109,14 @@ __global__ __launch_bounds__(256) void cast_bf16_kernel(const float* __restrict_
 __global__ __launch_bounds__(256) void extrapolate_kernel(const float* __restrict__ a_new,
                                                           const float* __restrict__ a_old,
                                                           float* __restrict__ out, int64_t n,
-                                                          const double* beta_src) {
+                                                          const double* beta_src, int project) {
   const double beta = *beta_src;
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i = tid; i < n; i += stride) {
     const double x = a_new[i];
     const double y = x + beta * (x - double(a_old[i]));
-    out[i] = float(y > 0.0 ? y : 0.0);
+    out[i] = float((y > 0.0 || !project) ? y : 0.0);
   }
 }
 
@@ -190,10 +190,20 @@ __global__ __launch_bounds__(256) void cp_grad_kernel(const float* __restrict__ 
   out[e] = float(f * (g - double(P[e])));
 }
 
-__global__ void her_init_kernel(ntf_her_state* st, double beta0, const double* fhat0) {
+// Bro's sequence in the block-wise form (Sec. 3.3): omega for outer iteration k after
+// `nrestarts` increases of the error; h = 3 grows by one every fifth increase, and no
+// extrapolation happens before iteration 5.
+__device__ __forceinline__ double bro_h(int nrestarts) { return 3.0 + double(nrestarts / 5); }
+__device__ __forceinline__ double bro_omega(int64_t k, double h) {
+  return k < 5 ? 0.0 : pow(double(k), 1.0 / h) - 1.0;
+}
+
+__global__ void her_init_kernel(ntf_her_state* st, double beta0, int scheme,
+                                const double* fhat0) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->beta = beta0;
-    st->beta_bar = 1.0;
+    // scheme 1 keeps omega_1 in beta and h in beta_bar
+    st->beta = scheme == 1 ? bro_omega(1, bro_h(0)) : beta0;
+    st->beta_bar = scheme == 1 ? bro_h(0) : 1.0;
     st->fhat_prev = *fhat0;
     st->fhat = *fhat0;
     st->k = 0;
@@ -224,7 +234,13 @@ __global__ __launch_bounds__(256) void her_decide_kernel(DecideArgs a) {
   const bool restart = !finite || f > st->fhat_prev;
   const double beta = st->beta;
   const double beta_bar = st->beta_bar;
-  if (restart) {
+  if (a.p.scheme == 1) {
+    // Bro: the next iteration's omega from its index and the increases so far
+    const int nr = st->nrestarts + (restart ? 1 : 0);
+    const double h = bro_h(nr);
+    st->beta = bro_omega(st->k + 2, h);
+    st->beta_bar = h;
+  } else if (restart) {
     st->beta_bar = beta;
     st->beta = beta / a.p.eta;
   } else {
@@ -339,9 +355,9 @@ hipError_t launch_cast_bf16(const float* src, uint16_t* dst, int64_t n, hipStrea
 }
 
 hipError_t launch_extrapolate(const float* a_new, const float* a_old, float* out, int64_t n,
-                              const double* beta_src, hipStream_t s) {
+                              const double* beta_src, hipStream_t s, bool project) {
   hipLaunchKernelGGL(extrapolate_kernel, dim3(grid_for(n)), dim3(256), 0, s, a_new, a_old, out,
-                     n, beta_src);
+                     n, beta_src, project ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -381,7 +397,8 @@ hipError_t launch_cp_grad(const float* A, const float* P, const double* G, int64
 
 hipError_t launch_her_init(ntf_her_state* st, const ntf_her_params& p, const double* fhat0,
                            hipStream_t s) {
-  hipLaunchKernelGGL(her_init_kernel, dim3(1), dim3(64), 0, s, st, p.beta0, fhat0);
+  hipLaunchKernelGGL(her_init_kernel, dim3(1), dim3(64), 0, s, st, p.beta0, int(p.scheme),
+                     fhat0);
   return hipGetLastError();
 }
 

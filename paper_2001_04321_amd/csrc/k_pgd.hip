@@ -200,7 +200,8 @@ hipError_t launch_rp(const PgdArgs& a, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_pgd(const PgdArgs& a, hipStream_t s) {
+hipError_t launch_lipschitz(const float* G, int r, double* L, int steps, float* coef,
+                            hipStream_t s) {
   static bool attr_done = false;  // r = 128: 64 KB of G plus the vector exceed the default
   if (!attr_done) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(lipschitz_kernel),
@@ -208,13 +209,21 @@ hipError_t launch_pgd(const PgdArgs& a, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr_done = true;
   }
-  hipLaunchKernelGGL(lipschitz_kernel, dim3(1), dim3(64), size_t(a.r) * a.r * sizeof(float), s,
-                     a.G, a.r, a.L, a.steps, a.accel ? a.coef : nullptr);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(lipschitz_kernel, dim3(1), dim3(64), size_t(r) * r * sizeof(float), s, G, r,
+                     L, steps, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_pgd_steps(const PgdArgs& a, hipStream_t s) {
   if (a.r <= 32) return launch_rp<32>(a, s);
   if (a.r <= 64) return launch_rp<64>(a, s);
   return launch_rp<128>(a, s);
+}
+
+hipError_t launch_pgd(const PgdArgs& a, hipStream_t s) {
+  hipError_t e = launch_lipschitz(a.G, a.r, a.L, a.steps, a.accel ? a.coef : nullptr, s);
+  if (e != hipSuccess) return e;
+  return launch_pgd_steps(a, s);
 }
 
 }  // namespace ntf

@@ -278,6 +278,7 @@ struct HalsArgs {
   double* gp_hat;        // Gram partials of A_hat
   double* err_part;      // per-workgroup share of 2 <P, W> - <G64, W^T W>
   double wait_limit_s = 2.0;  // bounded cross-workgroup waits give up after this long
+  bool project = true;        // A_hat projected onto the nonnegative orthant
 };
 hipError_t launch_hals(const HalsArgs& a, int num_cus, hipStream_t s);
 
@@ -297,6 +298,11 @@ struct PgdArgs {
   int32_t* steps_out;  // may be null
 };
 hipError_t launch_pgd(const PgdArgs& a, hipStream_t s);
+// The two parts of launch_pgd: L (and, with coef, the Nesterov weights of `steps` steps),
+// then the steps with the L already in *a.L.
+hipError_t launch_lipschitz(const float* G, int r, double* L, int steps, float* coef,
+                            hipStream_t s);
+hipError_t launch_pgd_steps(const PgdArgs& a, hipStream_t s);
 
 // ADMM block solver (k_admm.hip): K = (G + rho I)^-1 with rho = trace(G) / r, then ADMM
 // steps from W0 with the inner stopping rule (at most max_steps <= kAdmmMaxSteps), result
@@ -321,9 +327,10 @@ struct AdmmArgs {
 int64_t admm_workgroups(int64_t rows, int r);
 hipError_t launch_admm(const AdmmArgs& a, hipStream_t s);
 
-// Extrapolate-project: out = max(0, a_new + beta (a_new - a_old)), beta = *beta_src.
+// Extrapolate-project: out = max(0, a_new + beta (a_new - a_old)), beta = *beta_src (without
+// the projection when `project` is false).
 hipError_t launch_extrapolate(const float* a_new, const float* a_old, float* out, int64_t n,
-                              const double* beta_src, hipStream_t s);
+                              const double* beta_src, hipStream_t s, bool project = true);
 
 // Restart surrogate pieces: per-block partial sums of 2<p_i,a_i> - a_i^T G a_i (float64).
 int64_t error_partial_count(int64_t rows, int r);

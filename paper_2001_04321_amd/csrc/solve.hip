@@ -197,8 +197,8 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
         pa.steps_out = b.sweeps + n;
         if ((e = launch_pgd(pa, s)) != hipSuccess) return e;
       }
-      if ((e = launch_extrapolate(b.A_new[n], A[n], b.A_hat[n], I * r, &b.state->beta, s)) !=
-          hipSuccess)
+      if ((e = launch_extrapolate(b.A_new[n], A[n], b.A_hat[n], I * r, &b.state->beta, s,
+                                  p.scheme == 0)) != hipSuccess)
         return e;
       GramJob gj{};
       gj.nfac = 2;
@@ -216,6 +216,7 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
     }
     HalsArgs ha{};
     ha.wait_limit_s = h->wait_limit_s;
+    ha.project = p.scheme == 0;
     ha.W0 = A[n];
     ha.W = b.A_new[n];
     ha.P = b.P;
