@@ -99,7 +99,8 @@ class HERResult:
 
 
 def her_solve(T: np.ndarray, A0, iters: int, params: HERParams = HERParams(),
-              state: dict | None = None, hook=None) -> HERResult:
+              state: dict | None = None, hook=None, mttkrp_fn=None,
+              normT2: float | None = None) -> HERResult:
     """Algorithm 2 (HER) with A-HALS (or, by `params.inner`, projected gradient or ADMM
     steps) as the block solver, for `iters` outer iterations.
 
@@ -116,15 +117,28 @@ def her_solve(T: np.ndarray, A0, iters: int, params: HERParams = HERParams(),
 
     `hook(k, A_prev, A_new, A_hat, fhat_k)` (optional) sees each iteration's blocks just
     before the restart decision: A_{k-1}, A_k, A-hat_k and F-hat_k.
+
+    `mttkrp_fn(A, n)` and `normT2` replace the dense tensor's MTTKRP and ||T||^2 when the
+    data is given in another format (T then only supplies its order via len(A0));
+    F-hat_0 = F(A_0) is then formed by the same Gram-trick expansion as F-hat_k.
     """
     params.validate()
-    T = np.asarray(T, dtype=np.float64)
-    N = T.ndim
-    normT2 = float(np.sum(T * T))
+    if mttkrp_fn is None:
+        T = np.asarray(T, dtype=np.float64)
+        N = T.ndim
+        normT2 = float(np.sum(T * T))
+        mttkrp_fn = lambda A_, n_: mttkrp(T, A_, n_)  # noqa: E731
+        dense = True
+    else:
+        N = len(A0) if state is None else len(state["factors"])
+        dense = False
     if state is None:
         A = [np.array(a, dtype=np.float64, copy=True) for a in A0]
         beta, beta_bar = params.beta0, 1.0
-        fhat_prev = objective(T, A)
+        if dense:
+            fhat_prev = objective(T, A)
+        else:
+            fhat_prev = f_hat(normT2, mttkrp_fn(A, N - 1), A[N - 1], hadamard_gram(A, N - 1))
     else:
         A = [np.array(a, dtype=np.float64, copy=True) for a in state["factors"]]
         beta, beta_bar, fhat_prev = state["beta"], state["beta_bar"], state["fhat"]
@@ -137,7 +151,7 @@ def her_solve(T: np.ndarray, A0, iters: int, params: HERParams = HERParams(),
         for n in range(N):
             # A_hat holds A-hat_k^(l) for l < n and A-hat_{k-1}^(l) for l > n.
             G = hadamard_gram(A_hat, n)
-            P = mttkrp(T, A_hat, n)
+            P = mttkrp_fn(A_hat, n)
             solver = SOLVERS[params.inner]
             W, s, _ = solver(A[n], P, G, params.max_inner, params.inner_tol)
             sweeps_k.append(s)

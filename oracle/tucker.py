@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from .her import HERParams, her_solve
 from .tensor import hadamard_gram, kruskal, mttkrp
 
 
@@ -45,3 +46,24 @@ def tucker_gradient(core: np.ndarray, bases, factors, i: int) -> np.ndarray:
     """grad_{A^(i)} F_t as written in Appendix A."""
     A = np.asarray(factors[i], dtype=np.float64)
     return -tucker_mttkrp(core, bases, factors, i) + A @ hadamard_gram(factors, i)
+
+
+def tucker_norm2(core: np.ndarray, bases) -> float:
+    """||(U^(1) (x) ... (x) U^(N)) G||_F^2 = <G x_1 (U^(1)T U^(1)) ... x_N (U^(N)T U^(N)), G>
+    (||G||^2 when every basis has orthonormal columns), without forming the tensor."""
+    G = np.asarray(core, dtype=np.float64)
+    X = G
+    for p, U in enumerate(bases):
+        U = np.asarray(U, dtype=np.float64)
+        X = np.moveaxis(np.tensordot(U.T @ U, X, axes=([1], [p])), 0, p)
+    return float(np.sum(X * G))
+
+
+def tucker_her_solve(core: np.ndarray, bases, A0, iters: int,
+                     params: HERParams = HERParams()):
+    """Algorithm 2 on the Tucker-format tensor (Appendix A): the block problems and F-hat
+    use the compressed MTTKRP U^(i) G_[i] KR((U^(p))^T A^(p)) and ||T||^2 of the format,
+    so the full tensor is never formed."""
+    return her_solve(None, A0, iters, params,
+                     mttkrp_fn=lambda A, n: tucker_mttkrp(core, bases, A, n),
+                     normT2=tucker_norm2(core, bases))

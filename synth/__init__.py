@@ -28,6 +28,7 @@ __all__ = [
     "Problem", "generator", "uniform_factors", "correlated_factors", "apply_zero_mask",
     "planted_tensor", "add_noise", "make_problem", "bf16_bits", "bf16_to_f32",
     "round_to_bf16", "WORKLOADS", "workload", "batch_specs", "batch_problem",
+    "TuckerProblem", "make_tucker_problem", "TUCKER_WORKLOADS", "tucker_workload",
 ]
 
 
@@ -210,3 +211,72 @@ def batch_problem(spec, b: int, snr_db: float = 30.0) -> Problem:
     I1, I2, I3, r = spec
     return make_problem((I1, I2, I3), r, snr_db=snr_db, kind="uniform",
                         data_seed=1000 + b, init_seed=2000 + b)
+
+
+# ---------------------------------------------------------------------------------------
+# Data given in Tucker format (the compressed input of the paper's Appendix A)
+# ---------------------------------------------------------------------------------------
+
+@dataclass
+class TuckerProblem:
+    """T = (U^(1) (x) ... (x) U^(N)) core; float64 core (r_1 x ... x r_N) and bases
+    (n_p x r_p, orthonormal columns), the planted factors and an initial point."""
+    core: np.ndarray
+    bases: list
+    A_true: list
+    A0: list
+    r: int
+    sigma: float
+    meta: dict = field(default_factory=dict)
+
+
+def make_tucker_problem(dims, ranks, r: int, snr_db=None, data_seed: int = 0,
+                        init_seed: int = 1) -> TuckerProblem:
+    """A planted nonnegative CP tensor given in Tucker format, with noise in the core.
+
+    Data seed: planted factors A_p ~ U[0,1] (n_p x r) in mode order, then per mode a
+    Gaussian n_p x (r_p - r) block; U_p is the orthonormal basis (QR) of [A_p, block], so
+    span(U_p) contains the columns of A_p and (U_p U_p^T) A_p = A_p. The core is the planted
+    CP of the projected factors U_p^T A_p plus Gaussian noise E at `snr_db` relative to the
+    clean core (orthonormal bases keep the SNR of the full tensor); no clipping (the
+    format need not be nonnegative). Init seed: A_0 ~ U[0,1] in mode order.
+    """
+    dims = tuple(int(d) for d in dims)
+    ranks = tuple(int(x) for x in ranks)
+    if any(rp < r for rp in ranks):
+        raise ValueError("Tucker ranks must be at least the CP rank")
+    g = generator(data_seed)
+    A_true = uniform_factors(g, dims, r)
+    bases = []
+    for A, rp in zip(A_true, ranks):
+        X = np.concatenate([A, g.standard_normal((A.shape[0], rp - r))], axis=1)
+        Q, _ = np.linalg.qr(X)
+        bases.append(Q)
+    core_clean = planted_tensor([U.T @ A for U, A in zip(bases, A_true)])
+    sigma = 0.0
+    if snr_db is None:
+        core = core_clean
+    else:
+        E = g.standard_normal(core_clean.shape)
+        sigma = float(np.linalg.norm(core_clean.ravel()) /
+                      (np.linalg.norm(E.ravel()) * 10.0 ** (snr_db / 20.0)))
+        core = core_clean + sigma * E
+    A0 = uniform_factors(generator(init_seed), dims, r)
+    meta = dict(dims=dims, ranks=ranks, r=r, snr_db=snr_db, data_seed=data_seed,
+                init_seed=init_seed)
+    return TuckerProblem(core=core, bases=bases, A_true=A_true, A0=A0, r=r, sigma=sigma,
+                         meta=meta)
+
+
+TUCKER_WORKLOADS = {
+    # the shape of the paper's compressed video tensor (Sec. 4.2, "On big data"): 153 x 238
+    # x 14000, CP rank 10, Tucker ranks 30, 30 dB
+    "tucker_video_r10": dict(dims=(153, 238, 14000), ranks=(30, 30, 30), r=10, snr_db=30.0,
+                             iters=200),
+}
+
+
+def tucker_workload(name: str, data_seed: int = 0, init_seed: int = 1) -> TuckerProblem:
+    w = dict(TUCKER_WORKLOADS[name])
+    w.pop("iters")
+    return make_tucker_problem(data_seed=data_seed, init_seed=init_seed, **w)

@@ -120,3 +120,35 @@ def test_batch_specs_ranges():
     assert len(specs) == 256
     for I1, I2, I3, r in specs:
         assert 32 <= min(I1, I2, I3) and max(I1, I2, I3) <= 160 and 5 <= r <= 20
+
+
+def test_tucker_norm_and_solve_match_the_dense_tensor():
+    """||T||^2 of the format equals that of the expanded tensor (also for bases without
+    orthonormal columns), and Algorithm 2 on the format follows Algorithm 2 on the expanded
+    tensor: the same decisions and F-hat to rounding (Appendix A: only the MTTKRP changes)."""
+    g = np.random.default_rng(11)
+    core = g.standard_normal((4, 3, 5))
+    bases = [g.standard_normal((9, 4)), g.standard_normal((7, 3)), g.standard_normal((8, 5))]
+    T = tucker.tucker_full(core, bases)
+    assert tucker.tucker_norm2(core, bases) == pytest.approx(float(np.sum(T * T)), rel=1e-12)
+    pr = synth.make_tucker_problem((15, 12, 40), (6, 5, 7), 4, snr_db=30.0, data_seed=3)
+    T = tucker.tucker_full(pr.core, pr.bases)
+    assert tucker.tucker_norm2(pr.core, pr.bases) == pytest.approx(
+        float(np.sum(pr.core ** 2)), rel=1e-12)  # orthonormal bases
+    res_t = tucker.tucker_her_solve(pr.core, pr.bases, pr.A0, 30)
+    res_d = oracle.her_solve(T, pr.A0, 30)
+    assert res_t.restart == res_d.restart
+    assert np.allclose(res_t.fhat, res_d.fhat, rtol=1e-9)
+    assert res_t.fhat0 == pytest.approx(res_d.fhat0, rel=1e-9)
+    for a, b in zip(res_t.factors, res_d.factors):
+        assert np.allclose(a, b, rtol=1e-7, atol=1e-9)
+
+
+def test_tucker_generator_plants_the_factors_in_the_bases():
+    """The bases span the planted factors, so the noiseless format is exactly [[A]]."""
+    pr = synth.make_tucker_problem((15, 12, 40), (6, 5, 7), 4, snr_db=None, data_seed=5)
+    for U, A in zip(pr.bases, pr.A_true):
+        assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
+        assert np.allclose(U @ (U.T @ A), A, atol=1e-12)
+    assert np.allclose(tucker.tucker_full(pr.core, pr.bases), oracle.kruskal(pr.A_true),
+                       atol=1e-12)
