@@ -72,6 +72,15 @@ typedef struct ntf_tensor {
 
 typedef struct ntf_handle ntf_handle;
 
+/* Data given in Tucker format (Appendix A): T = (U^(1) (x) ... (x) U^(N)) G with a core G
+ * (float32, order N, dims r_1..r_N, C-contiguous device tensor) and bases U^(p) (n_p x r_p
+ * float32, row-major device matrices). dims: n_1..n_N, the sizes of T (never formed). */
+typedef struct ntf_tucker {
+  ntf_tensor core;
+  const float* U[NTF_MAX_ORDER];
+  int64_t dims[NTF_MAX_ORDER];
+} ntf_tucker;
+
 /* HER parameters (Sec. 3.1.4, table of HER parameters; defaults of Sec. 4.1) and the
  * inner stopping rule of Sec. 4.1. Validation: 0 <= beta0 < 1 (beta0 = 0 gives plain
  * Algorithm 1), 1 <= gamma_bar <= gamma <= eta, 1 <= max_inner <= 1000, inner_tol >= 0. */
@@ -318,6 +327,26 @@ ntf_status ntf_her_step(ntf_handle* h, ntf_her_op op, ntf_her_state* state,
  * P, A: rows x r float32; G: r x r float64. fhat: device double (overwritten). */
 ntf_status ntf_error(ntf_handle* h, const double* normT2, const float* P, const float* A,
                      const double* G, int64_t rows, int32_t r, double* fhat, void* stream);
+
+/* MTTKRP of mode `mode` of a Tucker-format tensor (Appendix A):
+ * P = U^(mode) MTTKRP_mode(G; Q^(p)) with Q^(p) = (U^(p))^T A^(p) (r_p x r, float64
+ * accumulation over n_p), the core's MTTKRP on the matrix cores and the expansion by
+ * U^(mode); T is never formed. A: `order` device pointers, n_p x r (A[mode] ignored);
+ * P: n_mode x r float32, overwritten. Tucker ranks r_p <= 4096. */
+ntf_status ntf_tucker_mttkrp(ntf_handle* h, const ntf_tucker* X, const float* const* A,
+                             int32_t r, int32_t mode, float* P, void* stream);
+
+/* ||T||_F^2 of a Tucker-format tensor in float64, from the core and the bases' Grams:
+ * <G x_1 (U^(1)T U^(1)) ... x_N (U^(N)T U^(N)), G> (||G||^2 for orthonormal bases).
+ * out: one device double. */
+ntf_status ntf_tucker_norm2(ntf_handle* h, const ntf_tucker* X, double* out, void* stream);
+
+/* ntf_solve on a Tucker-format tensor (Appendix A: HER is unchanged, the MTTKRP and ||T||^2
+ * come from the format; the objective is eq. objFunTucker). Same arguments and semantics as
+ * ntf_solve; A holds n_p x r factors. */
+ntf_status ntf_solve_tucker(ntf_handle* h, const ntf_tucker* X, int32_t r, float* const* A,
+                            const ntf_her_params* params, int32_t iters, ntf_her_state* state,
+                            int32_t resume, const ntf_trace* trace, void* stream);
 
 /* Algorithm 2 (HER) with A-HALS blocks for `iters` outer iterations (Sec. 3.1). The
  * factors A (host array of `order` device pointers) hold A_0 on entry and the final

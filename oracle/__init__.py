@@ -30,7 +30,8 @@ from .tensor import (kron_columns, khatri_rao, unfold, fold, kruskal, block_matr
 from .hals import hals_column, hals
 from .pgd import lipschitz, pg_step, pgd, nesterov
 from .admm import admm, admm_rho
-from .tucker import tucker_full, tucker_mttkrp, tucker_norm2, tucker_her_solve
+from .tucker import (tucker_full, tucker_her_solve, tucker_mttkrp, tucker_norm2,
+                     tucker_relative_error)
 from .comparators import apg_solve, ibpg_solve, ibpg_block, bro_solve, bro_omega, bro_h, t_next
 from .her import (HERParams, extrapolate, update_beta, f_hat, her_solve, ao_solve,
                   HERResult)
@@ -45,5 +46,5 @@ __all__ = [
     "residual_norm", "relative_error", "fit", "factor_error", "cp_loss", "cp_loss_grad",
     "lipschitz", "pg_step", "pgd", "nesterov", "admm", "admm_rho", "apg_solve", "ibpg_solve",
     "ibpg_block", "bro_solve", "bro_omega", "bro_h", "t_next", "tucker_full", "tucker_mttkrp",
-    "tucker_norm2", "tucker_her_solve",
+    "tucker_norm2", "tucker_her_solve", "tucker_relative_error",
 ]

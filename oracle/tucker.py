@@ -59,6 +59,22 @@ def tucker_norm2(core: np.ndarray, bases) -> float:
     return float(np.sum(X * G))
 
 
+def tucker_relative_error(core: np.ndarray, bases, factors) -> float:
+    """||T - [[A]]||_F / ||T||_F for Tucker-format T without forming it:
+    ||T - [[A]]||^2 = ||T||^2 - 2 <G, [[(U^(1))^T A^(1), ...]]> + sum of the Hadamard product
+    of all factor Grams (the cross term is the core's inner product with the Kruskal tensor
+    of the projected factors, since the bases act on both sides of <T, [[A]]>)."""
+    proj = [np.asarray(U, dtype=np.float64).T @ np.asarray(A, dtype=np.float64)
+            for U, A in zip(bases, factors)]
+    cross = float(np.sum(np.asarray(core, dtype=np.float64) * kruskal(proj)))
+    H = np.ones((proj[0].shape[1],) * 2)
+    for A in factors:
+        A = np.asarray(A, dtype=np.float64)
+        H = H * (A.T @ A)
+    n2 = tucker_norm2(core, bases)
+    return float(np.sqrt(max(n2 - 2.0 * cross + float(H.sum()), 0.0) / n2))
+
+
 def tucker_her_solve(core: np.ndarray, bases, A0, iters: int,
                      params: HERParams = HERParams()):
     """Algorithm 2 on the Tucker-format tensor (Appendix A): the block problems and F-hat

@@ -10,7 +10,8 @@ ntf_mttkrp_autotune,
 ntf_tune_export, ntf_tune_import, ntf_gram, ntf_hals_update, ntf_pgd_update,
 ntf_admm_update, ntf_her_step,
 ntf_error,
-ntf_solve, ntf_solve_apg, ntf_solve_ibpg, ntf_residual_norm2, ntf_cp_loss, ntf_cp_grad,
+ntf_solve, ntf_solve_apg, ntf_solve_ibpg, ntf_tucker_mttkrp, ntf_tucker_norm2,
+ntf_solve_tucker, ntf_residual_norm2, ntf_cp_loss, ntf_cp_grad,
 ntf_solve_batched, plus the
 autograd loss `NTFLoss` / `ntf_loss` (module `autograd`) and a JSON file for the tuning
 table (`save_tuning`, `load_tuning`).
@@ -32,7 +33,8 @@ __all__ = [
     "ntf_cp_grad", "NTFLoss", "ntf_loss", "ntf_solve_batched", "ntf_mttkrp_autotune",
     "ntf_tune_export", "ntf_tune_import", "save_tuning", "load_tuning", "ntf_mttkrp_multi",
     "ntf_pgd_update", "ntf_mttkrp_noalloc", "ntf_handle_set_wait_limit", "ntf_admm_update",
-    "ntf_solve_apg", "ntf_solve_ibpg",
+    "ntf_solve_apg", "ntf_solve_ibpg", "ntf_tucker_mttkrp", "ntf_tucker_norm2",
+    "ntf_solve_tucker",
 ]
 
 _DTYPES = {torch.float32: _abi.NTF_F32, torch.bfloat16: _abi.NTF_BF16}
@@ -441,23 +443,101 @@ def ntf_solve(T: torch.Tensor, factors, iters: int, params: HerParams | None = N
         state = new_state(dev)
     if state.numel() < C.sizeof(_abi.NtfHerState):
         raise ValueError("state buffer is smaller than one ntf_her_state")
-    tr = None
-    ctr = None
-    if trace and iters > 0:
-        tr = dict(fhat=torch.zeros(iters, dtype=torch.float64, device=dev),
-                  beta=torch.zeros(iters, dtype=torch.float64, device=dev),
-                  beta_bar=torch.zeros(iters, dtype=torch.float64, device=dev),
-                  restart=torch.zeros(iters, dtype=torch.int32, device=dev),
-                  sweeps=torch.zeros((iters, N), dtype=torch.int32, device=dev))
-        ctr = _abi.NtfTrace(tr["fhat"].data_ptr(), tr["beta"].data_ptr(),
-                            tr["beta_bar"].data_ptr(), tr["restart"].data_ptr(),
-                            tr["sweeps"].data_ptr())
+    tr, ctr = _trace_buffers(iters, N, dev) if trace and iters > 0 else (None, None)
     d = _tensor_desc(T)
     ptrs = ptr_array([_dev(A, f"A[{l}]", torch.float32) for l, A in enumerate(factors)])
     check(lib().ntf_solve(_h(h), C.byref(d), r, ptrs, C.byref(p), int(iters),
                           _dev(state, "state"), 1 if resume else 0,
                           C.byref(ctr) if ctr is not None else None, _stream(stream)))
     return state, tr
+
+
+def _tucker_desc(core: torch.Tensor, bases, dims=None) -> _abi.NtfTucker:
+    """Descriptor of T = (U^(1) (x) ... (x) U^(N)) core (float32 core, bases n_p x r_p)."""
+    bases = list(bases)
+    if core.dtype != torch.float32:
+        raise ValueError("the Tucker core must be float32")
+    if len(bases) != core.dim():
+        raise ValueError(f"{len(bases)} bases for a {core.dim()}-way core")
+    X = _abi.NtfTucker()
+    X.core = _tensor_desc(core)
+    for p, U in enumerate(bases):
+        if U.dim() != 2 or int(U.shape[1]) != int(core.shape[p]):
+            raise ValueError(f"basis {p} has shape {tuple(U.shape)}; it needs "
+                             f"{int(core.shape[p])} columns")
+        X.U[p] = _dev(U, f"U[{p}]", torch.float32)
+        X.dims[p] = int(U.shape[0])
+    return X
+
+
+def _tucker_factors(X: _abi.NtfTucker, core, factors, skip=()) -> int:
+    factors = list(factors)
+    if len(factors) != core.dim():
+        raise ValueError(f"{len(factors)} factors for a {core.dim()}-way tensor")
+    r = None
+    for l, A in enumerate(factors):
+        if A is None and l in skip:
+            continue
+        if A is None or A.dim() != 2:
+            raise ValueError(f"factor {l} must be a matrix")
+        r = int(A.shape[1]) if r is None else r
+        _check_shape(A, (X.dims[l], r), f"factor {l}")
+    return r
+
+
+def ntf_tucker_mttkrp(core: torch.Tensor, bases, factors, mode: int,
+                      out: torch.Tensor | None = None, h=None, stream=None) -> torch.Tensor:
+    """MTTKRP of mode `mode` of the Tucker-format tensor (Appendix A); T is never formed."""
+    X = _tucker_desc(core, bases)
+    if not 0 <= int(mode) < core.dim():
+        raise ValueError(f"mode {mode} outside [0, {core.dim()})")
+    r = _tucker_factors(X, core, factors, skip=(int(mode),))
+    if out is None:
+        out = torch.empty((X.dims[mode], r), dtype=torch.float32, device=core.device)
+    _check_shape(out, (X.dims[mode], r), "out")
+    ptrs = ptr_array([(_dev(A, f"A[{l}]", torch.float32) if (A is not None and l != mode) else None)
+                      for l, A in enumerate(factors)])
+    check(lib().ntf_tucker_mttkrp(_h(h), C.byref(X), ptrs, r, int(mode),
+                                  _dev(out, "P", torch.float32), _stream(stream)))
+    return out
+
+
+def ntf_tucker_norm2(core: torch.Tensor, bases, h=None, stream=None) -> torch.Tensor:
+    out = torch.empty((), dtype=torch.float64, device=core.device)
+    X = _tucker_desc(core, bases)
+    check(lib().ntf_tucker_norm2(_h(h), C.byref(X), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def ntf_solve_tucker(core: torch.Tensor, bases, factors, iters: int,
+                     params: HerParams | None = None, state: torch.Tensor | None = None,
+                     resume: bool = False, trace: bool = True, h=None, stream=None):
+    """ntf_solve on a Tucker-format tensor (Appendix A); returns (state, trace)."""
+    p = (params or HerParams()).to_c()
+    X = _tucker_desc(core, bases)
+    r = _tucker_factors(X, core, factors)
+    N = core.dim()
+    dev = core.device
+    if state is None:
+        state = new_state(dev)
+    tr, ctr = _trace_buffers(iters, N, dev) if trace and iters > 0 else (None, None)
+    ptrs = ptr_array([_dev(A, f"A[{l}]", torch.float32) for l, A in enumerate(factors)])
+    check(lib().ntf_solve_tucker(_h(h), C.byref(X), r, ptrs, C.byref(p), int(iters),
+                                 _dev(state, "state"), 1 if resume else 0,
+                                 C.byref(ctr) if ctr is not None else None, _stream(stream)))
+    return state, tr
+
+
+def _trace_buffers(iters: int, N: int, dev):
+    tr = dict(fhat=torch.zeros(iters, dtype=torch.float64, device=dev),
+              beta=torch.zeros(iters, dtype=torch.float64, device=dev),
+              beta_bar=torch.zeros(iters, dtype=torch.float64, device=dev),
+              restart=torch.zeros(iters, dtype=torch.int32, device=dev),
+              sweeps=torch.zeros((iters, N), dtype=torch.int32, device=dev))
+    ctr = _abi.NtfTrace(tr["fhat"].data_ptr(), tr["beta"].data_ptr(),
+                        tr["beta_bar"].data_ptr(), tr["restart"].data_ptr(),
+                        tr["sweeps"].data_ptr())
+    return tr, ctr
 
 
 def ntf_solve_apg(T: torch.Tensor, factors, iters: int, delta_w: float = 0.9999, h=None,

@@ -22,6 +22,11 @@ class NtfTensor(C.Structure):
                 ("dims", C.c_int64 * NTF_MAX_ORDER), ("data", C.c_void_p)]
 
 
+class NtfTucker(C.Structure):
+    _fields_ = [("core", NtfTensor), ("U", C.c_void_p * NTF_MAX_ORDER),
+                ("dims", C.c_int64 * NTF_MAX_ORDER)]
+
+
 class NtfHerParams(C.Structure):
     _fields_ = [("beta0", C.c_double), ("gamma", C.c_double), ("gamma_bar", C.c_double),
                 ("eta", C.c_double), ("max_inner", C.c_int32), ("inner_solver", C.c_int32),
@@ -89,6 +94,12 @@ SIGNATURES = {
                                 C.c_double, PTR, PTR, PTR]),
     "ntf_solve_ibpg": (C.c_int, [PTR, C.POINTER(NtfTensor), C.c_int32, PTRS, C.c_int32,
                                  C.c_int32, C.c_double, C.c_double, PTR, PTR]),
+    "ntf_tucker_mttkrp": (C.c_int, [PTR, C.POINTER(NtfTucker), PTRS, C.c_int32, C.c_int32, PTR,
+                                    PTR]),
+    "ntf_tucker_norm2": (C.c_int, [PTR, C.POINTER(NtfTucker), PTR, PTR]),
+    "ntf_solve_tucker": (C.c_int, [PTR, C.POINTER(NtfTucker), C.c_int32, PTRS,
+                                   C.POINTER(NtfHerParams), C.c_int32, PTR, C.c_int32,
+                                   C.POINTER(NtfTrace), PTR]),
     "ntf_admm_update": (C.c_int, [PTR, PTR, PTR, PTR, C.c_int64, C.c_int32, C.c_int32,
                                   C.c_double, PTR, PTR]),
     "ntf_mttkrp_multi": (C.c_int, [PTR, C.POINTER(NtfTensor), PTRS, C.c_int32, C.c_int32, PTRS,

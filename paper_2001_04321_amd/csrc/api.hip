@@ -83,6 +83,21 @@ ntf_status check_tensor(const ntf_tensor* T) {
   return NTF_OK;
 }
 
+ntf_status check_tucker(const ntf_tucker* X) {
+  NTF_RETURN_IF(!X, NTF_EINVAL, "Tucker descriptor is NULL");
+  ntf_status st = check_tensor(&X->core);
+  if (st) return st;
+  NTF_RETURN_IF(X->core.dtype != NTF_F32, NTF_EUNSUPPORTED, "the Tucker core must be float32");
+  for (int p = 0; p < X->core.order; ++p) {
+    NTF_RETURN_IF(!X->U[p], NTF_EINVAL, "basis %d is NULL", p);
+    NTF_RETURN_IF(X->dims[p] < 1, NTF_EINVAL, "size %d of the Tucker tensor is < 1", p);
+    NTF_RETURN_IF(X->core.dims[p] > 4096, NTF_EUNSUPPORTED, "Tucker rank %d above 4096", p);
+    NTF_RETURN_IF(X->dims[p] > (int64_t(1) << 31) - 1, NTF_EUNSUPPORTED,
+                  "size %d of the Tucker tensor too large", p);
+  }
+  return NTF_OK;
+}
+
 ntf_status check_rank(int32_t r) {
   NTF_RETURN_IF(r < 1 || r > NTF_MAX_RANK, NTF_EINVAL, "rank %d outside [1, %d]", r,
                 NTF_MAX_RANK);
@@ -268,6 +283,55 @@ ntf_status ntf_mttkrp(ntf_handle* h, const ntf_tensor* T, const float* const* A,
   if (st) return st;
   NTF_HIP(launch_mttkrp(pl, T->data, fp, P, reinterpret_cast<float*>(h->ws), true,
                         as_stream(stream)));
+  return NTF_OK;
+}
+
+ntf_status ntf_tucker_mttkrp(ntf_handle* h, const ntf_tucker* X, const float* const* A,
+                             int32_t r, int32_t mode, float* P, void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_tucker(X);
+  if (st) return st;
+  if ((st = check_rank(r))) return st;
+  const int N = X->core.order;
+  NTF_RETURN_IF(mode < 0 || mode >= N, NTF_EINVAL, "mode %d outside [0, %d)", mode, N);
+  NTF_RETURN_IF(!A || !P, NTF_EINVAL, "factor array or output is NULL");
+  for (int l = 0; l < N; ++l)
+    NTF_RETURN_IF(l != mode && !A[l], NTF_EINVAL, "factor %d is NULL", l);
+  const MttkrpPlan pl =
+      plan_mttkrp(X->core, mode, r, h->num_cus, false, tuned_choice(h, X->core, mode, r));
+  Arena dry;
+  float* Q[kMaxOrder] = {};
+  for (int l = 0; l < N; ++l) dry.take<float>(size_t(X->core.dims[l]) * r);
+  dry.take<float>(size_t(X->core.dims[mode]) * r);
+  dry.take<float>(std::max<size_t>(pl.partial_floats(), 1));
+  if ((st = ensure_workspace(h, dry.off + 256))) return st;
+  Arena ar{h->ws, 0};
+  for (int l = 0; l < N; ++l) Q[l] = ar.take<float>(size_t(X->core.dims[l]) * r);
+  float* Pc = ar.take<float>(size_t(X->core.dims[mode]) * r);
+  float* part = ar.take<float>(std::max<size_t>(pl.partial_floats(), 1));
+  hipStream_t s = as_stream(stream);
+  FactorPtrs fq{};
+  for (int l = 0; l < N; ++l) {
+    fq.p[l] = Q[l];
+    if (l != mode)
+      NTF_HIP(launch_tucker_proj(X->U[l], A[l], X->dims[l], int(X->core.dims[l]), r, Q[l],
+                                 nullptr, s));
+  }
+  NTF_HIP(launch_mttkrp(pl, X->core.data, fq, Pc, part, true, s));
+  NTF_HIP(launch_tucker_expand(X->U[mode], Pc, X->dims[mode], int(X->core.dims[mode]), r, P, s));
+  return NTF_OK;
+}
+
+ntf_status ntf_tucker_norm2(ntf_handle* h, const ntf_tucker* X, double* out, void* stream) {
+  clear_error();
+  NTF_GUARD(h);
+  ntf_status st = check_tucker(X);
+  if (st) return st;
+  NTF_RETURN_IF(!out, NTF_EINVAL, "out is NULL");
+  if ((st = ensure_workspace(h, tucker_norm_workspace_doubles(*X) * sizeof(double) + 256)))
+    return st;
+  NTF_HIP(launch_tucker_norm2(*X, reinterpret_cast<double*>(h->ws), out, as_stream(stream)));
   return NTF_OK;
 }
 

@@ -327,6 +327,39 @@ struct AdmmArgs {
 int64_t admm_workgroups(int64_t rows, int r);
 hipError_t launch_admm(const AdmmArgs& a, hipStream_t s);
 
+// A-HALS without the residency bound (k_hals_rows.hip): one thread per row, r <= 32, the
+// stopping rule decided between two passes (at most kHalsRowsMaxSweeps sweeps). Workspace:
+// part (max_sweeps x hals_rows_workgroups(rows) doubles), sweeps_dev (1 int).
+constexpr int kHalsRowsMaxSweeps = 64;
+constexpr int kHalsRowsMaxRank = 32;
+struct HalsRowsArgs {
+  const float* W0;
+  float* W;
+  const float* P;
+  const float* G;
+  double* part;
+  int32_t* sweeps_dev;
+  int64_t rows;
+  int r;
+  int max_sweeps;
+  double tol;
+  int32_t* sweeps_out;  // may be null
+};
+int64_t hals_rows_workgroups(int64_t rows);
+hipError_t launch_hals_rows(const HalsRowsArgs& a, hipStream_t s);
+
+// Tucker-format data (k_tucker.hip).
+using TuckerDesc = ntf_tucker;
+// Q = U^T A (U: n x rp, A: n x r) into Q32 (float) and/or Q64 (double), either may be null.
+hipError_t launch_tucker_proj(const float* U, const float* A, int64_t n, int rp, int r,
+                              float* Q32, double* Q64, hipStream_t s);
+// P = U Pc (U: n x rp, Pc: rp x r).
+hipError_t launch_tucker_expand(const float* U, const float* Pc, int64_t n, int rp, int r,
+                                float* P, hipStream_t s);
+size_t tucker_norm_workspace_doubles(const TuckerDesc& X);
+hipError_t launch_tucker_norm2(const TuckerDesc& X, double* ws, double* out, hipStream_t s);
+ntf_status check_tucker(const ntf_tucker* X);
+
 // Extrapolate-project: out = max(0, a_new + beta (a_new - a_old)), beta = *beta_src (without
 // the projection when `project` is false).
 hipError_t launch_extrapolate(const float* a_new, const float* a_old, float* out, int64_t n,

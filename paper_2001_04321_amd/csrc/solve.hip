@@ -31,6 +31,7 @@ struct SolveKey {
   ntf_her_state* state;
   ntf_trace trace;
   uint64_t ws_generation;
+  const float* U[kMaxOrder];  // Tucker-format data: bases (T then names the core)
   bool operator==(const SolveKey& o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
 };
 
@@ -69,10 +70,15 @@ struct SolveBufs {
   float* admm_rho;
   double* admm_part;
   int32_t* admm_steps;
+  double* hr_part;      // A-HALS beyond the resident kernel's rows: per-sweep shares, stop
+  int32_t* hr_sweeps;
+  float* Q[kMaxOrder];  // Tucker-format data: projected factors U^(p)T A^(p) (r_p x r)
+  float* Pc;            // and the core's MTTKRP (r_n x r)
+  double* tnorm;        // workspace of ||T||^2 of the format
 };
 
 void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
-           const MttkrpPlan* plans, bool own_state, bool shared_y) {
+           const MttkrpPlan* plans, bool own_state, bool shared_y, const TuckerDesc* tk) {
   const int N = T.order;
   const size_t rr = size_t(r) * r;
   b.norm_part = ar.take<double>(norm2_partials());
@@ -115,6 +121,18 @@ void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
   b.admm_part = ar.take<double>(size_t(std::min(max_inner, kAdmmMaxSteps)) *
                                 size_t(admm_workgroups(maxI, r)));
   b.admm_steps = ar.take<int32_t>(1);
+  b.hr_part = ar.take<double>(size_t(std::min(max_inner, kHalsRowsMaxSweeps)) *
+                              size_t(hals_rows_workgroups(maxI)));
+  b.hr_sweeps = ar.take<int32_t>(1);
+  if (tk) {
+    int64_t maxr = 1;
+    for (int n = 0; n < N; ++n) {
+      b.Q[n] = ar.take<float>(size_t(tk->core.dims[n]) * r);
+      maxr = std::max(maxr, tk->core.dims[n]);
+    }
+    b.Pc = ar.take<float>(size_t(maxr) * r);
+    b.tnorm = ar.take<double>(tucker_norm_workspace_doubles(*tk));
+  }
 }
 
 FactorPtrs factors_for(int n, int N, float* const* A, const SolveBufs& b) {
@@ -128,10 +146,38 @@ FactorPtrs factors_for(int n, int N, float* const* A, const SolveBufs& b) {
 // A-HALS wait slots), the MTTKRP (and the fixed-order sum of its split partials), and the
 // fused A-HALS kernel (sweeps, extrapolation, Gram partials, F-hat share); then decide
 // and select.
+// The MTTKRP of mode n of Tucker-format data into b.P (Appendix A): projections of the
+// other factors, the core's MTTKRP (with the next A-HALS launch's Hadamard product as its
+// leading workgroups), the expansion by U^(n).
+hipError_t tucker_mttkrp_into(const TuckerDesc& tk, int n, int r, const FactorPtrs& fp,
+                              const MttkrpPlan& plan, const SolveBufs& b, hipStream_t s,
+                              const HadamardLaunch* had) {
+  const int N = tk.core.order;
+  hipError_t e;
+  FactorPtrs fq{};
+  for (int l = 0; l < N; ++l) {
+    fq.p[l] = b.Q[l];
+    if (l == n) continue;
+    if ((e = launch_tucker_proj(tk.U[l], fp.p[l], tk.dims[l], int(tk.core.dims[l]), r, b.Q[l],
+                                nullptr, s)) != hipSuccess)
+      return e;
+  }
+  if ((e = launch_mttkrp(plan, tk.core.data, fq, b.Pc, b.mt_part, true, s, nullptr, had)) !=
+      hipSuccess)
+    return e;
+  return launch_tucker_expand(tk.U[n], b.Pc, tk.dims[n], int(tk.core.dims[n]), r, b.P, s);
+}
+
+// Blocks the resident A-HALS kernel covers run it (fused epilogue); larger ones run the
+// row-parallel A-HALS variant followed by the same epilogue steps as the other solvers.
+bool fused_hals(ntf_handle* h, const ntf_her_params& p, int64_t rows, int r) {
+  return p.inner_solver == 0 && hals_supported(rows, r, h->num_cus);
+}
+
 hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* const* A,
                              const ntf_her_params& p, const SolveBufs& b,
                              const MttkrpPlan* plans, const MttkrpPlan* plan_y,
-                             const ntf_trace& trace, hipStream_t s) {
+                             const ntf_trace& trace, hipStream_t s, const TuckerDesc* tk) {
   const int N = T.order;
   hipError_t e;
   for (int n = 0; n < N; ++n) {
@@ -148,7 +194,11 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
     // Split partials are summed by the wide reduction kernel: the A-HALS grid is too
     // narrow (one workgroup per row chunk) to stream them quickly.
     HadamardLaunch hl{hj, r, b.G32, b.G64, b.slots, hals_slot_count(I, r, p.max_inner)};
-    if (b.Y && n == 0) {
+    if (tk) {
+      if ((e = tucker_mttkrp_into(*tk, n, r, factors_for(n, N, A, b), plans[n], b, s, &hl)) !=
+          hipSuccess)
+        return e;
+    } else if (b.Y && n == 0) {
       if ((e = launch_mttkrp(*plan_y, T.data, factors_for(0, N, A, b), b.P, b.mt_part, true, s,
                              b.Y, &hl)) != hipSuccess)
         return e;
@@ -162,11 +212,25 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
                                   true, s, nullptr, &hl)) != hipSuccess) {
       return e;
     }
-    if (p.inner_solver != 0) {
-      // projected-gradient (Sec. 2.2) or ADMM (Sec. 2.1.2) block, then the steps the A-HALS
-      // epilogue fuses: extrapolation, Gram partials of A_new and A-hat, the F-hat share
-      // of the last block
-      if (p.inner_solver == 3) {
+    if (!fused_hals(h, p, I, r)) {
+      // projected-gradient (Sec. 2.2), ADMM (Sec. 2.1.2) or row-parallel A-HALS block, then
+      // the steps the resident A-HALS kernel's epilogue fuses: extrapolation, Gram partials
+      // of A_new and A-hat, the F-hat share of the last block
+      if (p.inner_solver == 0) {
+        HalsRowsArgs ra{};
+        ra.W0 = A[n];
+        ra.W = b.A_new[n];
+        ra.P = b.P;
+        ra.G = b.G32;
+        ra.part = b.hr_part;
+        ra.sweeps_dev = b.hr_sweeps;
+        ra.rows = I;
+        ra.r = r;
+        ra.max_sweeps = p.max_inner;
+        ra.tol = p.inner_tol;
+        ra.sweeps_out = b.sweeps + n;
+        if ((e = launch_hals_rows(ra, s)) != hipSuccess) return e;
+      } else if (p.inner_solver == 3) {
         AdmmArgs aa{};
         aa.W0 = A[n];
         aa.W = b.A_new[n];
@@ -242,7 +306,7 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
   d.p = p;
   d.normT2 = b.normT2;
   d.partials = b.err_part;
-  d.nparts = p.inner_solver != 0 ? error_partial_count(IN, r) : hals_wgs(IN, r);
+  d.nparts = fused_hals(h, p, IN, r) ? hals_wgs(IN, r) : error_partial_count(IN, r);
   d.trace = trace;
   d.order = N;
   d.sweeps_src = b.sweeps;
@@ -287,11 +351,12 @@ void release_solve_graph(ntf_handle* h) {
 
 using namespace ntf;
 
-extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, float* const* A,
-                                const ntf_her_params* params, int32_t iters,
-                                ntf_her_state* state, int32_t resume, const ntf_trace* trace,
-                                void* stream) {
-  clear_error();
+// Dense tensor T, or (tk != null) Tucker-format data whose logical tensor T has the sizes
+// of the full tensor (its data is the core's pointer and is never read as a tensor).
+static ntf_status solve_impl(ntf_handle* h, const ntf_tensor* T, const TuckerDesc* tk, int32_t r,
+                             float* const* A, const ntf_her_params* params, int32_t iters,
+                             ntf_her_state* state, int32_t resume, const ntf_trace* trace,
+                             void* stream) {
   NTF_RETURN_IF(!h, NTF_EINVAL, "handle is NULL");
   int old_dev = -1;
   (void)hipGetDevice(&old_dev);
@@ -303,7 +368,7 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
     }
   } restore{old_dev != h->device ? old_dev : -1};
 
-  ntf_status st = check_tensor(T);
+  ntf_status st = tk ? NTF_OK : check_tensor(T);
   if (st) return st;
   if ((st = check_rank(r))) return st;
   if ((st = check_params(params))) return st;
@@ -323,17 +388,23 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
       NTF_RETURN_IF(r > 128, NTF_EUNSUPPORTED, "projected-gradient and ADMM kernels support r <= 128");
       continue;
     }
-    NTF_RETURN_IF(!hals_supported(T->dims[n], r, h->num_cus), NTF_EUNSUPPORTED,
-                  "mode %d: A-HALS kernel supports r <= 128 and at most 256 row workgroups", n);
+    if (hals_supported(T->dims[n], r, h->num_cus)) continue;
+    // beyond the resident kernel's rows: the row-parallel variant
+    NTF_RETURN_IF(r > kHalsRowsMaxRank || params->max_inner > kHalsRowsMaxSweeps,
+                  NTF_EUNSUPPORTED,
+                  "mode %d: A-HALS covers this many rows for r <= %d and at most %d sweeps", n,
+                  kHalsRowsMaxRank, kHalsRowsMaxSweeps);
   }
+  // the MTTKRP plans: of the tensor, or of the core for Tucker-format data
+  const ntf_tensor& MT = tk ? tk->core : *T;
   MttkrpPlan plans[kMaxOrder];
   for (int n = 0; n < N; ++n) {
-    plans[n] = plan_mttkrp(*T, n, r, h->num_cus, false, tuned_choice(h, *T, n, r));
+    plans[n] = plan_mttkrp(MT, n, r, h->num_cus, false, tuned_choice(h, MT, n, r));
     NTF_RETURN_IF(plans[n].chunks >= (int64_t(1) << 31), NTF_EUNSUPPORTED, "reduction too long");
   }
   MttkrpPlan plan_y{};
   bool shared_y = false;
-  if (N == 3) {
+  if (N == 3 && !tk) {
     plan_y = plan_mttkrp(*T, 0, r, h->num_cus, true);
     shared_y = use_shared_y(*T, r, plan_y);
   }
@@ -342,10 +413,10 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
 
   Arena dry;
   SolveBufs b{};
-  carve(dry, b, *T, r, params->max_inner, plans, state == nullptr, shared_y);
+  carve(dry, b, *T, r, params->max_inner, plans, state == nullptr, shared_y, tk);
   if ((st = ensure_workspace(h, dry.off + 256))) return st;
   Arena ar{h->ws, 0};
-  carve(ar, b, *T, r, params->max_inner, plans, state == nullptr, shared_y);
+  carve(ar, b, *T, r, params->max_inner, plans, state == nullptr, shared_y, tk);
   if (state) b.state = state;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -353,7 +424,10 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
   for (int l = 0; l < N; ++l) n_all *= T->dims[l];
 
   // ---- set-up: ||T||^2, Gram cache of A, F-hat_0 = F(A_0) (or resume) ----
-  NTF_HIP(launch_norm2(T->data, T->dtype, n_all, b.norm_part, b.normT2, s));
+  if (tk)
+    NTF_HIP(launch_tucker_norm2(*tk, b.tnorm, b.normT2, s));
+  else
+    NTF_HIP(launch_norm2(T->data, T->dtype, n_all, b.norm_part, b.normT2, s));
   GramJob gj{};
   gj.nfac = N;
   for (int l = 0; l < N; ++l) {
@@ -372,7 +446,10 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
     NTF_HIP(launch_hadamard(hj, r, b.G32, b.G64, nullptr, 0, s));
     FactorPtrs fp{};
     for (int l = 0; l < N; ++l) fp.p[l] = A[l];
-    NTF_HIP(launch_mttkrp(plans[N - 1], T->data, fp, b.P, b.mt_part, true, s));
+    if (tk)
+      NTF_HIP(tucker_mttkrp_into(*tk, N - 1, r, fp, plans[N - 1], b, s, nullptr));
+    else
+      NTF_HIP(launch_mttkrp(plans[N - 1], T->data, fp, b.P, b.mt_part, true, s));
     const int64_t IN = T->dims[N - 1];
     NTF_HIP(launch_error_partials(b.P, A[N - 1], b.G64, IN, r, b.err_part, s));
     NTF_HIP(launch_error_finalize(b.normT2, b.err_part, error_partial_count(IN, r), b.fhat0,
@@ -397,6 +474,8 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
   key.p = *params;
   key.state = b.state;
   key.trace = tr;
+  if (tk)
+    for (int l = 0; l < N; ++l) key.U[l] = tk->U[l];
   key.ws_generation = h->ws_generation;
   if (!h->graph || !(h->graph->key == key)) {
     release_solve_graph(h);
@@ -404,7 +483,7 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
     g->key = key;
     NTF_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed));
     hipError_t e = enqueue_iteration(h, *T, r, A, *params, b, plans, &plan_y, tr,
-                                     h->capture_stream);
+                                     h->capture_stream, tk);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(h->capture_stream, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -425,4 +504,28 @@ extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, f
   }
   for (int k = 0; k < iters; ++k) NTF_HIP(hipGraphLaunch(h->graph->exec, s));
   return NTF_OK;
+}
+
+extern "C" ntf_status ntf_solve(ntf_handle* h, const ntf_tensor* T, int32_t r, float* const* A,
+                                const ntf_her_params* params, int32_t iters,
+                                ntf_her_state* state, int32_t resume, const ntf_trace* trace,
+                                void* stream) {
+  clear_error();
+  return solve_impl(h, T, nullptr, r, A, params, iters, state, resume, trace, stream);
+}
+
+extern "C" ntf_status ntf_solve_tucker(ntf_handle* h, const ntf_tucker* X, int32_t r,
+                                       float* const* A, const ntf_her_params* params,
+                                       int32_t iters, ntf_her_state* state, int32_t resume,
+                                       const ntf_trace* trace, void* stream) {
+  clear_error();
+  NTF_RETURN_IF(!h, NTF_EINVAL, "handle is NULL");
+  ntf_status st = check_tucker(X);
+  if (st) return st;
+  ntf_tensor T{};
+  T.order = X->core.order;
+  T.dtype = NTF_F32;
+  for (int l = 0; l < T.order; ++l) T.dims[l] = X->dims[l];
+  T.data = X->core.data;
+  return solve_impl(h, &T, X, r, A, params, iters, state, resume, trace, stream);
 }

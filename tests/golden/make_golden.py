@@ -2,6 +2,7 @@
 
     python tests/golden/make_golden.py cube50_r10 cube400_r32_corr quad128_r64_sparse:bf16:20
     python tests/golden/make_golden.py batch256:200
+    python tests/golden/make_golden.py tucker_video_r10
 
 Calls only the oracle (and the seeded input generator for its inputs). The oracle sees
 the float32 values of the tensor and the initial factors, as the GPU does; a spec
@@ -12,7 +13,8 @@ workload's outer-iteration count. For each spec it records the final relative er
 of Algorithm 2 (HER with A-HALS, the paper's default parameters; the fit is taken against
 the tensor the oracle solved), the number of restarts, and the F-hat trace, under the key
 `name` (float32 tensor, the workload's own count) or the spec itself. `batch256:K` records
-the fits after K iterations of 16 problems of the 256-problem batch (see `batch_pick`).
+the fits after K iterations of 16 problems of the 256-problem batch (see `batch_pick`); a
+Tucker-format workload name records Algorithm 2 on the format (Appendix A).
 """
 import json
 import os
@@ -83,10 +85,33 @@ def run_batch(iters: int) -> dict:
     return out
 
 
+def run_tucker(name: str) -> dict:
+    """Algorithm 2 on a Tucker-format workload (Appendix A) from the float32 core, bases and
+    initial factors the GPU receives; the fit by the format's own residual norm."""
+    w = synth.TUCKER_WORKLOADS[name]
+    pr = synth.tucker_workload(name)
+    core = pr.core.astype(np.float32).astype(np.float64)
+    bases = [U.astype(np.float32).astype(np.float64) for U in pr.bases]
+    A0 = [a.astype(np.float32).astype(np.float64) for a in pr.A0]
+    t0 = time.perf_counter()
+    res = oracle.tucker_her_solve(core, bases, A0, w["iters"])
+    dt = time.perf_counter() - t0
+    rel = oracle.tucker_relative_error(core, bases, res.factors)
+    return dict(workload=name, tensor="tucker_f32", iters=w["iters"], relerr=rel, fit=1.0 - rel,
+                restarts=int(sum(res.restart)), fhat=res.fhat, fhat0=res.fhat0,
+                oracle_seconds=dt, cpu_count=os.cpu_count())
+
+
 def main(names):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for n in names:
         print(f"running {n} ...", flush=True)
+        if n in synth.TUCKER_WORKLOADS:
+            data[n] = run_tucker(n)
+            print(f"{n}: fit {data[n]['fit']:.8f} in {data[n]['oracle_seconds']:.1f}s",
+                  flush=True)
+            json.dump(data, open(OUT, "w"), indent=1)
+            continue
         if n.startswith("batch256"):
             data[n] = run_batch(int(n.split(":")[1]))
             json.dump(data, open(OUT, "w"), indent=1)

@@ -51,6 +51,7 @@ def test_version_and_status_strings(lib):
 def test_null_handle_is_rejected_without_device_work(lib):
     from paper_2001_04321_amd import _abi
     T = _abi.NtfTensor()
+    X = _abi.NtfTucker()
     p = _abi.NtfHerParams(0.5, 1.05, 1.01, 1.5, 50, 0, 1e-2)
     calls = [
         lambda: lib.ntf_norm2(None, C.byref(T), None, None),
@@ -68,6 +69,13 @@ def test_null_handle_is_rejected_without_device_work(lib):
         lambda: lib.ntf_tune_import(None, b"f32:4x4x4:mode0:r4 1 4\n"),
         lambda: lib.ntf_mttkrp_noalloc(None, C.byref(T), None, 4, 0, None, None),
         lambda: lib.ntf_handle_set_wait_limit(None, 1.0),
+        lambda: lib.ntf_admm_update(None, None, None, None, 10, 4, 50, 1e-2, None, None),
+        lambda: lib.ntf_solve_apg(None, C.byref(T), 4, None, 10, 0.9999, None, None, None),
+        lambda: lib.ntf_solve_ibpg(None, C.byref(T), 4, None, 10, 50, 0.99, 1.01, None, None),
+        lambda: lib.ntf_tucker_mttkrp(None, C.byref(X), None, 4, 0, None, None),
+        lambda: lib.ntf_tucker_norm2(None, C.byref(X), None, None),
+        lambda: lib.ntf_solve_tucker(None, C.byref(X), 4, None, C.byref(p), 10, None, 0, None,
+                                     None),
     ]
     for call in calls:
         assert call() == _abi.NTF_EINVAL

@@ -144,6 +144,21 @@ def test_tucker_norm_and_solve_match_the_dense_tensor():
         assert np.allclose(a, b, rtol=1e-7, atol=1e-9)
 
 
+def test_tucker_relative_error_matches_the_explicit_residual():
+    """The compressed ||T - [[A]]|| / ||T|| equals the explicit residual of the expanded
+    tensor (non-orthonormal bases, 4-way), and is 0 at the planted factors without noise."""
+    g = np.random.default_rng(12)
+    core = g.standard_normal((3, 4, 2, 3))
+    bases = [g.standard_normal((6, 3)), g.standard_normal((5, 4)), g.standard_normal((7, 2)),
+             g.standard_normal((4, 3))]
+    A = [g.random((U.shape[0], 3)) for U in bases]
+    T = tucker.tucker_full(core, bases)
+    ref = np.linalg.norm((T - oracle.kruskal(A)).ravel()) / np.linalg.norm(T.ravel())
+    assert tucker.tucker_relative_error(core, bases, A) == pytest.approx(ref, rel=1e-12)
+    pr = synth.make_tucker_problem((15, 12, 40), (6, 5, 7), 4, snr_db=None, data_seed=5)
+    assert tucker.tucker_relative_error(pr.core, pr.bases, pr.A_true) < 1e-6
+
+
 def test_tucker_generator_plants_the_factors_in_the_bases():
     """The bases span the planted factors, so the noiseless format is exactly [[A]]."""
     pr = synth.make_tucker_problem((15, 12, 40), (6, 5, 7), 4, snr_db=None, data_seed=5)
