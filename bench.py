@@ -13,14 +13,16 @@ MTTKRP throughput, final relative errors (explicit residual against the float32 
 and the FP64 oracle's rate on the host are reported beside it.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
-                    [--no-autograd] [--no-quad] [--no-accuracy] [--copy-probe]
+                    [--no-autograd] [--no-quad] [--no-tucker] [--no-accuracy]
+                    [--copy-probe]
                     [--profile TARGET]
 
 Also reported (not the headline value): HER with projected-gradient and Nesterov block
 solvers on the same workload, the read-only streaming rate at each tensor's
 footprint (the MTTKRP's practical roof), the 4-way 128^4 bf16 r=64 workload (solver rate,
-per-mode MTTKRP and its fraction of the bf16 MFMA peak), the 256-problem batched workload
-solved in one persistent launch, and the 512^3 r=50 autograd loss with its backward.
+per-mode MTTKRP and its fraction of the bf16 MFMA peak), the 153 x 238 x 14000 data given in
+Tucker format (ranks 30, r=10), the 256-problem batched workload solved in one persistent
+launch, and the 512^3 r=50 autograd loss with its backward.
 """
 from __future__ import annotations
 
@@ -75,12 +77,20 @@ def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def time_solve(ntf, torch, Td, A_dev, A0_dev, steps, warmup, params):
-    """Warm up (captures the graph), restore A_0, then time `steps` outer iterations."""
+def time_solve(ntf, torch, Td, A_dev, A0_dev, steps, warmup, params, solve=None):
+    """Warm up (captures the iteration graph), restore A_0, then time `steps` outer
+    iterations. Both calls get the same state and trace buffers, so the timed call replays
+    the graph the warm-up captured."""
+    if solve is None:
+        def solve(A, iters, state, trace):
+            return ntf.ntf_solve(Td, A, iters, params=params, state=state, trace=trace)
+    order = len(A_dev)
+    state = ntf.new_state()
+    trace = ntf.new_trace(max(steps, warmup, 1), order)
     for a, a0 in zip(A_dev, A0_dev):
         a.copy_(a0)
     if warmup > 0:
-        ntf.ntf_solve(Td, A_dev, warmup, params=params, trace=False)
+        solve(A_dev, warmup, state, trace)
     torch.cuda.synchronize()
     for a, a0 in zip(A_dev, A0_dev):
         a.copy_(a0)
@@ -88,12 +98,12 @@ def time_solve(ntf, torch, Td, A_dev, A0_dev, steps, warmup, params):
     e0, e1 = _events(torch)
     t0 = time.perf_counter()
     e0.record()
-    state, trace = ntf.ntf_solve(Td, A_dev, steps, params=params, trace=True)
+    solve(A_dev, steps, state, trace)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    return ms, wall, state, trace
+    return ms, wall, state, {k: v[:steps] for k, v in trace.items()}
 
 
 def time_mttkrp(ntf, torch, Td, A_dev, reps):
@@ -323,6 +333,55 @@ def bench_quad128(ntf, torch, iters: int, warmup: int, reps: int, autotune: bool
     return out
 
 
+def bench_tucker(ntf, torch, warmup: int):
+    """Data given in Tucker format (Appendix A): the 153 x 238 x 14000 video-shaped workload
+    (Tucker ranks 30, CP rank 10, 30 dB) solved by ntf_solve_tucker for the workload's
+    outer-iteration count; its fit from the format's residual norm
+    ||T||^2 - 2 <P_N, A_N> + sum(Hadamard of the factor Grams), all terms from library
+    calls (ntf_tucker_norm2, ntf_tucker_mttkrp) summed in float64, against the oracle's
+    stored fit."""
+    import numpy as np
+
+    import synth
+    name = "tucker_video_r10"
+    w = synth.TUCKER_WORKLOADS[name]
+    pr = synth.tucker_workload(name)
+    core = torch.from_numpy(pr.core.astype(np.float32)).cuda()
+    bases = [torch.from_numpy(U.astype(np.float32)).cuda() for U in pr.bases]
+    A0 = [torch.from_numpy(a.astype(np.float32)).cuda() for a in pr.A0]
+    del pr
+    iters = int(w["iters"])
+    A = [a.clone() for a in A0]
+
+    def solve(Ax, n, state, trace):
+        return ntf.ntf_solve_tucker(core, bases, Ax, n, state=state, trace=trace)
+
+    ms, _, _, trace = time_solve(ntf, torch, None, A, A0, iters, warmup, None, solve=solve)
+    normT2 = float(ntf.ntf_tucker_norm2(core, bases).item())
+    N = len(A)
+    P = ntf.ntf_tucker_mttkrp(core, bases, A, N - 1)
+    cross = float((P.double() * A[N - 1].double()).sum().item())
+    H = torch.ones((A[0].shape[1],) * 2, dtype=torch.float64, device="cuda")
+    for a in A:
+        H = H * (a.double().T @ a.double())
+    relerr = max(normT2 - 2.0 * cross + float(H.sum().item()), 0.0) ** 0.5 / normT2 ** 0.5
+    out = dict(workload=name, dims=list(w["dims"]), tucker_ranks=list(w["ranks"]),
+               rank=int(w["r"]), iters=iters, iters_per_s=round(iters / (ms / 1e3), 1),
+               ms_per_iter=round(ms / iters, 4), final_relerr=relerr,
+               restarts=int(trace["restart"].sum().item()),
+               mean_inner_sweeps=[round(x, 2) for x in
+                                  trace["sweeps"].float().mean(0).tolist()])
+    gpath = os.path.join(ROOT, "tests", "golden", "oracle_fits.json")
+    if os.path.exists(gpath):
+        g = json.load(open(gpath)).get(name)
+        if g and int(g["iters"]) == iters:
+            out["oracle_relerr"] = g["relerr"]
+            out["fit_within_1e-3"] = abs((1.0 - relerr) - g["fit"]) <= 1e-3 * g["fit"]
+    del core, bases, A, A0
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_probe(torch, nbytes: int = 256 << 20):
     """A plain device copy of known size (traffic counters are scaled by it)."""
     x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -389,7 +448,8 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, out_path: str, command
     return out
 
 
-PROFILE_TARGETS = ("mttkrp-cube400", "mttkrp-quad128", "fused4-quad128", "solve-cube400")
+PROFILE_TARGETS = ("mttkrp-cube400", "mttkrp-quad128", "fused4-quad128", "solve-cube400",
+                   "hals-cube400")
 
 
 def profile_calls(ntf, torch, target: str, reps: int):
@@ -397,7 +457,8 @@ def profile_calls(ntf, torch, target: str, reps: int):
     shapes): `mttkrp-cube400` reps ntf_mttkrp calls per mode on the 400^3 tensor as bf16 and
     as float32, `mttkrp-quad128` the same on the 128^4 bf16 tensor, `fused4-quad128` reps
     four-mode ntf_mttkrp_multi calls on the 128^4 bf16 tensor, `solve-cube400` reps outer
-    iterations of the bf16 solver."""
+    iterations of the bf16 solver, `hals-cube400` reps ntf_hals_update calls per mode
+    (50 sweeps at most, tol 1e-2) from A_0 with the P (bf16 tensor) and G of A_0."""
     import numpy as np
 
     import synth
@@ -417,6 +478,13 @@ def profile_calls(ntf, torch, target: str, reps: int):
                 P = ntf.ntf_mttkrp(Td, A, n)
                 for _ in range(reps):
                     ntf.ntf_mttkrp(Td, A, n, out=P)
+    elif target.startswith("hals"):
+        for n in range(T16.dim()):
+            P = ntf.ntf_mttkrp(T16, A, n)
+            G32, _ = ntf.ntf_gram(A, exclude=n, want64=False)
+            for _ in range(reps):
+                W = A[n].clone()
+                ntf.ntf_hals_update(W, P, G32, 50, 1e-2)
     elif target.startswith("fused4"):
         for _ in range(reps):
             ntf.ntf_mttkrp_multi(T16, A, range(4))
@@ -519,6 +587,7 @@ def main(argv=None):
     ap.add_argument("--comp-iters", type=int, default=100,
                     help="outer iterations of the APG and iBPG comparison runs")
     ap.add_argument("--no-quad", action="store_true")
+    ap.add_argument("--no-tucker", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MB device copy (reference for traffic counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -771,6 +840,9 @@ def main(argv=None):
         line["quad128"] = bench_quad128(ntf, torch, a.quad_iters, 5, a.mttkrp_reps,
                                         not a.no_autotune)
         line["stream_gbs"]["bf16_537MB"] = line["quad128"]["stream_gbs"]
+    if not a.no_tucker:
+        log("[bench] Tucker format: 153 x 238 x 14000, ranks 30, r=10")
+        line["tucker"] = bench_tucker(ntf, torch, a.warmup)
     if not a.no_batched:
         log(f"[bench] batched: 256 problems, {a.batched_iters} iterations, one launch")
         line["batched"] = bench_batched(ntf, torch, a.batched_iters)

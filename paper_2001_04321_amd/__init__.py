@@ -34,7 +34,7 @@ __all__ = [
     "ntf_tune_export", "ntf_tune_import", "save_tuning", "load_tuning", "ntf_mttkrp_multi",
     "ntf_pgd_update", "ntf_mttkrp_noalloc", "ntf_handle_set_wait_limit", "ntf_admm_update",
     "ntf_solve_apg", "ntf_solve_ibpg", "ntf_tucker_mttkrp", "ntf_tucker_norm2",
-    "ntf_solve_tucker",
+    "ntf_solve_tucker", "new_trace",
 ]
 
 _DTYPES = {torch.float32: _abi.NTF_F32, torch.bfloat16: _abi.NTF_BF16}
@@ -429,11 +429,12 @@ def ntf_residual_norm2(T: torch.Tensor, factors, h=None, stream=None) -> torch.T
 
 
 def ntf_solve(T: torch.Tensor, factors, iters: int, params: HerParams | None = None,
-              state: torch.Tensor | None = None, resume: bool = False, trace: bool = True,
+              state: torch.Tensor | None = None, resume: bool = False, trace=True,
               h=None, stream=None):
     """Run `iters` HER outer iterations in place on `factors` (list of float32 tensors).
 
-    Returns (state, trace) where trace is a dict of device tensors (or None).
+    trace: True (new buffers), a dict from new_trace (reused), or False. Returns
+    (state, trace) where trace is a dict of device tensors (or None).
     """
     p = (params or HerParams()).to_c()
     N = T.dim()
@@ -443,7 +444,7 @@ def ntf_solve(T: torch.Tensor, factors, iters: int, params: HerParams | None = N
         state = new_state(dev)
     if state.numel() < C.sizeof(_abi.NtfHerState):
         raise ValueError("state buffer is smaller than one ntf_her_state")
-    tr, ctr = _trace_buffers(iters, N, dev) if trace and iters > 0 else (None, None)
+    tr, ctr = _trace_buffers(trace, iters, N, dev)
     d = _tensor_desc(T)
     ptrs = ptr_array([_dev(A, f"A[{l}]", torch.float32) for l, A in enumerate(factors)])
     check(lib().ntf_solve(_h(h), C.byref(d), r, ptrs, C.byref(p), int(iters),
@@ -511,7 +512,7 @@ def ntf_tucker_norm2(core: torch.Tensor, bases, h=None, stream=None) -> torch.Te
 
 def ntf_solve_tucker(core: torch.Tensor, bases, factors, iters: int,
                      params: HerParams | None = None, state: torch.Tensor | None = None,
-                     resume: bool = False, trace: bool = True, h=None, stream=None):
+                     resume: bool = False, trace=True, h=None, stream=None):
     """ntf_solve on a Tucker-format tensor (Appendix A); returns (state, trace)."""
     p = (params or HerParams()).to_c()
     X = _tucker_desc(core, bases)
@@ -520,7 +521,7 @@ def ntf_solve_tucker(core: torch.Tensor, bases, factors, iters: int,
     dev = core.device
     if state is None:
         state = new_state(dev)
-    tr, ctr = _trace_buffers(iters, N, dev) if trace and iters > 0 else (None, None)
+    tr, ctr = _trace_buffers(trace, iters, N, dev)
     ptrs = ptr_array([_dev(A, f"A[{l}]", torch.float32) for l, A in enumerate(factors)])
     check(lib().ntf_solve_tucker(_h(h), C.byref(X), r, ptrs, C.byref(p), int(iters),
                                  _dev(state, "state"), 1 if resume else 0,
@@ -528,12 +529,34 @@ def ntf_solve_tucker(core: torch.Tensor, bases, factors, iters: int,
     return state, tr
 
 
-def _trace_buffers(iters: int, N: int, dev):
-    tr = dict(fhat=torch.zeros(iters, dtype=torch.float64, device=dev),
-              beta=torch.zeros(iters, dtype=torch.float64, device=dev),
-              beta_bar=torch.zeros(iters, dtype=torch.float64, device=dev),
-              restart=torch.zeros(iters, dtype=torch.int32, device=dev),
-              sweeps=torch.zeros((iters, N), dtype=torch.int32, device=dev))
+def new_trace(iters: int, order: int, device=None) -> dict:
+    """Device buffers for the trace of up to `iters` outer iterations of an order-`order`
+    problem. Passing the same dict (and state) to successive ntf_solve calls keeps their
+    arguments equal, so the captured iteration graph is reused instead of captured again."""
+    dev = device or "cuda"
+    return dict(fhat=torch.zeros(iters, dtype=torch.float64, device=dev),
+                beta=torch.zeros(iters, dtype=torch.float64, device=dev),
+                beta_bar=torch.zeros(iters, dtype=torch.float64, device=dev),
+                restart=torch.zeros(iters, dtype=torch.int32, device=dev),
+                sweeps=torch.zeros((iters, order), dtype=torch.int32, device=dev))
+
+
+def _trace_buffers(trace, iters: int, N: int, dev):
+    """(trace dict, ntf_trace) for trace=True (new buffers), a dict from new_trace (reused;
+    the call writes its first `iters` entries), or False/None (no trace)."""
+    if not trace or iters <= 0:
+        return None, None
+    if isinstance(trace, dict):
+        tr = trace
+        if tr["fhat"].numel() < iters or tuple(tr["sweeps"].shape[1:]) != (N,):
+            raise ValueError(f"trace buffers hold {tr['fhat'].numel()} iterations of order "
+                             f"{tuple(tr['sweeps'].shape[1:])}; need {iters} of order {N}")
+        for k, dt in (("fhat", torch.float64), ("beta", torch.float64),
+                      ("beta_bar", torch.float64), ("restart", torch.int32),
+                      ("sweeps", torch.int32)):
+            _dev(tr[k], f"trace[{k}]", dt)
+    else:
+        tr = new_trace(iters, N, dev)
     ctr = _abi.NtfTrace(tr["fhat"].data_ptr(), tr["beta"].data_ptr(),
                         tr["beta_bar"].data_ptr(), tr["restart"].data_ptr(),
                         tr["sweeps"].data_ptr())

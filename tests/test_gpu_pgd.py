@@ -93,15 +93,13 @@ def test_gradient_blocks_reject_a_tolerance_and_the_batched_solver(ntf):
 
 
 def test_gradient_blocks_beyond_the_ahals_row_limit(ntf):
-    """A block of 13000 rows (more than the A-HALS kernel's resident limit of 12288 at r <= 32):
-    A-HALS blocks are refused, projected-gradient blocks (rows are independent) are not."""
+    """A block of 13000 rows (more than the resident A-HALS kernel's 12288 at r <= 32):
+    projected-gradient blocks (rows are independent) cover it as they cover any block."""
     pr = synth.make_problem((13000, 8, 6), 4, snr_db=30.0, data_seed=8, init_seed=9)
     T32 = pr.T.astype(np.float32)
     A0 = [a.astype(np.float32) for a in pr.A0]
     Td, T64 = dev_tensor(T32, "f32")
     A = [dev_f32(a) for a in A0]
-    with pytest.raises(ntf.NtfError, match="A-HALS"):
-        ntf.ntf_solve(Td, [a.clone() for a in A], 1)
     iters = 5
     params = ntf.HerParams(inner="pgd", inner_tol=0.0, max_inner=50)
     _, tr = ntf.ntf_solve(Td, A, iters, params=params)
