@@ -449,7 +449,7 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, out_path: str, command
 
 
 PROFILE_TARGETS = ("mttkrp-cube400", "mttkrp-quad128", "fused4-quad128", "solve-cube400",
-                   "hals-cube400")
+                   "hals-cube400", "solve-quad128")
 
 
 def profile_calls(ntf, torch, target: str, reps: int):
@@ -457,7 +457,8 @@ def profile_calls(ntf, torch, target: str, reps: int):
     shapes): `mttkrp-cube400` reps ntf_mttkrp calls per mode on the 400^3 tensor as bf16 and
     as float32, `mttkrp-quad128` the same on the 128^4 bf16 tensor, `fused4-quad128` reps
     four-mode ntf_mttkrp_multi calls on the 128^4 bf16 tensor, `solve-cube400` reps outer
-    iterations of the bf16 solver, `hals-cube400` reps ntf_hals_update calls per mode
+    iterations of the bf16 solver (`solve-quad128`: on the 128^4 bf16 tensor),
+    `hals-cube400` reps ntf_hals_update calls per mode
     (50 sweeps at most, tol 1e-2) from A_0 with the P (bf16 tensor) and G of A_0."""
     import numpy as np
 

@@ -116,27 +116,37 @@ __device__ inline void hadamard_work(const HadamardJob& job, int r, float* G32, 
                                      double* slots, int64_t nslots, int64_t blk, int64_t nblk) {
   const int64_t tid = blk * blockDim.x + threadIdx.x;
   const int rr = r * r;
-  for (int64_t e64 = tid; e64 < rr; e64 += nblk * blockDim.x) {
+  // four consecutive threads per entry: thread q sums chunks q, q + 4, ... in order (up to
+  // sixteen loads in flight), then the four sums are combined as (s0 + s1) + (s2 + s3) by
+  // two exchanges (a + b and b + a are the same bits, so all four get the same value)
+  const int q = int(tid & 3);
+  const int64_t nq = (nblk * blockDim.x) >> 2;
+  for (int64_t e64 = tid >> 2; e64 < rr; e64 += nq) {
     const int e = int(e64);
     double g = 1.0;
     for (int f = 0; f < job.nfac; ++f) {
-      // chunk order; loads in batches of 8 so that they are in flight together
       double s = 0.0;
       const double* part = job.part[f];
       const int64_t nc = job.nchunks[f];
-      int64_t c = 0;
-      for (; c + 8 <= nc; c += 8) {
-        double v[8];
+      for (int64_t c0 = 0; c0 < nc; c0 += 64) {
+        double v[16];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) v[t] = part[(c + t) * rr + e];
+        for (int t = 0; t < 16; ++t) {
+          const int64_t c = c0 + q + 4 * t;
+          v[t] = part[(c < nc ? c : 0) * rr + e];
+        }
 #pragma unroll
-        for (int t = 0; t < 8; ++t) s += v[t];
+        for (int t = 0; t < 16; ++t)
+          if (c0 + q + 4 * t < nc) s += v[t];
       }
-      for (; c < nc; ++c) s += part[c * rr + e];
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
       g *= s;
     }
-    if (G32) G32[e] = float(g);
-    if (G64) G64[e] = g;
+    if (q == 0) {
+      if (G32) G32[e] = float(g);
+      if (G64) G64[e] = g;
+    }
   }
   for (int64_t e = tid; e < nslots; e += nblk * blockDim.x)
     slots[e] = __longlong_as_double(-1ll);

@@ -52,7 +52,7 @@ hipError_t launch_gram_partials(const GramJob& job, int r, hipStream_t s) {
 
 hipError_t launch_hadamard(const HadamardJob& job, int r, float* G32, double* G64,
                            double* slots, int64_t nslots, hipStream_t s) {
-  const int64_t work = std::max<int64_t>(int64_t(r) * r, nslots);
+  const int64_t work = std::max<int64_t>(4 * int64_t(r) * r, nslots);  // four threads per entry
   const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(ceil_div(work, 256), 1024)));
   hipLaunchKernelGGL(hadamard_kernel, dim3(blocks), dim3(256), 0, s, job, r, G32, G64, slots,
                      nslots);

@@ -1016,16 +1016,18 @@ __global__ __launch_bounds__(256) void mttkrp_reduce_kernel(const float* __restr
     const int64_t e = e0 + o;
     double acc = 0.0;
     if (e < n) {
-      // splits g, g + 4, ... in order; sixteen loads in flight (clamped, no branch per load)
-      for (int64_t q0 = g; q0 < splits; q0 += 64) {
+      // splits g, g + 4, ... in order: sixteen loads in flight (clamped, no branch per load)
+      // while at least sixteen remain, then the rest one by one (few splits: no repeated
+      // loads of the last one)
+      int64_t q0 = g;
+      for (; q0 + 60 < splits; q0 += 64) {
         float v[16];
 #pragma unroll
-        for (int t = 0; t < 16; ++t)
-          v[t] = part[std::min<int64_t>(q0 + 4 * t, splits - 1) * n + e];
+        for (int t = 0; t < 16; ++t) v[t] = part[(q0 + 4 * t) * n + e];
 #pragma unroll
-        for (int t = 0; t < 16; ++t)
-          if (q0 + 4 * t < splits) acc += double(v[t]);
+        for (int t = 0; t < 16; ++t) acc += double(v[t]);
       }
+      for (; q0 < splits; q0 += 4) acc += double(part[q0 * n + e]);
     }
     s[g][o] = acc;
     __syncthreads();
@@ -1075,15 +1077,16 @@ __global__ __launch_bounds__(256) void fold_u_kernel(const float* __restrict__ Y
 }
 
 // fold_i: workgroup (u tile of 256 / r' outputs, i range); partial[split][u][p].
-// With a Hadamard job, the first row of blocks (blockIdx.y == 0) computes it instead.
+// With a Hadamard job, the first `has_had` rows of blocks compute it instead (enough
+// blocks for four threads per entry of G).
 __global__ __launch_bounds__(256) void fold_i_kernel(const float* __restrict__ Y,
                                                      const float* __restrict__ X, int64_t I,
                                                      int64_t U, int r, int64_t per,
                                                      float* __restrict__ part, int has_had,
                                                      HadamardLaunch had) {
-  if (has_had && blockIdx.y == 0) {
-    hadamard_work(had.job, had.r, had.G32, had.G64, had.slots, had.nslots, blockIdx.x,
-                  gridDim.x);
+  if (int(blockIdx.y) < has_had) {
+    hadamard_work(had.job, had.r, had.G32, had.G64, had.slots, had.nslots,
+                  int64_t(blockIdx.y) * gridDim.x + blockIdx.x, int64_t(has_had) * gridDim.x);
     return;
   }
   const int64_t n = U * r;
@@ -1343,7 +1346,7 @@ static hipError_t launch_slab(const MttkrpPlan& pl, const void* T, const FactorP
                               const HadamardLaunch* had) {
   SArgs k{};
   if (had) {
-    k.nh = kHadamardBlocks;
+    k.nh = hadamard_blocks(had->r);
     k.had = *had;
   }
   const int N = pl.v.order;
@@ -1395,7 +1398,7 @@ hipError_t launch_mttkrp(const MttkrpPlan& pl, const void* T, const FactorPtrs& 
   KArgs k{};
   if (pl.slab) return launch_slab(pl, T, A, P, partials, reduce, s, had);
   if (had) {
-    k.nh = kHadamardBlocks;
+    k.nh = hadamard_blocks(had->r);
     k.had = *had;
   }
   k.ystore = pl.store_y ? ystore : nullptr;
@@ -1542,11 +1545,13 @@ hipError_t launch_fold_i(const float* Y, const float* X, int64_t I, int64_t U, i
   const int64_t splits = fold_i_splits(I, U, r);
   const int64_t per = ceil_div(I, splits);
   const int64_t n = U * r;
-  const int has_had = had ? 1 : 0;
+  const int64_t gx = ceil_div(n, 256);
+  // rows of Hadamard blocks: four threads per entry of the r x r product
+  const int has_had =
+      had ? int(ceil_div(ceil_div(4 * int64_t(had->r) * had->r, int64_t(256)), gx)) : 0;
   HadamardLaunch h{};
   if (had) h = *had;
-  hipLaunchKernelGGL(fold_i_kernel,
-                     dim3(unsigned(ceil_div(n, 256)), unsigned(splits + has_had)), dim3(256),
+  hipLaunchKernelGGL(fold_i_kernel, dim3(unsigned(gx), unsigned(splits + has_had)), dim3(256),
                      0, s, Y, X, I, U, r, per, partials, has_had, h);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -239,7 +239,7 @@ struct HadamardJob {
 };
 hipError_t launch_hadamard(const HadamardJob& job, int r, float* G32, double* G64,
                            double* slots, int64_t nslots, hipStream_t s);
-// The same work done by kHadamardBlocks leading workgroups of another launch (the MTTKRP
+// The same work done by hadamard_blocks(r) leading workgroups of another launch (the MTTKRP
 // or fold that precedes the A-HALS launch needing G), which saves a launch per block.
 struct HadamardLaunch {
   HadamardJob job;
@@ -249,7 +249,9 @@ struct HadamardLaunch {
   double* slots;
   int64_t nslots;
 };
-constexpr int kHadamardBlocks = 8;  // a multiple of 8 keeps the XCD dealing of the rest
+// leading workgroups of a launch that compute the Hadamard product: a multiple of 8 keeps
+// the XCD dealing of the rest; more for large r (r^2 entries, four threads each)
+inline int hadamard_blocks(int r) { return r <= 32 ? 8 : 32; }
 
 // A-HALS on one block. `slots` holds hals_slot_count(rows, r, max_sweeps) doubles that
 // are set to the sentinel (launch_fill_sentinel or launch_hadamard) before the call.

@@ -43,6 +43,21 @@ struct SolveGraph {
 
 namespace {
 
+// 4-way tensors: two tensor passes per outer iteration instead of four. With the block
+// order of Algorithm 2 the first two blocks see A-hat^(3), A-hat^(4) of the previous
+// iteration and the last two see A-hat^(1), A-hat^(2) of this one, so
+//   W = T x_3 A-hat^(3) x_4 A-hat^(4)  (the mode-1 MTTKRP of the (I_1 I_2) x I_3 x I_4 view)
+//   V = T x_1 A-hat^(1) x_2 A-hat^(2)  (the mode-3 MTTKRP of the I_1 x I_2 x (I_3 I_4) view)
+// give every block's MTTKRP by one fold: P^(1) = sum_j W[i, j] A^(2)[j], P^(2) = sum_i
+// A-hat^(1)[i] W[i, j], P^(3) = sum_l V[k, l] A^(4)[l], P^(4) = sum_k A-hat^(3)[k] V[k, l]
+// (equal to the four MTTKRPs up to summation order). Used when W and V are small next to
+// the tensor.
+struct PairPlans {
+  bool on = false;
+  ntf_tensor tw{}, tv{};  // the two 3-way views of T
+  MttkrpPlan pw, pv;
+};
+
 // Device buffers of one solve, carved from the handle's workspace.
 struct SolveBufs {
   double* norm_part;
@@ -59,6 +74,8 @@ struct SolveBufs {
   float* P;
   float* mt_part;
   float* Y;  // 3-way: Y = T x_3 A_3 (I_1 x I_2 x r), shared by the mode-1 and mode-2 MTTKRPs
+  float* W4;  // 4-way: W (I_1 I_2 x r) and V (I_3 I_4 x r), see PairPlans
+  float* V4;
   double* slots;
   int64_t nslots;
   int32_t* sweeps;
@@ -78,7 +95,8 @@ struct SolveBufs {
 };
 
 void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
-           const MttkrpPlan* plans, bool own_state, bool shared_y, const TuckerDesc* tk) {
+           const MttkrpPlan* plans, bool own_state, bool shared_y, const TuckerDesc* tk,
+           const PairPlans& pp) {
   const int N = T.order;
   const size_t rr = size_t(r) * r;
   b.norm_part = ar.take<double>(norm2_partials());
@@ -106,6 +124,15 @@ void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
   if (shared_y)
     maxpart = std::max<size_t>(
         maxpart, size_t(fold_i_splits(T.dims[0], T.dims[1], r)) * T.dims[1] * r);
+  if (pp.on) {
+    maxpart = std::max({maxpart, pp.pw.partial_floats(), pp.pv.partial_floats(),
+                        size_t(fold_i_splits(T.dims[0], T.dims[1], r)) * T.dims[1] * r,
+                        size_t(fold_i_splits(T.dims[2], T.dims[3], r)) * T.dims[3] * r});
+    b.W4 = ar.take<float>(size_t(T.dims[0]) * T.dims[1] * r);
+    b.V4 = ar.take<float>(size_t(T.dims[2]) * T.dims[3] * r);
+  } else {
+    b.W4 = b.V4 = nullptr;
+  }
   b.mt_part = ar.take<float>(std::max<size_t>(maxpart, 1));
   // (+64: padding that out-of-range stores of the Y kernel write to)
   b.Y = shared_y ? ar.take<float>(size_t(T.dims[0]) * T.dims[1] * r + 64) : nullptr;
@@ -177,7 +204,8 @@ bool fused_hals(ntf_handle* h, const ntf_her_params& p, int64_t rows, int r) {
 hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* const* A,
                              const ntf_her_params& p, const SolveBufs& b,
                              const MttkrpPlan* plans, const MttkrpPlan* plan_y,
-                             const ntf_trace& trace, hipStream_t s, const TuckerDesc* tk) {
+                             const ntf_trace& trace, hipStream_t s, const TuckerDesc* tk,
+                             const PairPlans& pp) {
   const int N = T.order;
   hipError_t e;
   for (int n = 0; n < N; ++n) {
@@ -198,6 +226,30 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
       if ((e = tucker_mttkrp_into(*tk, n, r, factors_for(n, N, A, b), plans[n], b, s, &hl)) !=
           hipSuccess)
         return e;
+    } else if (pp.on) {
+      // W (before block 1) and V (before block 3), each folded twice
+      float* WV = n < 2 ? b.W4 : b.V4;
+      const int64_t Ia = n < 2 ? T.dims[0] : T.dims[2];
+      const int64_t Ib = n < 2 ? T.dims[1] : T.dims[3];
+      if (n == 0 || n == 2) {
+        FactorPtrs fv{};
+        if (n == 0) {
+          fv.p[0] = A[2];  // not read (the row mode of the view)
+          fv.p[1] = A[2];
+          fv.p[2] = A[3];
+        } else {
+          fv.p[0] = b.A_hat[0];
+          fv.p[1] = b.A_hat[1];
+          fv.p[2] = b.A_hat[1];  // not read
+        }
+        if ((e = launch_mttkrp(n == 0 ? pp.pw : pp.pv, T.data, fv, WV, b.mt_part, true, s,
+                               nullptr, &hl)) != hipSuccess)
+          return e;
+        if ((e = launch_fold_u(WV, A[n + 1], Ia, Ib, r, b.P, s)) != hipSuccess) return e;
+      } else if ((e = launch_fold_i(WV, b.A_hat[n - 1], Ia, Ib, r, b.mt_part, b.P, s, &hl)) !=
+                 hipSuccess) {
+        return e;
+      }
     } else if (b.Y && n == 0) {
       if ((e = launch_mttkrp(*plan_y, T.data, factors_for(0, N, A, b), b.P, b.mt_part, true, s,
                              b.Y, &hl)) != hipSuccess)
@@ -332,6 +384,34 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
 // 3-way tensors: the mode-1 and mode-2 MTTKRPs share Y = T x_3 A-hat^(3) (A-hat^(3) does not
 // change before the mode-3 update), so the tensor is streamed twice per iteration instead of
 // three times. Used when Y is smaller than the tensor and A_3 fits one LDS block.
+// The two 3-way views of a 4-way tensor and their MTTKRP plans, when W and V are each at
+// most an eighth of the tensor's bytes.
+PairPlans plan_pairs(const ntf_tensor& T, int r, int num_cus) {
+  PairPlans pp;
+  if (T.order != 4) return pp;
+  const int64_t s = T.dtype == NTF_BF16 ? 2 : 4;
+  int64_t n_all = 1;
+  for (int l = 0; l < 4; ++l) n_all *= T.dims[l];
+  const int64_t w = T.dims[0] * T.dims[1], v = T.dims[2] * T.dims[3];
+  if (8 * w * r * 4 > n_all * s || 8 * v * r * 4 > n_all * s) return pp;
+  if (w > (int64_t(1) << 31) - 1 || v > (int64_t(1) << 31) - 1) return pp;
+  pp.tw = T;
+  pp.tw.order = 3;
+  pp.tw.dims[0] = w;
+  pp.tw.dims[1] = T.dims[2];
+  pp.tw.dims[2] = T.dims[3];
+  pp.tv = T;
+  pp.tv.order = 3;
+  pp.tv.dims[0] = T.dims[0];
+  pp.tv.dims[1] = T.dims[1];
+  pp.tv.dims[2] = v;
+  for (int l = 3; l < kMaxOrder; ++l) pp.tw.dims[l] = pp.tv.dims[l] = 1;
+  pp.pw = plan_mttkrp(pp.tw, 0, r, num_cus, false);
+  pp.pv = plan_mttkrp(pp.tv, 2, r, num_cus, false);
+  pp.on = pp.pw.chunks < (int64_t(1) << 31) && pp.pv.chunks < (int64_t(1) << 31);
+  return pp;
+}
+
 bool use_shared_y(const ntf_tensor& T, int r, const MttkrpPlan& plan_y) {
   if (T.order != 3 || plan_y.nvb != 1) return false;
   const int64_t s = T.dtype == NTF_BF16 ? 2 : 4;
@@ -413,10 +493,11 @@ static ntf_status solve_impl(ntf_handle* h, const ntf_tensor* T, const TuckerDes
 
   Arena dry;
   SolveBufs b{};
-  carve(dry, b, *T, r, params->max_inner, plans, state == nullptr, shared_y, tk);
+  const PairPlans pp = tk ? PairPlans{} : plan_pairs(*T, r, h->num_cus);
+  carve(dry, b, *T, r, params->max_inner, plans, state == nullptr, shared_y, tk, pp);
   if ((st = ensure_workspace(h, dry.off + 256))) return st;
   Arena ar{h->ws, 0};
-  carve(ar, b, *T, r, params->max_inner, plans, state == nullptr, shared_y, tk);
+  carve(ar, b, *T, r, params->max_inner, plans, state == nullptr, shared_y, tk, pp);
   if (state) b.state = state;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -483,7 +564,7 @@ static ntf_status solve_impl(ntf_handle* h, const ntf_tensor* T, const TuckerDes
     g->key = key;
     NTF_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed));
     hipError_t e = enqueue_iteration(h, *T, r, A, *params, b, plans, &plan_y, tr,
-                                     h->capture_stream, tk);
+                                     h->capture_stream, tk, pp);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(h->capture_stream, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {

@@ -41,7 +41,10 @@ def _fit(T64, A):
 
 @pytest.mark.parametrize("dims,r,seed", [((12, 10, 8), 3, 0), ((30, 20, 25), 5, 1),
                                          ((9, 8, 7, 6), 3, 2), ((40, 35), 4, 3),
-                                         ((16, 14, 12, 10), 40, 11)])
+                                         ((16, 14, 12, 10), 40, 11),
+                                         # 4-way with small (I1 I2 x r) and (I3 I4 x r):
+                                         # two tensor passes per iteration (W and V)
+                                         ((20, 18, 30, 34), 5, 12), ((33, 7, 16, 40), 8, 13)])
 def test_small_problem_trajectory_and_fit(ntf, dims, r, seed):
     pr = synth.make_problem(dims, r, snr_db=30.0, data_seed=seed, init_seed=seed + 50)
     T32 = pr.T.astype(np.float32)
@@ -110,4 +113,30 @@ def test_bf16_tensor_solve_reaches_oracle_fit(ntf):
     ref = oracle.her_solve(T64, [a.astype(np.float64) for a in A0], 60)
     f_gpu, f_ref = _fit(T64, A_gpu), _fit(T64, ref.factors)
     print(f"bf16 fit gpu={f_gpu:.6f} oracle={f_ref:.6f}")
+    assert abs(f_gpu - f_ref) <= 1e-3 * f_ref
+
+
+def test_four_way_bf16_two_pass_trajectory(ntf):
+    """A bf16 4-way tensor on the two-pass path against the oracle on its bf16 values."""
+    pr = synth.make_problem((24, 20, 32, 36), 6, snr_db=30.0, data_seed=14, init_seed=15)
+    A0 = [a.astype(np.float32) for a in pr.A0]
+    A_gpu, tr, st, Tq = _run_gpu(ntf, pr.T.astype(np.float32), A0, 30, dtype="bf16")
+    ref = oracle.her_solve(Tq, [a.astype(np.float64) for a in A0], 30)
+    # F-hat is a difference of terms of size ||T||^2, 7e3 times F-hat here: float32 rounding
+    # of the MTTKRP moves it by about u ||T||^2 (u = 2^-24), so the tolerance is
+    # 1e-4 |F-hat| + 8 u ||T||^2, and decisions are compared while F-hat moves by more
+    normT2 = float(np.sum(Tq * Tq))
+    prev = ref.fhat0
+    checked = 0
+    for k in range(30):
+        tol = 1e-4 * abs(ref.fhat[k]) + 2.0 ** -21 * normT2
+        if abs(ref.fhat[k] - prev) < 2 * tol:
+            break
+        assert bool(tr["restart"][k]) == ref.restart[k], k
+        assert abs(tr["fhat"][k] - ref.fhat[k]) <= tol, (k, tr["fhat"][k], ref.fhat[k])
+        prev = ref.fhat[k]
+        checked += 1
+    f_gpu, f_ref = _fit(Tq, A_gpu), _fit(Tq, ref.factors)
+    print(f"4-way bf16 checked {checked} fit gpu={f_gpu:.6f} oracle={f_ref:.6f}")
+    assert checked >= 3
     assert abs(f_gpu - f_ref) <= 1e-3 * f_ref
