@@ -392,15 +392,16 @@ typedef struct ntf_problem {
 } ntf_problem;
 
 /* Algorithm 2 (HER with A-HALS blocks, Sec. 3.1) for `nprob` independent 3-way float32
- * problems of any shapes and ranks, `iters` outer iterations each, in ONE persistent
- * launch: a workgroup owns a problem for all iterations (problems larger in I_1 I_2 I_3 r
- * start first). Per problem the results equal those of ntf_solve up to rounding order
- * (same method, parameters and F-hat_0 = F(A_0)); restart decisions may differ where
- * rounding decides them. probs: host array; all pointers inside are device pointers.
- * resume != 0 continues from each problem's state and factors. The launch is captured
- * into a HIP graph and replayed while the problem set and parameters are unchanged. The
- * host descriptors are copied from pinned staging: the call waits until the previous
- * call's copy has completed. */
+ * problems of any shapes and ranks, `iters` outer iterations each. One outer iteration of
+ * every problem is a short sequence of grouped launches (the tensor passes and folds split
+ * each problem into many workgroups; each A-HALS block takes one workgroup per problem,
+ * larger problems first), captured once into a HIP graph and replayed `iters` times while
+ * the problem set and parameters are unchanged. Per problem the results equal those of
+ * ntf_solve up to rounding order (same method, parameters and F-hat_0 = F(A_0)); restart
+ * decisions may differ where rounding decides them. probs: host array; all pointers
+ * inside are device pointers. resume != 0 continues from each problem's state and
+ * factors. The host descriptors and work lists are copied from pinned staging: the call
+ * waits until the previous call's copy has completed. */
 ntf_status ntf_solve_batched(ntf_handle* h, int32_t nprob, const ntf_problem* probs,
                              const ntf_her_params* params, int32_t iters, int32_t resume,
                              void* stream);

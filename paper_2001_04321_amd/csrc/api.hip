@@ -812,7 +812,23 @@ ntf_status solve_batched_impl(ntf_handle* h, int32_t nprob, const ntf_problem* p
     ws_bytes = align_up(ws_bytes, 256) + batched_problem_bytes(d.I, d.rb);
     cost[size_t(b)] = int64_t(d.I[0]) * d.I[1] * d.I[2] * d.rb;
   }
-  const size_t desc_bytes = batched_desc_bytes(nprob);
+  // largest problems first, so the per-problem launches start the long ones early
+  std::vector<int32_t> order(static_cast<size_t>(nprob));
+  for (int b = 0; b < nprob; ++b) order[size_t(b)] = b;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return cost[size_t(x)] > cost[size_t(y)]; });
+  BatchedJob job{};
+  job.probs = bp.data();
+  job.order = order.data();
+  job.nprob = nprob;
+  job.resume = resume ? 1 : 0;
+  job.params = *params;
+  job.flags = h->dev_flags;
+  const BatchedPlan pl = batched_plan(job);
+  NTF_RETURN_IF(pl.lds_y > 150 * 1024 || pl.lds_last > 150 * 1024 || pl.lds_hals > 128 * 1024,
+                NTF_EUNSUPPORTED, "problem set needs %zu bytes of LDS",
+                std::max({pl.lds_y, pl.lds_last, pl.lds_hals}));
+  const size_t desc_bytes = pl.bytes;
   const size_t need = align_up(desc_bytes, 256) + ws_bytes;
   hipStream_t s = as_stream(stream);
   if (need > h->bws_size) {
@@ -848,65 +864,62 @@ ntf_status solve_batched_impl(ntf_handle* h, int32_t nprob, const ntf_problem* p
     bp[size_t(b)].ws = h->bws + off;
     off += batched_problem_bytes(bp[size_t(b)].I, bp[size_t(b)].rb);
   }
-  // largest problems first, so a grid wider than the device starts the long ones early
-  std::vector<int32_t> order(static_cast<size_t>(nprob));
-  for (int b = 0; b < nprob; ++b) order[size_t(b)] = b;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t x, int32_t y) { return cost[size_t(x)] > cost[size_t(y)]; });
-  BatchedJob job{};
-  job.probs = bp.data();
-  job.order = order.data();
-  job.nprob = nprob;
-  job.iters = iters;
-  job.resume = resume ? 1 : 0;
-  job.params = *params;
   job.host_desc = h->bstage;
   job.dev_desc = h->bws;
-  job.flags = h->dev_flags;
-  size_t lds = 0;
-  NTF_HIP(batched_upload(job, &lds, s));
+  NTF_HIP(batched_upload(job, pl, s));
   NTF_HIP(hipEventRecord(h->bstage_done, s));
-  NTF_RETURN_IF(lds > 150 * 1024, NTF_EUNSUPPORTED, "problem set needs %zu bytes of LDS", lds);
-  // the persistent launch is captured once into a graph and replayed while its
-  // arguments are unchanged
-  unsigned char key[sizeof(h->bgraph_key)] = {};
-  {
-    struct K {
-      void* ws;
-      int nprob, iters, resume, pad;
-      ntf_her_params p;
-      size_t lds;
-      uint32_t* flags;
-    } k{};
-    k.ws = h->bws;
-    k.nprob = nprob;
-    k.iters = iters;
-    k.resume = job.resume;
-    k.p = *params;
-    k.lds = lds;
-    k.flags = h->dev_flags;
-    static_assert(sizeof(K) <= sizeof(key), "graph key too small");
-    std::memcpy(key, &k, sizeof(K));
-  }
-  if (!h->bgraph || std::memcmp(key, h->bgraph_key, sizeof(key)) != 0) {
-    if (h->bgraph) {
-      NTF_HIP(hipStreamSynchronize(s));
-      (void)hipGraphExecDestroy(h->bgraph);
-      h->bgraph = nullptr;
+  NTF_HIP(batched_setup(job, pl, s));
+  if (iters > 0) {
+    // one outer iteration of every problem (a few grouped launches) is captured once into
+    // a graph and replayed while the problem set and parameters are unchanged
+    unsigned char key[sizeof(h->bgraph_key)] = {};
+    {
+      struct K {
+        void* ws;
+        int nprob, resume;
+        ntf_her_params p;
+        int64_t n_y, n_fu, n_fi, n_last, n_sum;
+        size_t lds_y, lds_last, lds_hals;
+        uint32_t* flags;
+      } k{};
+      k.ws = h->bws;
+      k.nprob = nprob;
+      k.resume = job.resume;
+      k.p = *params;
+      k.n_y = pl.n_y;
+      k.n_fu = pl.n_fu;
+      k.n_fi = pl.n_fi;
+      k.n_last = pl.n_last;
+      k.n_sum = pl.n_sum;
+      k.lds_y = pl.lds_y;
+      k.lds_last = pl.lds_last;
+      k.lds_hals = pl.lds_hals;
+      k.flags = h->dev_flags;
+      static_assert(sizeof(K) <= sizeof(key), "graph key too small");
+      std::memcpy(key, &k, sizeof(K));
     }
-    if (!h->capture_stream) NTF_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
-    hipGraph_t g = nullptr;
-    NTF_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed));
-    const hipError_t le = batched_launch(job, lds, h->capture_stream);
-    const hipError_t ce = hipStreamEndCapture(h->capture_stream, &g);
-    NTF_HIP(le);
-    NTF_HIP(ce);
-    const hipError_t ie = hipGraphInstantiate(&h->bgraph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    NTF_HIP(ie);
-    std::memcpy(h->bgraph_key, key, sizeof(key));
+    if (!h->bgraph || std::memcmp(key, h->bgraph_key, sizeof(key)) != 0) {
+      if (h->bgraph) {
+        NTF_HIP(hipStreamSynchronize(s));
+        (void)hipGraphExecDestroy(h->bgraph);
+        h->bgraph = nullptr;
+      }
+      if (!h->capture_stream)
+        NTF_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      NTF_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed));
+      const hipError_t le = batched_iteration(job, pl, h->capture_stream);
+      const hipError_t ce = hipStreamEndCapture(h->capture_stream, &g);
+      NTF_HIP(le);
+      NTF_HIP(ce);
+      const hipError_t ie = hipGraphInstantiate(&h->bgraph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      NTF_HIP(ie);
+      std::memcpy(h->bgraph_key, key, sizeof(key));
+    }
+    for (int k = 0; k < iters; ++k) NTF_HIP(hipGraphLaunch(h->bgraph, s));
   }
-  NTF_HIP(hipGraphLaunch(h->bgraph, s));
+  NTF_HIP(batched_final(job, pl, s));
   return NTF_OK;
 }
 }  // namespace

@@ -415,7 +415,8 @@ hipError_t launch_select(const SelectJob& j, const ntf_her_state* st, hipStream_
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s);
 hipError_t launch_reset_call(ntf_her_state* st, hipStream_t s);
 
-// Batched solver (one workgroup per 3-way float32 problem, all iterations in one launch).
+// Batched solver (many 3-way float32 problems; each outer iteration of all problems is a
+// short sequence of grouped launches, captured once into a graph).
 constexpr int kBatchedMaxDim = 256;
 constexpr int kBatchedMaxRank = 32;
 constexpr size_t kBatchedDescBytes = 512;
@@ -434,18 +435,24 @@ struct BatchedJob {
   const BatchedProblem* probs;
   const int32_t* order;  // host: processing order (largest first)
   int nprob;
-  int iters;
   int resume;
   ntf_her_params params;
-  void* host_desc;       // pinned, batched_desc_bytes(nprob)
-  void* dev_desc;        // device, batched_desc_bytes(nprob)
+  void* host_desc;       // pinned, batched_plan(job).bytes
+  void* dev_desc;        // device, the same size
   uint32_t* flags;
 };
+// Layout of the descriptor area (descriptors, order, work-item lists) and launch sizes.
+struct BatchedPlan {
+  size_t off_order, off_y, off_fu, off_fi, off_last, off_sum, bytes;
+  int64_t n_y, n_fu, n_fi, n_last, n_sum;  // work items of the grouped launches
+  size_t lds_y, lds_last, lds_hals;
+};
 size_t batched_problem_bytes(const int I[3], int rb);
-size_t batched_lds_bytes(int I0, int I1, int I2, int rb);
-size_t batched_desc_bytes(int nprob);
-hipError_t batched_upload(const BatchedJob& job, size_t* lds_out, hipStream_t s);
-hipError_t batched_launch(const BatchedJob& job, size_t lds, hipStream_t s);
+BatchedPlan batched_plan(const BatchedJob& job);
+hipError_t batched_upload(const BatchedJob& job, const BatchedPlan& pl, hipStream_t s);
+hipError_t batched_setup(const BatchedJob& job, const BatchedPlan& pl, hipStream_t s);
+hipError_t batched_iteration(const BatchedJob& job, const BatchedPlan& pl, hipStream_t s);
+hipError_t batched_final(const BatchedJob& job, const BatchedPlan& pl, hipStream_t s);
 
 // || T - [[A]] ||^2 (explicit residual, float64).
 int residual_partials();

@@ -35,10 +35,15 @@ struct SolveKey {
   bool operator==(const SolveKey& o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
 };
 
+// One outer iteration, and kGraphUnroll iterations back to back (consecutive graph launches
+// leave a gap of several microseconds between them, which the longer graph amortizes).
+constexpr int kGraphUnroll = 4;
 struct SolveGraph {
   SolveKey key;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipGraph_t graph_u = nullptr;
+  hipGraphExec_t exec_u = nullptr;
 };
 
 namespace {
@@ -423,6 +428,8 @@ void release_solve_graph(ntf_handle* h) {
   if (!h->graph) return;
   if (h->graph->exec) (void)hipGraphExecDestroy(h->graph->exec);
   if (h->graph->graph) (void)hipGraphDestroy(h->graph->graph);
+  if (h->graph->exec_u) (void)hipGraphExecDestroy(h->graph->exec_u);
+  if (h->graph->graph_u) (void)hipGraphDestroy(h->graph->graph_u);
   delete h->graph;
   h->graph = nullptr;
 }
@@ -562,28 +569,41 @@ static ntf_status solve_impl(ntf_handle* h, const ntf_tensor* T, const TuckerDes
     release_solve_graph(h);
     SolveGraph* g = new SolveGraph();
     g->key = key;
-    NTF_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed));
-    hipError_t e = enqueue_iteration(h, *T, r, A, *params, b, plans, &plan_y, tr,
-                                     h->capture_stream, tk, pp);
-    hipGraph_t graph = nullptr;
-    hipError_t e2 = hipStreamEndCapture(h->capture_stream, &graph);
-    if (e != hipSuccess || e2 != hipSuccess) {
-      if (graph) (void)hipGraphDestroy(graph);
-      delete g;
-      set_error("graph capture failed: %s / %s", hipGetErrorString(e), hipGetErrorString(e2));
-      return NTF_EDEVICE;
+    // capture n iterations into (graph, exec)
+    auto capture = [&](int n, hipGraph_t* graph_out, hipGraphExec_t* exec_out) -> ntf_status {
+      NTF_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed));
+      hipError_t e = hipSuccess;
+      for (int k = 0; k < n && e == hipSuccess; ++k)
+        e = enqueue_iteration(h, *T, r, A, *params, b, plans, &plan_y, tr, h->capture_stream,
+                              tk, pp);
+      hipGraph_t graph = nullptr;
+      hipError_t e2 = hipStreamEndCapture(h->capture_stream, &graph);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        set_error("graph capture failed: %s / %s", hipGetErrorString(e), hipGetErrorString(e2));
+        return NTF_EDEVICE;
+      }
+      hipError_t e3 = hipGraphInstantiate(exec_out, graph, nullptr, nullptr, 0);
+      if (e3 != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        set_error("graph instantiate failed: %s", hipGetErrorString(e3));
+        return NTF_EDEVICE;
+      }
+      *graph_out = graph;
+      return NTF_OK;
+    };
+    h->graph = g;  // released (both graphs) by release_solve_graph on failure below
+    ntf_status cs = capture(1, &g->graph, &g->exec);
+    if (cs == NTF_OK) cs = capture(kGraphUnroll, &g->graph_u, &g->exec_u);
+    if (cs != NTF_OK) {
+      release_solve_graph(h);
+      return cs;
     }
-    g->graph = graph;
-    hipError_t e3 = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
-    if (e3 != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      delete g;
-      set_error("graph instantiate failed: %s", hipGetErrorString(e3));
-      return NTF_EDEVICE;
-    }
-    h->graph = g;
   }
-  for (int k = 0; k < iters; ++k) NTF_HIP(hipGraphLaunch(h->graph->exec, s));
+  int k = 0;
+  for (; k + kGraphUnroll <= iters; k += kGraphUnroll)
+    NTF_HIP(hipGraphLaunch(h->graph->exec_u, s));
+  for (; k < iters; ++k) NTF_HIP(hipGraphLaunch(h->graph->exec, s));
   return NTF_OK;
 }
 

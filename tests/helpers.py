@@ -54,3 +54,22 @@ def dev_tensor(T, dtype: str):
 def to_np(t):
     return t.detach().cpu().double().numpy()
 
+
+
+def check_trajectory(fhat, restart, ref, iters, normT2) -> int:
+    """Compare a device run's F-hat and restart decisions with the oracle's (`ref`, an
+    oracle.her_solve result) while F-hat moves by more than twice the tolerance; returns
+    the number of iterations compared. F-hat = ||T||^2 / 2 - <P, A> + <G, A^T A> / 2 is a
+    small difference of terms of size ||T||^2, so float32 rounding of the MTTKRP alone moves
+    it by about u ||T||^2 (u = 2^-24): the tolerance is 1e-4 |F-hat| + 8 u ||T||^2."""
+    prev = ref.fhat0
+    checked = 0
+    for k in range(iters):
+        tol = 1e-4 * abs(ref.fhat[k]) + 2.0 ** -21 * normT2
+        if abs(ref.fhat[k] - prev) < 2 * tol:
+            break
+        assert bool(restart[k]) == ref.restart[k], k
+        assert abs(fhat[k] - ref.fhat[k]) <= tol, (k, fhat[k], ref.fhat[k], tol)
+        prev = ref.fhat[k]
+        checked += 1
+    return checked

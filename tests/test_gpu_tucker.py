@@ -8,7 +8,7 @@ on identical float32 inputs, and the row-parallel A-HALS blocks that large modes
 * ntf_tucker_norm2: float64 throughout, 1e-12 relative to the oracle (also for bases without
   orthonormal columns, where it is not ||G||^2).
 * ntf_solve_tucker: decisions and F-hat while F-hat moves by far more than float32
-  rounding (1e-4 |F-hat| + 8 u ||T||^2, see _check_trajectory), and the final fit (by the format's own residual norm, oracle.tucker_relative_
+  rounding (1e-4 |F-hat| + 8 u ||T||^2, tests.helpers.check_trajectory), and the final fit (by the format's own residual norm, oracle.tucker_relative_
   error, on the host) within 1e-3 relative of the oracle's; the 153 x 238 x 14000 video-
   shaped workload against its stored oracle fit.
 * Modes with more rows than the resident A-HALS kernel holds (more than 12288 rows for
@@ -22,7 +22,8 @@ import pytest
 
 import oracle
 import synth
-from tests.helpers import ROOT, dev_f32, dev_tensor, elementwise_err, ensure_built, to_np
+from tests.helpers import (ROOT, check_trajectory, dev_f32, dev_tensor, elementwise_err,
+                           ensure_built, to_np)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -54,22 +55,7 @@ def _random_tucker(seed, dims, ranks, orthonormal):
 
 
 def _check_trajectory(tr, ref, iters, normT2):
-    """F-hat and the restart decisions while F-hat moves by more than twice the tolerance.
-    F-hat = ||T||^2 / 2 - <P, A> + <G, A^T A> / 2 is a small difference of terms of size
-    ||T||^2 (30 dB: F-hat is about 1e-3 ||T||^2 near the fit), so the float32 MTTKRP's
-    rounding alone moves it by about u ||T||^2 (u = 2^-24): the tolerance is
-    1e-4 |F-hat| + 8 u ||T||^2."""
-    prev = ref.fhat0
-    checked = 0
-    for k in range(iters):
-        tol = 1e-4 * abs(ref.fhat[k]) + 2.0 ** -21 * normT2
-        if abs(ref.fhat[k] - prev) < 2 * tol:
-            break
-        assert bool(tr["restart"][k]) == ref.restart[k], k
-        assert abs(tr["fhat"][k] - ref.fhat[k]) <= tol, (k, tr["fhat"][k], ref.fhat[k], tol)
-        prev = ref.fhat[k]
-        checked += 1
-    return checked
+    return check_trajectory(tr["fhat"], tr["restart"], ref, iters, normT2)
 
 
 @pytest.mark.parametrize("dims,ranks,r,orth", [
