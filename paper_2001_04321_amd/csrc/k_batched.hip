@@ -395,15 +395,16 @@ __device__ int hals_rows(const float* __restrict__ W0, float* __restrict__ Wn,
 #pragma unroll
         for (int l4 = 0; l4 < RB / 4; ++l4) gb[(j + 1) & 1][l4] = G4[(j + 1) * (RB / 4) + l4];
       }
-      // four partial sums in a fixed pattern shorten the dependency chain
+      // four partial sums; the terms are taken in the order l = j, j + 1, ..., j - 1
+      // (cyclically), so the column updated last enters last and the chain from it to
+      // W_j is one multiply-add, the two adds and the max
       float acc[4] = {pinv[j], 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int l4 = 0; l4 < RB / 4; ++l4) {
-        const float4 g = gb[j & 1][l4];
-        acc[0] = fmaf(-w[4 * l4 + 0], g.x, acc[0]);
-        acc[1] = fmaf(-w[4 * l4 + 1], g.y, acc[1]);
-        acc[2] = fmaf(-w[4 * l4 + 2], g.z, acc[2]);
-        acc[3] = fmaf(-w[4 * l4 + 3], g.w, acc[3]);
+      for (int m = 0; m < RB; ++m) {
+        const int l = (j + m) % RB;
+        const float4 g4 = gb[j & 1][l / 4];
+        const float g = (l & 3) == 0 ? g4.x : (l & 3) == 1 ? g4.y : (l & 3) == 2 ? g4.z : g4.w;
+        acc[m & 3] = fmaf(-w[l], g, acc[m & 3]);
       }
       const float wn = fmaxf((acc[0] + acc[1]) + (acc[2] + acc[3]), 0.f);
       const double dd = double(wn) - double(w[j]);
