@@ -449,7 +449,7 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, out_path: str, command
 
 
 PROFILE_TARGETS = ("mttkrp-cube400", "mttkrp-quad128", "fused4-quad128", "solve-cube400",
-                   "hals-cube400", "solve-quad128")
+                   "hals-cube400", "solve-quad128", "solve-tucker", "batched")
 
 
 def profile_calls(ntf, torch, target: str, reps: int):
@@ -457,12 +457,26 @@ def profile_calls(ntf, torch, target: str, reps: int):
     shapes): `mttkrp-cube400` reps ntf_mttkrp calls per mode on the 400^3 tensor as bf16 and
     as float32, `mttkrp-quad128` the same on the 128^4 bf16 tensor, `fused4-quad128` reps
     four-mode ntf_mttkrp_multi calls on the 128^4 bf16 tensor, `solve-cube400` reps outer
-    iterations of the bf16 solver (`solve-quad128`: on the 128^4 bf16 tensor),
+    iterations of the bf16 solver (`solve-quad128`: on the 128^4 bf16 tensor;
+    `solve-tucker`: ntf_solve_tucker on the 153 x 238 x 14000 Tucker-format workload;
+    `batched`: the 256-problem batch for reps outer iterations),
     `hals-cube400` reps ntf_hals_update calls per mode
     (50 sweeps at most, tol 1e-2) from A_0 with the P (bf16 tensor) and G of A_0."""
     import numpy as np
 
     import synth
+    if target == "batched":
+        return {"target": target, "batched": bench_batched(ntf, torch, reps),
+                "device_flags": ntf.ntf_device_flags()}
+    if target == "solve-tucker":
+        pr = synth.tucker_workload("tucker_video_r10")
+        core = torch.from_numpy(pr.core.astype(np.float32)).cuda()
+        bases = [torch.from_numpy(U.astype(np.float32)).cuda() for U in pr.bases]
+        A = [torch.from_numpy(a.astype(np.float32)).cuda() for a in pr.A0]
+        ntf.ntf_solve_tucker(core, bases, A, reps, trace=False)
+        torch.cuda.synchronize()
+        return {"target": target, "workload": "tucker_video_r10", "reps": reps,
+                "device_flags": ntf.ntf_device_flags()}
     name = "cube400_r32_corr" if target.endswith("cube400") else "quad128_r64_sparse"
     pr = synth.workload(name)
     T32 = torch.from_numpy(pr.T.astype(np.float32)).cuda()

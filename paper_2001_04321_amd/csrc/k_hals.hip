@@ -278,10 +278,13 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
       align_up((size_t(RB) * RMAX + 2 * size_t(RPW) * r + size_t(R) * NR * C * kCT) * sizeof(float),
                16));
 
-  // setup: the loads of each batch are all in flight before any is used
+  // setup: the scaled G table and this workgroup's P block (rows row0 .. row0+nrows-1,
+  // contiguous in memory), in batches whose loads are all in flight before any is used;
+  // the first batches of both go out together
   constexpr int kB = 8;
-  for (int base = 0; base < RB * RMAX; base += kB * kThreads) {
-    float gv[kB], gd[kB];
+  const int np = nrows * r;
+  const float* Pb = a.P + row0 * r;
+  auto g_load = [&](int base, float (&gv)[kB], float (&gd)[kB]) {
 #pragma unroll
     for (int i = 0; i < kB; ++i) {
       const int e = base + i * kThreads + tid;
@@ -291,6 +294,8 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
       gv[i] = ok ? a.G[j * r + k] : 0.f;
       gd[i] = ok ? a.G[k * r + k] : 0.f;
     }
+  };
+  auto g_store = [&](int base, const float (&gv)[kB], const float (&gd)[kB]) {
 #pragma unroll
     for (int i = 0; i < kB; ++i) {
       const int e = base + i * kThreads + tid;
@@ -299,24 +304,37 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
       if (e < RB * RMAX)
         s_g[e] = gd[i] != 0.f ? (j == k ? -1.f : -(gv[i] * (1.f / gd[i]))) : 0.f;
     }
-  }
-  // P block of this workgroup: rows row0 .. row0+nrows-1 are contiguous in memory
-  {
-    const int n = nrows * r;
-    const float* Pb = a.P + row0 * r;
-    for (int base = 0; base < n; base += kB * kThreads) {
-      float pv[kB];
+  };
+  auto p_load = [&](int base, float (&pv)[kB]) {
 #pragma unroll
-      for (int i = 0; i < kB; ++i) {
-        const int e = base + i * kThreads + tid;
-        pv[i] = e < n ? Pb[e] : 0.f;
-      }
-#pragma unroll
-      for (int i = 0; i < kB; ++i) {
-        const int e = base + i * kThreads + tid;
-        if (e < n) s_rows[e] = pv[i];
-      }
+    for (int i = 0; i < kB; ++i) {
+      const int e = base + i * kThreads + tid;
+      pv[i] = e < np ? Pb[e] : 0.f;
     }
+  };
+  auto p_store = [&](int base, const float (&pv)[kB]) {
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      const int e = base + i * kThreads + tid;
+      if (e < np) s_rows[e] = pv[i];
+    }
+  };
+  {
+    float gv[kB], gd[kB], pv[kB];
+    g_load(0, gv, gd);
+    p_load(0, pv);
+    g_store(0, gv, gd);
+    p_store(0, pv);
+  }
+  for (int base = kB * kThreads; base < RB * RMAX; base += kB * kThreads) {
+    float gv[kB], gd[kB];
+    g_load(base, gv, gd);
+    g_store(base, gv, gd);
+  }
+  for (int base = kB * kThreads; base < np; base += kB * kThreads) {
+    float pv[kB];
+    p_load(base, pv);
+    p_store(base, pv);
   }
   for (int e = tid; e < K * kCT; e += kThreads) s_sh[e] = -1.0;  // every share slot empty
   __syncthreads();
