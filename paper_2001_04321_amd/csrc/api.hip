@@ -300,23 +300,28 @@ ntf_status ntf_tucker_mttkrp(ntf_handle* h, const ntf_tucker* X, const float* co
     NTF_RETURN_IF(l != mode && !A[l], NTF_EINVAL, "factor %d is NULL", l);
   const MttkrpPlan pl =
       plan_mttkrp(X->core, mode, r, h->num_cus, false, tuned_choice(h, X->core, mode, r));
+  size_t qp = 1;
+  for (int l = 0; l < N; ++l)
+    qp = std::max(qp, tucker_proj_part_doubles(X->dims[l], int(X->core.dims[l]), r));
   Arena dry;
   float* Q[kMaxOrder] = {};
   for (int l = 0; l < N; ++l) dry.take<float>(size_t(X->core.dims[l]) * r);
   dry.take<float>(size_t(X->core.dims[mode]) * r);
   dry.take<float>(std::max<size_t>(pl.partial_floats(), 1));
+  dry.take<double>(qp);
   if ((st = ensure_workspace(h, dry.off + 256))) return st;
   Arena ar{h->ws, 0};
   for (int l = 0; l < N; ++l) Q[l] = ar.take<float>(size_t(X->core.dims[l]) * r);
   float* Pc = ar.take<float>(size_t(X->core.dims[mode]) * r);
   float* part = ar.take<float>(std::max<size_t>(pl.partial_floats(), 1));
+  double* qpart = ar.take<double>(qp);
   hipStream_t s = as_stream(stream);
   FactorPtrs fq{};
   for (int l = 0; l < N; ++l) {
     fq.p[l] = Q[l];
     if (l != mode)
       NTF_HIP(launch_tucker_proj(X->U[l], A[l], X->dims[l], int(X->core.dims[l]), r, Q[l],
-                                 nullptr, s));
+                                 nullptr, qpart, s));
   }
   NTF_HIP(launch_mttkrp(pl, X->core.data, fq, Pc, part, true, s));
   NTF_HIP(launch_tucker_expand(X->U[mode], Pc, X->dims[mode], int(X->core.dims[mode]), r, P, s));

@@ -19,38 +19,60 @@ namespace {
 
 constexpr int kRowThreads = 256;
 
-template <int RMAX, int PASS>
+// RM columns per row in registers: RM = r (EXACT) or the next of 24, 32 (columns past r hold
+// zeros and are skipped; predicated, so the loops unroll and w stays in registers). G is in
+// LDS transposed, s_gt[j * RM + l] = G[l][j]; column j's terms are taken in the order
+// l = j + 1, ..., j - 1 (cyclically) over four partial sums, so the column updated last
+// enters last, and row j + 1 of s_gt is read while column j is updated.
+template <int RM, bool EXACT, int PASS>
 __global__ __launch_bounds__(kRowThreads) void hals_rows_kernel(HalsRowsArgs a) {
-  extern __shared__ float s_g[];  // r x r
+  __shared__ float s_gt[RM * RM];
   __shared__ double s_w[kHalsRowsMaxSweeps][kRowThreads / 64];
   const int t = threadIdx.x;
-  const int r = a.r;
-  for (int e = t; e < r * r; e += kRowThreads) s_g[e] = a.G[e];
+  const int r = EXACT ? RM : a.r;
+  for (int e = t; e < RM * RM; e += kRowThreads) {
+    const int j = e / RM, l = e - (e / RM) * RM;
+    s_gt[e] = (j < r && l < r) ? a.G[l * r + j] : 0.f;
+  }
   __syncthreads();
   const int64_t row = int64_t(blockIdx.x) * kRowThreads + t;
   const bool live = row < a.rows;
   const int64_t base = (live ? row : 0) * r;
-  float w[RMAX], pv[RMAX];
+  float w[RM], pv[RM];
 #pragma unroll
-  for (int j = 0; j < RMAX; ++j) {
-    const int jj = j < r ? j : 0;
+  for (int j = 0; j < RM; ++j) {
+    const bool in = EXACT || j < r;
+    const int jj = in ? j : 0;
     const float pw = a.P[base + jj], ww = a.W0[base + jj];
-    pv[j] = (live && j < r) ? pw : 0.f;
-    w[j] = (live && j < r) ? ww : 0.f;
+    pv[j] = (live && in) ? pw : 0.f;
+    w[j] = (live && in) ? ww : 0.f;
   }
   const int sweeps = PASS == 1 ? a.max_sweeps : *a.sweeps_dev;
   for (int s = 0; s < sweeps; ++s) {
+    // an opaque (zero) offset per sweep keeps G in LDS, read where it is used, instead of
+    // being hoisted out of the loop into RM * RM registers
+    int zero = 0;
+    asm volatile("" : "+v"(zero));
+    const float* gt = s_gt + zero;
     double d2 = 0.0;
-    // columns past r hold zeros in w and are skipped (predicated, so the loops unroll and
-    // w stays in registers)
+    float gb[2][RM];
 #pragma unroll
-    for (int j = 0; j < RMAX; ++j) {
-      if (j < r) {
-        float num = pv[j];
+    for (int l = 0; l < RM; ++l) gb[0][l] = gt[l];
 #pragma unroll
-        for (int l = 0; l < RMAX; ++l)
-          if (l < r && l != j) num = fmaf(-w[l], s_g[l * r + j], num);
-        const float gjj = s_g[j * r + j];
+    for (int j = 0; j < RM; ++j) {
+      if (j + 1 < RM) {
+#pragma unroll
+        for (int l = 0; l < RM; ++l) gb[(j + 1) & 1][l] = gt[(j + 1) * RM + l];
+      }
+      if (EXACT || j < r) {
+        float acc[4] = {pv[j], 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int m = 1; m < RM; ++m) {
+          const int l = (j + m) % RM;
+          if (EXACT || l < r) acc[m & 3] = fmaf(-w[l], gb[j & 1][l], acc[m & 3]);
+        }
+        const float num = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        const float gjj = gb[j & 1][j];
         const float nw = gjj > 0.f ? fmaxf(0.f, num) / gjj : 0.f;
         const double df = double(nw) - double(w[j]);
         d2 = fma(df, df, d2);
@@ -74,8 +96,8 @@ __global__ __launch_bounds__(kRowThreads) void hals_rows_kernel(HalsRowsArgs a) 
     }
   } else if (live) {
 #pragma unroll
-    for (int j = 0; j < RMAX; ++j)
-      if (j < r) a.W[base + j] = w[j];
+    for (int j = 0; j < RM; ++j)
+      if (EXACT || j < r) a.W[base + j] = w[j];
   }
 }
 
@@ -86,8 +108,17 @@ __global__ __launch_bounds__(64) void hals_rows_decide_kernel(HalsRowsArgs a, in
   __shared__ double s_d[kHalsRowsMaxSweeps];
   const int t = threadIdx.x;
   if (t < a.max_sweeps) {
+    // workgroups in order, sixteen loads in flight
     double x = 0.0;
-    for (int k = 0; k < nwg; ++k) x += a.part[int64_t(t) * nwg + k];
+    const double* pt = a.part + int64_t(t) * nwg;
+    for (int k0 = 0; k0 < nwg; k0 += 16) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = pt[min(k0 + u, nwg - 1)];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (k0 + u < nwg) x += v[u];
+    }
     s_d[t] = x;
   }
   __syncthreads();
@@ -104,17 +135,26 @@ __global__ __launch_bounds__(64) void hals_rows_decide_kernel(HalsRowsArgs a, in
   }
 }
 
-template <int RMAX>
+template <int RM, bool EXACT>
 hipError_t launch_passes(const HalsRowsArgs& a, hipStream_t s) {
   const int nwg = int(hals_rows_workgroups(a.rows));
-  const size_t lds = size_t(a.r) * a.r * sizeof(float);
-  hipLaunchKernelGGL((hals_rows_kernel<RMAX, 1>), dim3(nwg), dim3(kRowThreads), lds, s, a);
+  hipLaunchKernelGGL((hals_rows_kernel<RM, EXACT, 1>), dim3(nwg), dim3(kRowThreads), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(hals_rows_decide_kernel, dim3(1), dim3(64), 0, s, a, nwg);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((hals_rows_kernel<RMAX, 2>), dim3(nwg), dim3(kRowThreads), lds, s, a);
+  hipLaunchKernelGGL((hals_rows_kernel<RM, EXACT, 2>), dim3(nwg), dim3(kRowThreads), 0, s, a);
   return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_exact(const HalsRowsArgs& a, hipStream_t s) {
+  if constexpr (R > 16) {
+    return hipErrorInvalidValue;
+  } else {
+    if (a.r == R) return launch_passes<R, true>(a, s);
+    return launch_exact<R + 1>(a, s);
+  }
 }
 
 }  // namespace
@@ -122,9 +162,10 @@ hipError_t launch_passes(const HalsRowsArgs& a, hipStream_t s) {
 int64_t hals_rows_workgroups(int64_t rows) { return ceil_div(rows, kRowThreads); }
 
 hipError_t launch_hals_rows(const HalsRowsArgs& a, hipStream_t s) {
-  if (a.r > kHalsRowsMaxRank) return hipErrorInvalidValue;
-  if (a.r <= 16) return launch_passes<16>(a, s);
-  return launch_passes<32>(a, s);
+  if (a.r < 1 || a.r > kHalsRowsMaxRank) return hipErrorInvalidValue;
+  if (a.r <= 16) return launch_exact<1>(a, s);
+  if (a.r <= 24) return launch_passes<24, false>(a, s);
+  return launch_passes<32, false>(a, s);
 }
 
 }  // namespace ntf

@@ -15,8 +15,82 @@ namespace {
 
 constexpr int kTThreads = 256;
 
-// Q[i][p] = sum_n U[n][i] A[n][p] (U: n x rp, A: n x r). Workgroup i; its threads are
-// 8 lanes along n by 32 along p, summed over the lanes in a fixed order (float64).
+// Q = U^T A for small outputs (rp r <= kProjOut): workgroup g takes row chunks g, g + G, ...
+// of cr rows, stages each chunk's U and A rows in LDS and accumulates its outputs (thread
+// t: outputs t, t + 256, ...) over the rows in order (float64); partial[g] holds its sums,
+// which tucker_proj_sum_kernel adds in workgroup order.
+constexpr int kProjOut = 8 * kTThreads;
+constexpr int kProjWgs = 1024;
+
+// rows per chunk: what fits 64 KB of LDS, at most 256, and few enough that the rows spread
+// over about 128 workgroups
+int proj_chunk_rows(int64_t n, int rp, int r) {
+  const int64_t spread = std::max<int64_t>(1, ceil_div(n, int64_t(128)));
+  return int(std::max<int64_t>(1, std::min<int64_t>({256, 16384 / (rp + r), spread})));
+}
+
+int64_t proj_wgs(int64_t n, int rp, int r) {
+  return std::min<int64_t>(kProjWgs, ceil_div(n, proj_chunk_rows(n, rp, r)));
+}
+
+__global__ __launch_bounds__(kTThreads) void tucker_proj_part_kernel(
+    const float* __restrict__ U, const float* __restrict__ A, int64_t n, int rp, int r, int cr,
+    double* __restrict__ part) {
+  extern __shared__ float sm[];
+  float* Us = sm;            // cr x rp
+  float* As = sm + cr * rp;  // cr x r
+  const int t = threadIdx.x;
+  const int no = rp * r;
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  for (int64_t c = blockIdx.x; c * cr < n; c += gridDim.x) {
+    const int64_t m0 = c * cr;
+    const int rows = int(std::min<int64_t>(cr, n - m0));
+    for (int e = t; e < rows * rp; e += kTThreads) Us[e] = U[m0 * rp + e];
+    for (int e = t; e < rows * r; e += kTThreads) As[e] = A[m0 * r + e];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int o = t + q * kTThreads;
+      if (o < no) {
+        const int i = o / r, p = o - (o / r) * r;
+        double a = acc[q];
+        for (int m = 0; m < rows; ++m) a = fma(double(Us[m * rp + i]), double(As[m * r + p]), a);
+        acc[q] = a;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int o = t + q * kTThreads;
+    if (o < no) part[int64_t(blockIdx.x) * no + o] = acc[q];
+  }
+}
+
+// Q[o] = sum over workgroups g (in order) of part[g][o]; sixteen loads in flight per thread
+__global__ __launch_bounds__(kTThreads) void tucker_proj_sum_kernel(
+    const double* __restrict__ part, int nwg, int no, float* __restrict__ Q32,
+    double* __restrict__ Q64) {
+  const int o = blockIdx.x * kTThreads + threadIdx.x;
+  if (o >= no) return;
+  double s = 0.0;
+  for (int g0 = 0; g0 < nwg; g0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = part[int64_t(min(g0 + u, nwg - 1)) * no + o];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (g0 + u < nwg) s += v[u];
+  }
+  if (Q32) Q32[o] = float(s);
+  if (Q64) Q64[o] = s;
+}
+
+// Q[i][p] = sum_n U[n][i] A[n][p] (U: n x rp, A: n x r), for outputs too large for the
+// kernels above. Workgroup i; its threads are 8 lanes along n by 32 along p, summed over
+// the lanes in a fixed order (float64).
 __global__ __launch_bounds__(kTThreads) void tucker_proj_kernel(const float* __restrict__ U,
                                                                 const float* __restrict__ A,
                                                                 int64_t n, int rp, int r,
@@ -106,10 +180,34 @@ int blocks_for(int64_t n) { return int(std::max<int64_t>(1, ceil_div(n, kTThread
 
 }  // namespace
 
+size_t tucker_proj_part_doubles(int64_t n, int rp, int r) {
+  if (int64_t(rp) * r > kProjOut) return 0;
+  return size_t(proj_wgs(n, rp, r)) * rp * r;
+}
+
 hipError_t launch_tucker_proj(const float* U, const float* A, int64_t n, int rp, int r,
-                              float* Q32, double* Q64, hipStream_t s) {
-  hipLaunchKernelGGL(tucker_proj_kernel, dim3(rp), dim3(kTThreads), 0, s, U, A, n, rp, r, Q32,
-                     Q64);
+                              float* Q32, double* Q64, double* part, hipStream_t s) {
+  if (int64_t(rp) * r > kProjOut) {
+    hipLaunchKernelGGL(tucker_proj_kernel, dim3(rp), dim3(kTThreads), 0, s, U, A, n, rp, r,
+                       Q32, Q64);
+    return hipGetLastError();
+  }
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(tucker_proj_part_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int cr = proj_chunk_rows(n, rp, r);
+  const int nwg = int(proj_wgs(n, rp, r));
+  hipLaunchKernelGGL(tucker_proj_part_kernel, dim3(nwg), dim3(kTThreads),
+                     size_t(cr) * (rp + r) * sizeof(float), s, U, A, n, rp, r, cr, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int no = rp * r;
+  hipLaunchKernelGGL(tucker_proj_sum_kernel, dim3(unsigned(ceil_div(no, kTThreads))),
+                     dim3(kTThreads), 0, s, part, nwg, no, Q32, Q64);
   return hipGetLastError();
 }
 
@@ -122,12 +220,14 @@ hipError_t launch_tucker_expand(const float* U, const float* Pc, int64_t n, int 
 
 size_t tucker_norm_workspace_doubles(const TuckerDesc& X) {
   int64_t core = 1;
-  size_t grams = 0;
+  size_t grams = 0, part = 0;
   for (int p = 0; p < X.core.order; ++p) {
     core *= X.core.dims[p];
-    grams += size_t(X.core.dims[p]) * X.core.dims[p];
+    grams = std::max(grams, size_t(X.core.dims[p]) * X.core.dims[p]);
+    part = std::max(part, tucker_proj_part_doubles(X.dims[p], int(X.core.dims[p]),
+                                                   int(X.core.dims[p])));
   }
-  return size_t(2 * core) + grams;
+  return size_t(2 * core) + grams + part;
 }
 
 hipError_t launch_tucker_norm2(const TuckerDesc& X, double* ws, double* out, hipStream_t s) {
@@ -136,6 +236,9 @@ hipError_t launch_tucker_norm2(const TuckerDesc& X, double* ws, double* out, hip
   for (int p = 0; p < N; ++p) total *= X.core.dims[p];
   double* buf[2] = {ws, ws + total};
   double* gram = ws + 2 * total;
+  size_t gmax = 0;
+  for (int p = 0; p < N; ++p) gmax = std::max(gmax, size_t(X.core.dims[p]) * X.core.dims[p]);
+  double* part = gram + gmax;
   const float* core = static_cast<const float*>(X.core.data);
   hipLaunchKernelGGL(f32_to_f64_kernel, dim3(std::min(blocks_for(total), 4096)), dim3(kTThreads),
                      0, s, core, buf[0], total);
@@ -147,7 +250,7 @@ hipError_t launch_tucker_norm2(const TuckerDesc& X, double* ws, double* out, hip
     const int dm = int(X.core.dims[p]);
     inner /= dm;
     // M = U^(p)T U^(p) (float64)
-    if ((e = launch_tucker_proj(X.U[p], X.U[p], X.dims[p], dm, dm, nullptr, gram, s)) !=
+    if ((e = launch_tucker_proj(X.U[p], X.U[p], X.dims[p], dm, dm, nullptr, gram, part, s)) !=
         hipSuccess)
       return e;
     hipLaunchKernelGGL(mode_product_kernel, dim3(blocks_for(total)), dim3(kTThreads), 0, s,

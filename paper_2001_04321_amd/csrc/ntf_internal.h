@@ -352,9 +352,12 @@ hipError_t launch_hals_rows(const HalsRowsArgs& a, hipStream_t s);
 
 // Tucker-format data (k_tucker.hip).
 using TuckerDesc = ntf_tucker;
-// Q = U^T A (U: n x rp, A: n x r) into Q32 (float) and/or Q64 (double), either may be null.
+// Q = U^T A (U: n x rp, A: n x r, float64 accumulation) into Q32 (float) and/or Q64
+// (double), rp x r, either may be null; part: tucker_proj_part_doubles(n, rp, r) doubles of
+// workspace (may be null when that is 0).
+size_t tucker_proj_part_doubles(int64_t n, int rp, int r);
 hipError_t launch_tucker_proj(const float* U, const float* A, int64_t n, int rp, int r,
-                              float* Q32, double* Q64, hipStream_t s);
+                              float* Q32, double* Q64, double* part, hipStream_t s);
 // P = U Pc (U: n x rp, Pc: rp x r).
 hipError_t launch_tucker_expand(const float* U, const float* Pc, int64_t n, int rp, int r,
                                 float* P, hipStream_t s);

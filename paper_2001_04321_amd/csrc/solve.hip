@@ -96,6 +96,7 @@ struct SolveBufs {
   int32_t* hr_sweeps;
   float* Q[kMaxOrder];  // Tucker-format data: projected factors U^(p)T A^(p) (r_p x r)
   float* Pc;            // and the core's MTTKRP (r_n x r)
+  double* tq_part;      // per-workgroup partial sums of the projections
   double* tnorm;        // workspace of ||T||^2 of the format
 };
 
@@ -163,6 +164,10 @@ void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
       maxr = std::max(maxr, tk->core.dims[n]);
     }
     b.Pc = ar.take<float>(size_t(maxr) * r);
+    size_t qp = 1;
+    for (int n = 0; n < N; ++n)
+      qp = std::max(qp, tucker_proj_part_doubles(tk->dims[n], int(tk->core.dims[n]), r));
+    b.tq_part = ar.take<double>(qp);
     b.tnorm = ar.take<double>(tucker_norm_workspace_doubles(*tk));
   }
 }
@@ -191,7 +196,7 @@ hipError_t tucker_mttkrp_into(const TuckerDesc& tk, int n, int r, const FactorPt
     fq.p[l] = b.Q[l];
     if (l == n) continue;
     if ((e = launch_tucker_proj(tk.U[l], fp.p[l], tk.dims[l], int(tk.core.dims[l]), r, b.Q[l],
-                                nullptr, s)) != hipSuccess)
+                                nullptr, b.tq_part, s)) != hipSuccess)
       return e;
   }
   if ((e = launch_mttkrp(plan, tk.core.data, fq, b.Pc, b.mt_part, true, s, nullptr, had)) !=
