@@ -152,8 +152,17 @@ __global__ __launch_bounds__(64) void admm_decide_kernel(AdmmArgs a, int nwg) {
   __shared__ double s_d[kAdmmMaxSteps];
   const int t = threadIdx.x;
   if (t < a.max_steps) {
+    // workgroups in order, sixteen loads in flight
     double x = 0.0;
-    for (int k = 0; k < nwg; ++k) x += a.part[int64_t(t) * nwg + k];
+    const double* pt = a.part + int64_t(t) * nwg;
+    for (int k0 = 0; k0 < nwg; k0 += 16) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = pt[min(k0 + u, nwg - 1)];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (k0 + u < nwg) x += v[u];
+    }
     s_d[t] = x;
   }
   __syncthreads();
