@@ -64,6 +64,10 @@ def _check_trajectory(tr, ref, iters, normT2):
     ((21, 17, 9, 30), (4, 3, 5, 6), 8, False),
     ((300, 64), (20, 9), 40, False),
     ((70, 50, 90), (12, 10, 11), 100, True),
+    # outputs r_p r above 2048 (one workgroup per core index), and a long mode whose row
+    # chunks outnumber the projection's workgroups (each takes several chunks)
+    ((60, 45, 50), (40, 36, 8), 64, False),
+    ((300000, 6, 5), (8, 3, 4), 4, True),
 ])
 def test_tucker_mttkrp_matches_oracle(ntf, dims, ranks, r, orth):
     print(f"tucker mttkrp dims={dims} ranks={ranks} r={r}", flush=True)
@@ -171,11 +175,15 @@ def test_solve_tucker_video_workload_fit(ntf):
     assert abs((1 - rel) - g["fit"]) <= 1e-3 * g["fit"]
 
 
-@pytest.mark.parametrize("dims,r,seed", [((12300, 16, 12), 6, 0), ((12500, 10, 9), 20, 1),
-                                         ((14, 13000, 11), 5, 2)])
-def test_dense_solve_with_row_parallel_hals(ntf, dims, r, seed):
-    """Dense tensors with a mode beyond the resident A-HALS kernel (r <= 16 and r <= 32
-    variants of the row kernel, first and middle mode)."""
+@pytest.mark.parametrize("dims,r,seed,iters", [((12300, 16, 12), 6, 0, 25),
+                                               ((12500, 10, 9), 20, 1, 25),
+                                               ((14, 13000, 11), 5, 2, 25),
+                                               ((12400, 9, 8), 26, 3, 8),
+                                               ((8, 7, 13000), 16, 4, 15)])
+def test_dense_solve_with_row_parallel_hals(ntf, dims, r, seed, iters):
+    """Dense tensors with a mode beyond the resident A-HALS kernel: the row kernel with the
+    exact rank (r = 5, 6, 16) and with 24 and 32 padded columns (r = 20, 26), in the first,
+    middle and last mode."""
     print(f"dense row-parallel dims={dims} r={r}", flush=True)
     pr = synth.make_problem(dims, r, snr_db=30.0, data_seed=seed + 70, init_seed=seed + 80)
     T32 = _f32(pr.T)
@@ -183,7 +191,6 @@ def test_dense_solve_with_row_parallel_hals(ntf, dims, r, seed):
     del pr
     Td, T64 = dev_tensor(T32, "f32")
     A = [dev_f32(a) for a in A0]
-    iters = 25
     _, tr = ntf.ntf_solve(Td, A, iters)
     torch.cuda.synchronize()
     tr = {k: v.cpu().numpy() for k, v in tr.items()}
