@@ -38,7 +38,6 @@ constexpr int kWaves = kHalsRowWaves;      // waves that own rows
 constexpr int kCT = 64 * kWaves;           // their threads
 constexpr int kThreads = kCT + 64;         // plus one wave that runs the stopping rule
 constexpr int kMaxLag = 16;                // sweeps the row waves may run ahead of a decision
-constexpr int kDecide = 4;                 // slot loads per lane in one round trip of the rule
 constexpr int kRefresh = 4;  // sweeps between exact recomputations of q
 constexpr uint64_t kSentinel = ~uint64_t(0);
 
@@ -139,43 +138,87 @@ __device__ __forceinline__ void lds_barrier() {
 // and the critical path is the max and one multiply-add: the deferred update and the w
 // update fill the two wait states a DPP read of the freshly written d needs. Per element
 // the updates keep the column order, so the results do not depend on the deferral.
-// the DPP broadcast of lane %[n] (or %[p]) of each 16-lane row, as a source modifier
+// Eight columns (one block of G) form one asm statement: between two statements where the
+// second reads what the first wrote, the compiler inserts a wait state of its own.
+//
+// Operands of a block starting at column J0 (t = 0..7, column j = J0 + t, o = j mod 16):
+// zc / zo the slot of the block's columns and the other one, w that slot's iterate entries,
+// d0 / d1 the changes of even / odd t, dp and gp the previous column's change and the
+// coefficient of its deferred update, gi_t the coefficient of column t's immediate update,
+// gd_t that of its deferred one, f_t its owner flag, n_t = o and p_t = (j - 1) mod 16.
 #define NTF_BC(x) " row_newbcast:%[" #x "] row_mask:0xf bank_mask:0xf bound_ctrl:1"
-// next column in the same slot: zc holds the column and the next one; zo takes the deferred
-// update of the previous column (owner lane P)
-template <int N, int P>
-__device__ __forceinline__ void col_same(float& zc, float& zo, float& w, float& d, float dp,
-                                         float gp, float f, float gc) {
-  asm volatile("v_max_f32_e64 %[d], %[zc], -%[w]\n\t"
-               "v_fmac_f32_dpp %[zo], %[dp], %[gp]" NTF_BC(p) "\n\t"
-               "v_fmac_f32_e32 %[w], %[d], %[f]\n\t"
-               "v_fmac_f32_dpp %[zc], %[d], %[gc]" NTF_BC(n)
-               : [zc] "+v"(zc), [zo] "+v"(zo), [w] "+v"(w), [d] "=&v"(d)
-               : [dp] "v"(dp), [gp] "v"(gp), [f] "v"(f), [gc] "v"(gc), [n] "i"(N), [p] "i"(P));
-}
-// next column in the other slot: zm holds the column, zo the next one (and takes the
-// deferred update of the previous column first)
-template <int N, int P>
-__device__ __forceinline__ void col_switch(float zm, float& zo, float& w, float& d, float dp,
-                                           float gp, float f, float gc) {
-  asm volatile("v_max_f32_e64 %[d], %[zm], -%[w]\n\t"
-               "v_fmac_f32_dpp %[zo], %[dp], %[gp]" NTF_BC(p) "\n\t"
-               "v_fmac_f32_e32 %[w], %[d], %[f]\n\t"
-               "v_fmac_f32_dpp %[zo], %[d], %[gc]" NTF_BC(n)
-               : [zo] "+v"(zo), [w] "+v"(w), [d] "=&v"(d)
-               : [zm] "v"(zm), [dp] "v"(dp), [gp] "v"(gp), [f] "v"(f), [gc] "v"(gc),
-                 [n] "i"(N), [p] "i"(P));
-}
-// first column of a sweep (nothing deferred yet), and the one-slot step (C = 1): the w
+// first column of a sweep, and every column of a one-slot sweep: nothing deferred; the w
 // update and an s_nop fill the two wait states
-template <int N>
-__device__ __forceinline__ void col_first(float& zc, float& w, float& d, float f, float gc) {
-  asm volatile("v_max_f32_e64 %[d], %[zc], -%[w]\n\t"
-               "v_fmac_f32_e32 %[w], %[d], %[f]\n\t"
-               "s_nop 0\n\t"
-               "v_fmac_f32_dpp %[zc], %[d], %[gc]" NTF_BC(n)
-               : [zc] "+v"(zc), [w] "+v"(w), [d] "=&v"(d)
-               : [f] "v"(f), [gc] "v"(gc), [n] "i"(N));
+#define NTF_C16F(t, dc)                                   \
+  "v_max_f32_e64 %[" #dc "], %[zc], -%[w]\n\t"            \
+  "v_fmac_f32_e32 %[w], %[" #dc "], %[f" #t "]\n\t"       \
+  "s_nop 0\n\t"                                           \
+  "v_fmac_f32_dpp %[zc], %[" #dc "], %[gi" #t "]" NTF_BC(n##t) "\n\t"
+// next column in the same slot (deferred update of the previous column into zo)
+#define NTF_C16S(t, dc, dpr, gpr)                                        \
+  "v_max_f32_e64 %[" #dc "], %[zc], -%[w]\n\t"                           \
+  "v_fmac_f32_dpp %[zo], %[" #dpr "], %[" #gpr "]" NTF_BC(p##t) "\n\t"   \
+  "v_fmac_f32_e32 %[w], %[" #dc "], %[f" #t "]\n\t"                      \
+  "v_fmac_f32_dpp %[zc], %[" #dc "], %[gi" #t "]" NTF_BC(n##t) "\n\t"
+// next column in the other slot: the immediate update goes to zo, the deferred one (of zc)
+// to the next block
+#define NTF_C16X(t, dc, dpr, gpr)                                        \
+  "v_max_f32_e64 %[" #dc "], %[zc], -%[w]\n\t"                           \
+  "v_fmac_f32_dpp %[zo], %[" #dpr "], %[" #gpr "]" NTF_BC(p##t) "\n\t"   \
+  "v_fmac_f32_e32 %[w], %[" #dc "], %[f" #t "]\n\t"                      \
+  "v_fmac_f32_dpp %[zo], %[" #dc "], %[gi" #t "]" NTF_BC(n##t) "\n\t"
+#define NTF_GI(g) [gi0] "v"(g[0]), [gi1] "v"(g[1]), [gi2] "v"(g[2]), [gi3] "v"(g[3]), \
+                  [gi4] "v"(g[4]), [gi5] "v"(g[5]), [gi6] "v"(g[6]), [gi7] "v"(g[7])
+#define NTF_GD(g) [gd0] "v"(g[0]), [gd1] "v"(g[1]), [gd2] "v"(g[2]), [gd3] "v"(g[3]), \
+                  [gd4] "v"(g[4]), [gd5] "v"(g[5]), [gd6] "v"(g[6])
+#define NTF_FL(f) [f0] "v"(f[0]), [f1] "v"(f[1]), [f2] "v"(f[2]), [f3] "v"(f[3]), \
+                  [f4] "v"(f[4]), [f5] "v"(f[5]), [f6] "v"(f[6]), [f7] "v"(f[7])
+#define NTF_IMM(c, J, k)                                                            \
+  [c##0] "i"((J + 0 - k) & 15), [c##1] "i"((J + 1 - k) & 15), [c##2] "i"((J + 2 - k) & 15), \
+  [c##3] "i"((J + 3 - k) & 15), [c##4] "i"((J + 4 - k) & 15), [c##5] "i"((J + 5 - k) & 15), \
+  [c##6] "i"((J + 6 - k) & 15), [c##7] "i"((J + 7 - k) & 15)
+
+// One-slot block (C = 1): columns J0 .. J0 + 7 of zc / w.
+template <int J0>
+__device__ __forceinline__ void blk16_one(float& zc, float& w, const float (&gi)[8],
+                                          const float (&f)[8]) {
+  float d0, d1;
+  asm volatile(NTF_C16F(0, d0) NTF_C16F(1, d1) NTF_C16F(2, d0) NTF_C16F(3, d1)
+               NTF_C16F(4, d0) NTF_C16F(5, d1) NTF_C16F(6, d0) NTF_C16F(7, d1)
+               : [zc] "+v"(zc), [w] "+v"(w), [d0] "=&v"(d0), [d1] "=&v"(d1)
+               : NTF_GI(gi), NTF_FL(f), NTF_IMM(n, J0, 0));
+}
+// Two-slot block (C = 2): columns J0 .. J0 + 7 (all in slot zc); SW: the column after the
+// block is in the other slot. dp / gp carry the deferred update in and out.
+template <int J0, bool SW>
+__device__ __forceinline__ void blk16_two(float& zc, float& zo, float& w, float& dp, float& gp,
+                                          const float (&gi)[8], const float (&gd)[8],
+                                          const float (&f)[8]) {
+  float d0, d1;
+  if constexpr (J0 == 0) {
+    static_assert(!SW, "a block of eight starts every slot");
+    asm volatile(NTF_C16F(0, d0) NTF_C16S(1, d1, d0, gd0) NTF_C16S(2, d0, d1, gd1)
+                 NTF_C16S(3, d1, d0, gd2) NTF_C16S(4, d0, d1, gd3) NTF_C16S(5, d1, d0, gd4)
+                 NTF_C16S(6, d0, d1, gd5) NTF_C16S(7, d1, d0, gd6)
+                 : [zc] "+v"(zc), [zo] "+v"(zo), [w] "+v"(w), [d0] "=&v"(d0), [d1] "=&v"(d1)
+                 : NTF_GI(gi), NTF_GD(gd), NTF_FL(f), NTF_IMM(n, J0, 0), NTF_IMM(p, J0, 1));
+  } else if constexpr (!SW) {
+    asm volatile(NTF_C16S(0, d0, dp, gp) NTF_C16S(1, d1, d0, gd0) NTF_C16S(2, d0, d1, gd1)
+                 NTF_C16S(3, d1, d0, gd2) NTF_C16S(4, d0, d1, gd3) NTF_C16S(5, d1, d0, gd4)
+                 NTF_C16S(6, d0, d1, gd5) NTF_C16S(7, d1, d0, gd6)
+                 : [zc] "+v"(zc), [zo] "+v"(zo), [w] "+v"(w), [d0] "=&v"(d0), [d1] "=&v"(d1)
+                 : [dp] "v"(dp), [gp] "v"(gp), NTF_GI(gi), NTF_GD(gd), NTF_FL(f),
+                   NTF_IMM(n, J0, 0), NTF_IMM(p, J0, 1));
+  } else {
+    asm volatile(NTF_C16S(0, d0, dp, gp) NTF_C16S(1, d1, d0, gd0) NTF_C16S(2, d0, d1, gd1)
+                 NTF_C16S(3, d1, d0, gd2) NTF_C16S(4, d0, d1, gd3) NTF_C16S(5, d1, d0, gd4)
+                 NTF_C16S(6, d0, d1, gd5) NTF_C16X(7, d1, d0, gd6)
+                 : [zc] "+v"(zc), [zo] "+v"(zo), [w] "+v"(w), [d0] "=&v"(d0), [d1] "=&v"(d1)
+                 : [dp] "v"(dp), [gp] "v"(gp), NTF_GI(gi), NTF_GD(gd), NTF_FL(f),
+                   NTF_IMM(n, J0, 0), NTF_IMM(p, J0, 1));
+  }
+  dp = d1;
+  gp = gd[7];
 }
 // the update deferred from the last column of a sweep
 template <int P>
@@ -184,21 +227,100 @@ __device__ __forceinline__ void col_flush(float& zo, float dp, float gp) {
                : [zo] "+v"(zo)
                : [dp] "v"(dp), [gp] "v"(gp), [p] "i"(P));
 }
-// refresh term of column N: a_c += bcast_N(w) g_c (w is not written during the refresh, so
-// its DPP reads need no wait states)
-template <int N>
-__device__ __forceinline__ void acc_bcast2(float& a0, float& a1, float w, float g0, float g1) {
-  asm volatile("v_fmac_f32_dpp %[a0], %[w], %[g0]" NTF_BC(n) "\n\t"
-               "v_fmac_f32_dpp %[a1], %[w], %[g1]" NTF_BC(n)
+
+// Column steps for 64-lane row groups (one slot): the owner's change d reaches the row
+// through v_readlane (a scalar operand of the multiply-add z += d_o g); the owner's own w
+// takes it one column later, deferred into the next step, as a multiply-add with the 0/1
+// flag of its lane within its 16-lane row, written to that row only (DPP row mask,
+// identity permutation). The critical path is the max, the read-lane and one multiply-add;
+// the deferred update fills the wait state between the max and the read-lane. Operands of
+// a block at J0: g_t the coefficient of column t, f_t / m_t the flag and row mask of the
+// previous column's owner, o_t = J0 + t.
+#define NTF_ROW(x) " quad_perm:[0,1,2,3] row_mask:%[" #x "] bank_mask:0xf"
+#define NTF_C64F(t, dc)                                   \
+  "v_max_f32_e64 %[" #dc "], %[z], -%[w]\n\t"             \
+  "s_nop 0\n\t"                                           \
+  "v_readlane_b32 %[s], %[" #dc "], %[o" #t "]\n\t"       \
+  "v_fmac_f32_e32 %[z], %[s], %[g" #t "]\n\t"
+#define NTF_C64(t, dc, dpr)                                              \
+  "v_max_f32_e64 %[" #dc "], %[z], -%[w]\n\t"                            \
+  "v_fmac_f32_dpp %[w], %[" #dpr "], %[f" #t "]" NTF_ROW(m##t) "\n\t"    \
+  "v_readlane_b32 %[s], %[" #dc "], %[o" #t "]\n\t"                      \
+  "v_fmac_f32_e32 %[z], %[s], %[g" #t "]\n\t"
+#define NTF_G64(g) [g0] "v"(g[0]), [g1] "v"(g[1]), [g2] "v"(g[2]), [g3] "v"(g[3]), \
+                   [g4] "v"(g[4]), [g5] "v"(g[5]), [g6] "v"(g[6]), [g7] "v"(g[7])
+#define NTF_LANES(J)                                                                     \
+  [o0] "i"(J + 0), [o1] "i"(J + 1), [o2] "i"(J + 2), [o3] "i"(J + 3), [o4] "i"(J + 4), \
+  [o5] "i"(J + 5), [o6] "i"(J + 6), [o7] "i"(J + 7)
+#define NTF_RM(J)                                                                     \
+  [m0] "i"(1 << (((J + 63) & 63) / 16)), [m1] "i"(1 << ((J + 0) / 16)),               \
+  [m2] "i"(1 << ((J + 1) / 16)), [m3] "i"(1 << ((J + 2) / 16)), [m4] "i"(1 << ((J + 3) / 16)), \
+  [m5] "i"(1 << ((J + 4) / 16)), [m6] "i"(1 << ((J + 5) / 16)), [m7] "i"(1 << ((J + 6) / 16))
+template <int J0>
+__device__ __forceinline__ void blk64(float& z, float& w, float& dp, const float (&g)[8],
+                                      const float (&f)[8]) {
+  float d0, d1;
+  int s;
+  if constexpr (J0 == 0) {
+    asm volatile(NTF_C64F(0, d0) NTF_C64(1, d1, d0) NTF_C64(2, d0, d1) NTF_C64(3, d1, d0)
+                 NTF_C64(4, d0, d1) NTF_C64(5, d1, d0) NTF_C64(6, d0, d1) NTF_C64(7, d1, d0)
+                 : [z] "+v"(z), [w] "+v"(w), [d0] "=&v"(d0), [d1] "=&v"(d1), [s] "=&s"(s)
+                 : NTF_G64(g), NTF_FL(f), NTF_LANES(J0), NTF_RM(J0));
+  } else {
+    asm volatile(NTF_C64(0, d0, dp) NTF_C64(1, d1, d0) NTF_C64(2, d0, d1) NTF_C64(3, d1, d0)
+                 NTF_C64(4, d0, d1) NTF_C64(5, d1, d0) NTF_C64(6, d0, d1) NTF_C64(7, d1, d0)
+                 : [z] "+v"(z), [w] "+v"(w), [d0] "=&v"(d0), [d1] "=&v"(d1), [s] "=&s"(s)
+                 : [dp] "v"(dp), NTF_G64(g), NTF_FL(f), NTF_LANES(J0), NTF_RM(J0));
+  }
+  dp = d1;
+}
+// the owner update deferred from the last column P of a sweep (its d was written three
+// instructions before the end of the block, so the DPP read needs no wait state)
+template <int P>
+__device__ __forceinline__ void col64_flush(float& w, float dp, float fp) {
+  asm volatile("v_fmac_f32_dpp %[w], %[dp], %[fp]" NTF_ROW(pm)
+               : [w] "+v"(w)
+               : [dp] "v"(dp), [fp] "v"(fp), [pm] "i"(1 << (P / 16)));
+}
+#undef NTF_ROW
+#undef NTF_C64F
+#undef NTF_C64
+#undef NTF_G64
+#undef NTF_LANES
+#undef NTF_RM
+#undef NTF_C16F
+#undef NTF_C16S
+#undef NTF_C16X
+#undef NTF_GI
+#undef NTF_GD
+#undef NTF_FL
+#undef NTF_IMM
+// refresh terms of columns J0 .. J0 + 7 (one slot of w): a_c += bcast_o(w) g_c (w is not
+// written during the refresh, so its DPP reads need no wait states)
+#define NTF_R1(t) "v_fmac_f32_dpp %[a0], %[w], %[g" #t "]" NTF_BC(n##t) "\n\t"
+#define NTF_R2(t) NTF_R1(t) "v_fmac_f32_dpp %[a1], %[w], %[h" #t "]" NTF_BC(n##t) "\n\t"
+#define NTF_G8(c, g) [c##0] "v"(g[0]), [c##1] "v"(g[1]), [c##2] "v"(g[2]), [c##3] "v"(g[3]), \
+                     [c##4] "v"(g[4]), [c##5] "v"(g[5]), [c##6] "v"(g[6]), [c##7] "v"(g[7])
+#define NTF_N8(J) [n0] "i"((J + 0) & 15), [n1] "i"((J + 1) & 15), [n2] "i"((J + 2) & 15), \
+                  [n3] "i"((J + 3) & 15), [n4] "i"((J + 4) & 15), [n5] "i"((J + 5) & 15), \
+                  [n6] "i"((J + 6) & 15), [n7] "i"((J + 7) & 15)
+template <int J0>
+__device__ __forceinline__ void acc_blk2(float& a0, float& a1, float w, const float (&g)[8],
+                                         const float (&h)[8]) {
+  asm volatile(NTF_R2(0) NTF_R2(1) NTF_R2(2) NTF_R2(3) NTF_R2(4) NTF_R2(5) NTF_R2(6) NTF_R2(7)
                : [a0] "+v"(a0), [a1] "+v"(a1)
-               : [w] "v"(w), [g0] "v"(g0), [g1] "v"(g1), [n] "i"(N));
+               : [w] "v"(w), NTF_G8(g, g), NTF_G8(h, h), NTF_N8(J0));
 }
-template <int N>
-__device__ __forceinline__ void acc_bcast1(float& a0, float w, float g0) {
-  asm volatile("v_fmac_f32_dpp %[a0], %[w], %[g0]" NTF_BC(n)
+template <int J0>
+__device__ __forceinline__ void acc_blk1(float& a0, float w, const float (&g)[8]) {
+  asm volatile(NTF_R1(0) NTF_R1(1) NTF_R1(2) NTF_R1(3) NTF_R1(4) NTF_R1(5) NTF_R1(6) NTF_R1(7)
                : [a0] "+v"(a0)
-               : [w] "v"(w), [g0] "v"(g0), [n] "i"(N));
+               : [w] "v"(w), NTF_G8(g, g), NTF_N8(J0));
 }
+#undef NTF_R1
+#undef NTF_R2
+#undef NTF_G8
+#undef NTF_N8
 #undef NTF_BC
 
 // f(std::integral_constant<int, J>()) for J = B .. E - 1, in order
@@ -237,7 +359,7 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
   const int gl = lane % RPAD;      // lane within its row group
   const int gi = lane / RPAD;      // row group within the wave
   const int64_t row0 = int64_t(blockIdx.x) * RPW;
@@ -378,9 +500,10 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
         gb[t][c] = GREG ? greg[GREG ? jb * 8 + t : 0][c] : s_g[(jb * 8 + t) * RMAX + c * RPAD + gl];
   };
   // 1 on the lanes that hold column offset o of their group, else 0 (16-lane groups)
+  // (64-lane groups: the lane within its 16-lane row, the row taken by a DPP row mask)
   float flag[16];
 #pragma unroll
-  for (int o = 0; o < 16; ++o) flag[o] = gl == o ? 1.f : 0.f;
+  for (int o = 0; o < 16; ++o) flag[o] = (lane & 15) == o ? 1.f : 0.f;
   // lanes owning column offset o of their group, as a wave-wide constant mask
   auto owner_mask = [&](int o) {
     uint64_t m = 0;
@@ -399,12 +522,18 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
 #pragma unroll
         for (int c = 0; c < C; ++c) a[c] = pinv[q][c];
         asm volatile("s_nop 1");  // w may have been written just before (DPP read below)
-        static_for<0, RB>([&](auto lc) {
-          constexpr int l = decltype(lc)::value;
+        static_for<0, NB>([&](auto bc) {
+          constexpr int J0 = decltype(bc)::value * 8;
+          float g0[8], g1[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            g0[t] = greg[J0 + t][0];
+            g1[t] = greg[J0 + t][C - 1];
+          }
           if constexpr (C == 2)
-            acc_bcast2<l % 16>(a[0], a[1], w[q][l / 16], greg[l][0], greg[l][1]);
+            acc_blk2<J0>(a[0], a[1], w[q][J0 / 16], g0, g1);
           else
-            acc_bcast1<l % 16>(a[0], w[q][0], greg[l][0]);
+            acc_blk1<J0>(a[0], w[q][0], g0);
         });
 #pragma unroll
         for (int c = 0; c < C; ++c) zv[q][c] = a[c];
@@ -448,37 +577,52 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   // a DPP broadcast that the compiler folds into the multiply-adds.
   auto sweep = [&]() {
     if constexpr (RPAD == 16 && GREG) {
-      // 16-lane groups, scaled G in registers: one inline-asm step per column
+      // 16-lane groups, scaled G in registers: one inline-asm statement per block of eight
+      // columns
 #pragma unroll
       for (int q = 0; q < NR; ++q) {
-        if constexpr (C == 1) {
-          static_for<0, RB>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            float d;
-            col_first<j>(zv[q][0], w[q][0], d, flag[j], greg[j][0]);
-          });
-        } else {
-          // the change d of the previous column and its G entry for the slot whose update is
-          // deferred into the next column's step
-          float dp = 0.f, gp = 0.f;
-          static_for<0, RB>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            constexpr int cs = j / 16, o = j % 16, po = (o + 15) % 16;
-            constexpr int ns = (j + 1 < RB ? j + 1 : 0) / 16;  // slot of the column read next
-            float d;
-            if constexpr (j == 0)
-              col_first<o>(zv[q][0], w[q][0], d, flag[o], greg[j][0]);
-            else if constexpr (ns == cs)
-              col_same<o, po>(zv[q][cs], zv[q][1 - cs], w[q][cs], d, dp, gp, flag[o],
-                              greg[j][cs]);
-            else
-              col_switch<o, po>(zv[q][cs], zv[q][ns], w[q][cs], d, dp, gp, flag[o],
-                                greg[j][ns]);
-            dp = d;
-            gp = greg[j][1 - ns];  // the slot the next column does not read
-            if constexpr (j + 1 == RB) col_flush<o>(zv[q][1 - ns], dp, gp);
-          });
-        }
+        // the change of the previous column and its coefficient for the slot whose update
+        // is deferred into the next column's step
+        float dp = 0.f, gp = 0.f;
+        static_for<0, NB>([&](auto bc) {
+          constexpr int J0 = decltype(bc)::value * 8;
+          constexpr int cs = J0 / 16;
+          float gi[8], gd[8], f[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int j = J0 + t;
+            const int ns = (j + 1 < RB ? j + 1 : 0) / 16;  // slot of the column read next
+            gi[t] = greg[j][C == 1 ? 0 : ns];
+            gd[t] = greg[j][C == 1 ? 0 : 1 - ns];
+            f[t] = flag[j % 16];
+          }
+          if constexpr (C == 1) {
+            blk16_one<J0>(zv[q][0], w[q][0], gi, f);
+          } else {
+            constexpr bool sw = ((J0 + 8 < RB ? J0 + 8 : 0) / 16) != cs;
+            blk16_two<J0, sw>(zv[q][cs], zv[q][1 - cs], w[q][cs], dp, gp, gi, gd, f);
+          }
+        });
+        // the last column's next is column 0 (slot 0): its deferred update is of slot 1
+        if constexpr (C == 2) col_flush<(RB - 1) % 16>(zv[q][1], dp, gp);
+      }
+    } else if constexpr (RPAD == 64 && C == 1 && GREG) {
+      // one 64-lane group per row, scaled G in registers: one inline-asm statement per block
+      // of eight columns
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        float dp = 0.f;
+        static_for<0, NB>([&](auto bc) {
+          constexpr int J0 = decltype(bc)::value * 8;
+          float g[8], f[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            g[t] = greg[J0 + t][0];
+            f[t] = flag[(J0 + t + 15) % 16];  // the previous column's owner
+          }
+          blk64<J0>(zv[q][0], w[q][0], dp, g, f);
+        });
+        col64_flush<RB - 1>(w[q][0], dp, flag[(RB - 1) % 16]);
       }
     } else {
       float gb0[8][C], gb1[8][C];
@@ -547,11 +691,18 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   bool timed_out = false;
   if (wave == WPG) {
     // ---- the rule wave ----
-    // KC slots per lane and sweep (a power of two covering nwg / 64), kDecide / KC sweeps
-    // per round trip
-    auto rule = [&](auto kc_tag) {
-      constexpr int KC = decltype(kc_tag)::value;
-      constexpr int M = kDecide / KC;
+    // M sweeps per round trip; the lanes form M groups of G = 64 / M: lane g of group m
+    // sums the global slots of sweep t_dec + m of workgroups g, g + G, ... (at most KL), in
+    // that order, then the group adds its lanes with a fixed DPP pairing, so every
+    // workgroup gets the same bits. Two ballots over the group leaders find the first
+    // sweep not yet published everywhere and the first that meets the rule.
+    auto rule = [&](auto m_tag, auto kl_tag) {
+      constexpr int M = decltype(m_tag)::value;
+      constexpr int KL = decltype(kl_tag)::value;
+      constexpr int G = 64 / M;
+      static_assert(G >= 4 && G <= 16, "groups of 4 to 16 lanes (one DPP row)");
+      const int gm = lane / G;  // this lane's sweep, relative to t_dec
+      const int gg = lane % G;
       int t_pub = 1, t_dec = 1;
       double lim = 0.0;
       const double tol2 = a.tol * a.tol;
@@ -592,44 +743,44 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
           __builtin_amdgcn_s_sleep(1);
           continue;
         }
-        uint64_t u[M][KC];
+        uint64_t u[KL];
+        const bool live = gm < n;
+        const uint64_t* srow = slots + int64_t(t_dec - 1 + (live ? gm : 0)) * a.nwg;
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-#pragma unroll
-          for (int k = 0; k < KC; ++k)
-            u[m][k] = (m < n && lane + 64 * k < a.nwg)
-                          ? __hip_atomic_load(
-                                &slots[int64_t(t_dec - 1 + m) * a.nwg + lane + 64 * k],
-                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                          : 0;
-        // every loaded sweep's sum (independent, so they overlap), then the scan in order
-        double Dm[M];
-        bool miss[M];
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-          bool ms = false;
-          double v = 0.0;
-#pragma unroll
-          for (int k = 0; k < KC; ++k) {
-            ms = ms || u[m][k] == kSentinel;
-            v += __longlong_as_double(int64_t(u[m][k]));
-          }
-          miss[m] = __any(ms);
-          Dm[m] = wave_sum64(v);
+        for (int i = 0; i < KL; ++i) {
+          const int k = gg + G * i;
+          u[i] = (live && k < a.nwg)
+                     ? __hip_atomic_load(&srow[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : 0;  // the bits of +0.0
         }
-        int ndone = 0, stop = 0;
+        bool ms = false;
+        double x = 0.0;
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-          if (m >= n || miss[m]) break;  // a workgroup has not published this sweep yet
-          const int t = t_dec + m;
-          if (t == 1) lim = tol2 * Dm[m];
-          ++ndone;
-          if (Dm[m] <= lim) {
-            stop = t;
-            break;
-          }
+        for (int i = 0; i < KL; ++i) {
+          ms = ms || u[i] == kSentinel;
+          x += __longlong_as_double(int64_t(u[i]));
         }
-        t_dec += ndone;
+        // the group's sum and whether any of its workgroups has not published
+        int mi = ms ? 1 : 0;
+        x += dpp64<0xB1>(x);
+        mi |= __builtin_amdgcn_update_dpp(0, mi, 0xB1, 0xF, 0xF, false);
+        x += dpp64<0x4E>(x);
+        mi |= __builtin_amdgcn_update_dpp(0, mi, 0x4E, 0xF, 0xF, false);
+        if constexpr (G >= 8) {
+          x += dpp64<0x141>(x);
+          mi |= __builtin_amdgcn_update_dpp(0, mi, 0x141, 0xF, 0xF, false);
+        }
+        if constexpr (G >= 16) {
+          x += dpp64<0x140>(x);
+          mi |= __builtin_amdgcn_update_dpp(0, mi, 0x140, 0xF, 0xF, false);
+        }
+        const bool lead = gg == 0;
+        const uint64_t bad = __ballot(lead && (mi != 0 || !live));
+        const int nd = bad ? min(n, int(__builtin_ctzll(bad)) / G) : n;  // decidable now
+        if (t_dec == 1 && nd > 0) lim = tol2 * readlane64(x, 0);  // ||W_1 - W_0||^2 tol^2
+        const uint64_t hit = __ballot(lead && gm < nd && x <= lim);
+        const int stop = hit ? t_dec + int(__builtin_ctzll(hit)) / G : 0;
+        t_dec = stop ? stop + 1 : t_dec + nd;
         // the emptied share slots are visible before the decision that lets them refill
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if (stop) {
@@ -640,15 +791,18 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
           return;
         }
         if (lane == 0) lds_st(&s_decided, t_dec - 1);
-        if (ndone == 0) __builtin_amdgcn_s_sleep(2);
+        if (nd == 0) __builtin_amdgcn_s_sleep(2);
       }
     };
-    if (a.nwg <= 64)
-      rule(std::integral_constant<int, 1>());
+    // M * nwg <= 512 slots per round trip (KL = 8 loads per lane), M >= 4
+    if (a.nwg <= 32)
+      rule(std::integral_constant<int, 16>(), std::integral_constant<int, 8>());
+    else if (a.nwg <= 64)
+      rule(std::integral_constant<int, 8>(), std::integral_constant<int, 8>());
     else if (a.nwg <= 128)
-      rule(std::integral_constant<int, 2>());
+      rule(std::integral_constant<int, 4>(), std::integral_constant<int, 8>());
     else
-      rule(std::integral_constant<int, 4>());
+      rule(std::integral_constant<int, 4>(), std::integral_constant<int, 16>());
   } else {
     // ---- the row waves ----
     int dec = 0, stp = 0;  // the decision state as last read (at most one sweep old)
@@ -658,8 +812,8 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
       sk = sk + 1 == K ? 0 : sk + 1;
       while (stp == 0 && s - dec > L) {
         __builtin_amdgcn_s_sleep(1);
-        dec = lds_ld(&s_decided);
-        stp = lds_ld(&s_stop);
+        dec = __builtin_amdgcn_readfirstlane(lds_ld(&s_decided));
+        stp = __builtin_amdgcn_readfirstlane(lds_ld(&s_stop));
       }
       if (stp != 0) break;
       float prev[NR][C];
@@ -684,13 +838,14 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
           d2 = fma(df, df, d2);
         }
       sh_st(s_sh + sk * kCT + tid, d2);
-      dec = dec_next;
-      stp = stp_next;
+      // the decision state is the same on every lane: scalar, so the loop control is too
+      dec = __builtin_amdgcn_readfirstlane(dec_next);
+      stp = __builtin_amdgcn_readfirstlane(stp_next);
     }
     // the decision for the sweeps still open
-    while (stp == 0 && lds_ld(&s_decided) < S) {
+    while (stp == 0 && __builtin_amdgcn_readfirstlane(lds_ld(&s_decided)) < S) {
       __builtin_amdgcn_s_sleep(1);
-      stp = lds_ld(&s_stop);
+      stp = __builtin_amdgcn_readfirstlane(lds_ld(&s_stop));
     }
     if (stp > 0) {
       ring_get(stp % R);
