@@ -805,6 +805,9 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
       rule(std::integral_constant<int, 4>(), std::integral_constant<int, 16>());
   } else {
     // ---- the row waves ----
+    // every LDS read so far (the scaled G in registers) has arrived: without this wait the
+    // first use inside the loop would wait for them, on every sweep
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
     int dec = 0, stp = 0;  // the decision state as last read (at most one sweep old)
     int sr = 0, sk = 0;    // s mod R, s mod K
     for (int s = 1; s <= S; ++s) {
