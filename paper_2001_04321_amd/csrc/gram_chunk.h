@@ -121,12 +121,13 @@ __device__ inline void hadamard_work(const HadamardJob& job, int r, float* G32, 
   // two exchanges (a + b and b + a are the same bits, so all four get the same value)
   const int q = int(tid & 3);
   const int64_t nq = (nblk * blockDim.x) >> 2;
+  const bool restart = job.st != nullptr && job.st->restart != 0;
   for (int64_t e64 = tid >> 2; e64 < rr; e64 += nq) {
     const int e = int(e64);
     double g = 1.0;
     for (int f = 0; f < job.nfac; ++f) {
       double s = 0.0;
-      const double* part = job.part[f];
+      const double* part = (restart && job.part_new[f]) ? job.part_new[f] : job.part[f];
       const int64_t nc = job.nchunks[f];
       for (int64_t c0 = 0; c0 < nc; c0 += 64) {
         double v[16];

@@ -29,6 +29,7 @@
 //    float64 partial Grams of the new and extrapolated rows (Gram cache of the solver), and
 //    the workgroup's share of 2 <P, W> - <G, W^T W> for the restart surrogate F-hat.
 #include "gram_chunk.h"
+#include "her_update.h"
 #include "ntf_internal.h"
 
 namespace ntf {
@@ -63,7 +64,34 @@ struct HKArgs {
   int nwg;
   int lag;                 // sweeps the row waves may run ahead of the last decision
   uint64_t timeout_ticks;
+  // fused decision of the outer iteration (null st: none)
+  ntf_her_state* st;
+  ntf_her_params hp;
+  const double* normT2;
+  ntf_trace trace;
+  int order;
+  const int32_t* sweeps_src;
+  SelectJob sel;
 };
+
+// dst[i] = src[i] for i = t0, t0 + stride, ... < n, eight loads in flight per thread
+template <typename T>
+__device__ __forceinline__ void copy_strided(T* dst, const T* src, int64_t n, int64_t t0,
+                                             int64_t stride) {
+  for (int64_t i0 = t0; i0 < n; i0 += 8 * stride) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = i0 + u * stride;
+      v[u] = i < n ? src[i] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < n) dst[i] = v[u];
+    }
+  }
+}
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float x) {
@@ -468,6 +496,10 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   double gm[TG][TG];
   gram_tile_m<TG>(gpre ? a.G64 : nullptr, r, tid, gm);
   const double beta = a.A_hat ? *a.beta_src : 0.0;  // for the epilogue
+  // for the fused decision: the reference F-hat of the test and ||T||^2 (read long before
+  // this workgroup publishes its share, so before any workgroup can update the state)
+  const double fhat_ref = a.st ? a.st->fhat_prev : 0.0;
+  const double normT2 = a.st ? *a.normT2 : 0.0;
 
   // local row q of this lane: wave * RPWV + q * GPW + gi
   float w[NR][C], pinv[NR][C], zv[NR][C];
@@ -863,10 +895,11 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
 
   // ---- epilogue: write W (and A_hat); stage rows for the Gram partials ----
   float pv_keep[NR][C];  // P entries of this lane's columns, read before the rows are replaced
+  float xh_keep[NR][C];  // the extrapolated entries (for the fused selection)
 #pragma unroll
   for (int q = 0; q < NR; ++q)
 #pragma unroll
-    for (int c = 0; c < C; ++c) pv_keep[q][c] = 0.f;
+    for (int c = 0; c < C; ++c) pv_keep[q][c] = xh_keep[q][c] = 0.f;
   lds_barrier();  // every lane has its P entries in registers (pinv) by now
 #pragma unroll
   for (int q = 0; q < NR; ++q)
@@ -884,6 +917,7 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
           const float xh = float((y > 0.0 || !a.project) ? y : 0.0);
           a.A_hat[gidx] = xh;
           s_rows2[lrow[q] * r + j] = xh;
+          xh_keep[q][c] = xh;
         }
       }
     }
@@ -914,6 +948,7 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
                 : chunk_gram_tiles<TG, false, 4>(s_rows, nrows, r, out_new, gmat, no_tile);
   }
   if (out_hat) chunk_gram_tiles<TG, false, 4>(s_rows2, nrows, r, out_hat, nullptr, no_tile);
+  double e_share = 0.0;  // thread 0: this workgroup's F-hat share
   if (a.err_part) {
     // share of 2 <P, W> - <G, W^T W> over the chunk's rows
     double t = -gdot;
@@ -931,9 +966,77 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
       double e = 0.0;
       for (int k = 0; k <= WPG; ++k) e += s_part[k];
       a.err_part[blockIdx.x] = e;
+      e_share = e;
     }
   }
   if (blockIdx.x == 0 && tid == 0 && a.sweeps_out) *a.sweeps_out = done;
+  if (a.st == nullptr) return;
+
+  // ---- the decision of the outer iteration (Algorithm 2), fused ----
+  // Every workgroup publishes its F-hat share in a slot after the stopping rule's (set to
+  // all-ones bits by the preceding kernel), reads all of them, sums them in the fixed order
+  // of the decision kernel and takes the same restart decision; workgroup 0 updates the
+  // state. The selection A <- restart ? A_new : A_hat (and of the Gram chunks) is split:
+  // each workgroup writes its own rows and chunk of the last block from what it holds, and a
+  // slice of the other blocks.
+  __shared__ double s_f;  // F-hat
+  uint64_t* const es = slots + int64_t(a.max_sweeps) * a.nwg;
+  if (tid == 0) {
+    // release: the reads of the state are complete before any workgroup can see the share,
+    // and workgroup 0 writes the state only after it has seen every share
+    __hip_atomic_store(&es[blockIdx.x], uint64_t(__double_as_longlong(e_share)),
+                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  double x = 0.0;
+  bool late = false;
+  if (tid < a.nwg) {
+    const uint64_t t_poll = wall_clock64();
+    uint64_t u;
+    while ((u = __hip_atomic_load(&es[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ==
+           kSentinel) {
+      if (wall_clock64() - t_poll > a.timeout_ticks) {
+        late = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    x = late ? 0.0 : __longlong_as_double(int64_t(u));
+  }
+  const bool any_late = __syncthreads_or(late);
+  const double esum = block_sum256(x);  // ordered as the decision kernel sums the partials
+  if (tid == 0) s_f = 0.5 * (normT2 - esum);
+  __syncthreads();
+  if (any_late) {
+    if (tid == 0)
+      __hip_atomic_fetch_or(a.flags, NTF_FLAG_WAIT_TIMEOUT, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  const double f = s_f;
+  const bool restart = her_restart(f, fhat_ref);
+  if (blockIdx.x == 0 && tid == 0)
+    her_update(a.st, a.hp, f, fhat_ref, a.trace, a.order, a.sweeps_src, nullptr, a.flags);
+  const int last = a.order - 1;
+#pragma unroll
+  for (int q = 0; q < NR; ++q)
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = c * RPAD + gl;
+      if (rok[q] && j < r) a.sel.dst[last][(row0 + lrow[q]) * r + j] = restart ? w[q][c] : xh_keep[q][c];
+    }
+  if (a.sel.ddst[last]) {
+    // this workgroup's Gram chunk, written by its own threads before the barriers above
+    const double* gsrc = (restart ? a.gp_new : a.gp_hat) + blockIdx.x * rr;
+    copy_strided(a.sel.ddst[last] + blockIdx.x * rr, gsrc, rr, int64_t(tid), int64_t(kThreads));
+  }
+  // a slice of the other blocks' rows
+  const int64_t gt = int64_t(blockIdx.x) * kThreads + tid;
+  const int64_t gs = int64_t(gridDim.x) * kThreads;
+  for (int b = 0; b < last; ++b) {
+    copy_strided(a.sel.dst[b], restart ? a.sel.a_new[b] : a.sel.a_hat[b], a.sel.n[b], gt, gs);
+    if (a.sel.ddst[b])
+      copy_strided(a.sel.ddst[b], restart ? a.sel.dnew[b] : a.sel.dhat[b], a.sel.dn[b], gt, gs);
+  }
 }
 
 using HFn = void (*)(HKArgs);
@@ -1000,8 +1103,8 @@ bool hals_supported(int64_t rows, int r, int num_cus) {
 }
 
 int64_t hals_slot_count(int64_t rows, int r, int max_sweeps) {
-  // one share per workgroup and sweep
-  return int64_t(max_sweeps) * hals_wgs(rows, r);
+  // one share per workgroup and sweep, and one F-hat share per workgroup (fused decision)
+  return int64_t(max_sweeps + 1) * hals_wgs(rows, r);
 }
 
 hipError_t launch_hals(const HalsArgs& h, int num_cus, hipStream_t s) {
@@ -1025,6 +1128,19 @@ hipError_t launch_hals(const HalsArgs& h, int num_cus, hipStream_t s) {
   a.gp_hat = h.gp_hat;
   a.err_part = h.err_part;
   a.nwg = int(hals_wgs(h.rows, h.r));
+  a.st = h.st;
+  if (h.st) {
+    // the fused decision needs every output of the epilogue
+    if (!h.err_part || !h.A_hat || !h.gp_new || !h.gp_hat || !h.normT2 || h.order < 1 ||
+        h.order > kMaxOrder || h.sel.nblocks != h.order)
+      return hipErrorInvalidValue;
+    a.hp = h.hp;
+    a.normT2 = h.normT2;
+    a.trace = h.trace;
+    a.order = h.order;
+    a.sweeps_src = h.sweeps_src;
+    a.sel = h.sel;
+  }
   // wall_clock64 runs at the device's wall-clock rate; the default 2 s is far above any
   // legitimate wait
   static const int rate_khz = [] {

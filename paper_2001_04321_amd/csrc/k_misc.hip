@@ -7,6 +7,7 @@
 //    HER_eq:beta_update and HER_eq:beta_bar_update) and the post-decision selection,
 //  - || T - [[A]] ||^2 from the explicit residual (eq. err_true_def).
 // Every reduction has a fixed order (per-block tree, then an ordered sum of partials).
+#include "her_update.h"
 #include "ntf_internal.h"
 
 namespace ntf {
@@ -16,18 +17,7 @@ constexpr int kNormBlocks = 1024;
 constexpr int kResidBlocks = 1024;
 
 // Sum of a double over a 256-thread block; result valid in thread 0.
-__device__ double block_sum(double v) {
-  __shared__ double red[4];
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0) s = ((red[0] + red[1]) + red[2]) + red[3];
-  __syncthreads();
-  return s;
-}
+__device__ double block_sum(double v) { return block_sum256(v); }
 
 __device__ __forceinline__ float bf16_bits_to_float(uint32_t h) { return __uint_as_float(h << 16); }
 
@@ -154,10 +144,6 @@ __global__ __launch_bounds__(256) void error_partials_kernel(const float* __rest
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-__device__ void flag_set(uint32_t* flags, uint32_t bit) {
-  if (flags) __hip_atomic_fetch_or(flags, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __global__ __launch_bounds__(256) void error_finalize_kernel(const double* normT2,
                                                              const double* partials,
                                                              int64_t nparts, double* fhat,
@@ -190,14 +176,6 @@ __global__ __launch_bounds__(256) void cp_grad_kernel(const float* __restrict__ 
   out[e] = float(f * (g - double(P[e])));
 }
 
-// Bro's sequence in the block-wise form (Sec. 3.3): omega for outer iteration k after
-// `nrestarts` increases of the error; h = 3 grows by one every fifth increase, and no
-// extrapolation happens before iteration 5.
-__device__ __forceinline__ double bro_h(int nrestarts) { return 3.0 + double(nrestarts / 5); }
-__device__ __forceinline__ double bro_omega(int64_t k, double h) {
-  return k < 5 ? 0.0 : pow(double(k), 1.0 / h) - 1.0;
-}
-
 __global__ void her_init_kernel(ntf_her_state* st, double beta0, int scheme,
                                 const double* fhat0) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -226,43 +204,8 @@ __global__ __launch_bounds__(256) void her_decide_kernel(DecideArgs a) {
     f = *a.fhat;
   }
   if (threadIdx.x != 0) return;
-  ntf_her_state* st = a.st;
-  const bool finite = isfinite(f);
-  if (!finite) flag_set(a.flags, NTF_FLAG_NONFINITE);
-  // Algorithm 2: restart when F-hat_k > F-hat_{k-1}; a non-finite F-hat also discards
-  // the extrapolated sequence.
-  const bool restart = !finite || f > st->fhat_prev;
-  const double beta = st->beta;
-  const double beta_bar = st->beta_bar;
-  if (a.p.scheme == 1) {
-    // Bro: the next iteration's omega from its index and the increases so far
-    const int nr = st->nrestarts + (restart ? 1 : 0);
-    const double h = bro_h(nr);
-    st->beta = bro_omega(st->k + 2, h);
-    st->beta_bar = h;
-  } else if (restart) {
-    st->beta_bar = beta;
-    st->beta = beta / a.p.eta;
-  } else {
-    st->beta = fmin(beta_bar, a.p.gamma * beta);
-    st->beta_bar = fmin(1.0, a.p.gamma_bar * beta_bar);
-  }
-  st->restart = restart ? 1 : 0;
-  st->nrestarts += restart ? 1 : 0;
-  // a non-finite F-hat is not a reference for the next test (f > NaN is false, which
-  // would accept the next extrapolation unconditionally): the last finite value stays
-  if (finite) st->fhat_prev = f;
-  st->fhat = f;
-  st->k += 1;
-  const int64_t it = st->it;
-  if (a.trace.fhat) a.trace.fhat[it] = f;
-  if (a.trace.beta) a.trace.beta[it] = st->beta;
-  if (a.trace.beta_bar) a.trace.beta_bar[it] = st->beta_bar;
-  if (a.trace.restart) a.trace.restart[it] = restart ? 1 : 0;
-  if (a.trace.sweeps && a.sweeps_src)
-    for (int n = 0; n < a.order; ++n) a.trace.sweeps[it * a.order + n] = a.sweeps_src[n];
-  if (a.fhat_out) *a.fhat_out = f;
-  st->it = it + 1;
+  her_update(a.st, a.p, f, a.st->fhat_prev, a.trace, a.order, a.sweeps_src, a.fhat_out,
+             a.flags);
 }
 
 __global__ __launch_bounds__(256) void select_kernel(SelectJob j, const ntf_her_state* st) {

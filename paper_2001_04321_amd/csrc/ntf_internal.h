@@ -234,6 +234,10 @@ hipError_t launch_gram_partials(const GramJob& job, int r, hipStream_t s);
 // also resets `nslots` inner-solver wait slots to the sentinel (may be 0).
 struct HadamardJob {
   const double* part[kMaxOrder];
+  // a factor whose Gram is the survivor of the last HER decision: its chunks are taken from
+  // part_new[f] when st->restart is set, else from part[f] (null part_new: always part)
+  const double* part_new[kMaxOrder];
+  const ntf_her_state* st;
   int64_t nchunks[kMaxOrder];
   int nfac;
 };
@@ -260,6 +264,19 @@ int64_t hals_wgs(int64_t rows, int r);
 // Workgroups never exceed min(256, CU count) so that all of them are resident at once.
 bool hals_supported(int64_t rows, int r, int num_cus);
 hipError_t launch_fill_sentinel(double* slots, int64_t n, hipStream_t s);
+// After DECIDE: dst[b] <- restart ? a_new[b] : a_hat[b] for every block (and the same
+// selection for optional float64 side buffers).
+struct SelectJob {
+  float* dst[kMaxOrder];
+  const float* a_new[kMaxOrder];
+  const float* a_hat[kMaxOrder];
+  int64_t n[kMaxOrder];
+  double* ddst[kMaxOrder];
+  const double* dnew[kMaxOrder];
+  const double* dhat[kMaxOrder];
+  int64_t dn[kMaxOrder];
+  int nblocks;
+};
 struct HalsArgs {
   const float* W0;       // warm start (may equal W)
   float* W;              // result
@@ -281,6 +298,17 @@ struct HalsArgs {
   double* err_part;      // per-workgroup share of 2 <P, W> - <G64, W^T W>
   double wait_limit_s = 2.0;  // bounded cross-workgroup waits give up after this long
   bool project = true;        // A_hat projected onto the nonnegative orthant
+  // optional fused decision (the last block of an outer iteration, with err_part): F-hat
+  // from every workgroup's share, the restart test, the state update and the selection of
+  // the next iterate, which otherwise take launch_her_decide and launch_select. The shares
+  // go through hals_wgs(rows, r) slots after the stopping rule's (the same reset).
+  ntf_her_state* st = nullptr;
+  ntf_her_params hp{};
+  const double* normT2 = nullptr;
+  ntf_trace trace{};
+  int order = 0;
+  const int32_t* sweeps_src = nullptr;
+  SelectJob sel{};
 };
 hipError_t launch_hals(const HalsArgs& a, int num_cus, hipStream_t s);
 
@@ -401,19 +429,6 @@ struct DecideArgs {
   uint32_t* flags;
 };
 hipError_t launch_her_decide(const DecideArgs& a, hipStream_t s);
-// After DECIDE: dst[b] <- restart ? a_new[b] : a_hat[b] for every block (and the same
-// selection for optional float64 side buffers).
-struct SelectJob {
-  float* dst[kMaxOrder];
-  const float* a_new[kMaxOrder];
-  const float* a_hat[kMaxOrder];
-  int64_t n[kMaxOrder];
-  double* ddst[kMaxOrder];
-  const double* dnew[kMaxOrder];
-  const double* dhat[kMaxOrder];
-  int64_t dn[kMaxOrder];
-  int nblocks;
-};
 hipError_t launch_select(const SelectJob& j, const ntf_her_state* st, hipStream_t s);
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s);
 hipError_t launch_reset_call(ntf_her_state* st, hipStream_t s);

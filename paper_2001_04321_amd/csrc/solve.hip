@@ -71,7 +71,6 @@ struct SolveBufs {
   ntf_her_state* state;
   float* A_new[kMaxOrder];
   float* A_hat[kMaxOrder];
-  double* gp_cur[kMaxOrder];
   double* gp_new[kMaxOrder];
   double* gp_hat[kMaxOrder];
   float* G32;
@@ -118,7 +117,6 @@ void carve(Arena& ar, SolveBufs& b, const ntf_tensor& T, int r, int max_inner,
     b.A_new[n] = ar.take<float>(size_t(I) * r);
     b.A_hat[n] = ar.take<float>(size_t(I) * r);
     const size_t g = size_t(gram_chunks(I, r)) * rr;
-    b.gp_cur[n] = ar.take<double>(g);
     b.gp_new[n] = ar.take<double>(g);
     b.gp_hat[n] = ar.take<double>(g);
     maxpart = std::max(maxpart, plans[n].partial_floats());
@@ -218,12 +216,30 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
                              const PairPlans& pp) {
   const int N = T.order;
   hipError_t e;
+  // the survivor selection after the decision: A <- restart ? A_new : A_hat. The cached Gram
+  // chunks are not copied: the survivor's chunks are read from gp_new or gp_hat by the flag
+  // (see the Hadamard jobs below)
+  SelectJob sj{};
+  sj.nblocks = N;
+  for (int l = 0; l < N; ++l) {
+    sj.dst[l] = A[l];
+    sj.a_new[l] = b.A_new[l];
+    sj.a_hat[l] = b.A_hat[l];
+    sj.n[l] = T.dims[l] * r;
+  }
+  // with the resident A-HALS kernel on the last block, its launch takes the decision too
+  const bool fuse_decide = fused_hals(h, p, T.dims[N - 1], r);
   for (int n = 0; n < N; ++n) {
     const int64_t I = T.dims[n];
     HadamardJob hj{};
+    hj.st = b.state;
     for (int l = 0; l < N; ++l) {
       if (l == n) continue;
-      hj.part[hj.nfac] = l < n ? b.gp_hat[l] : b.gp_cur[l];
+      // blocks before n: their extrapolated rows of this iteration; after n: the survivor
+      // of the last decision, whose chunks (new or extrapolated) stay untouched until
+      // block l is updated, after every block before it
+      hj.part[hj.nfac] = b.gp_hat[l];
+      hj.part_new[hj.nfac] = l < n ? nullptr : b.gp_new[l];
       hj.nchunks[hj.nfac] = gram_chunks(T.dims[l], r);
       hj.nfac++;
     }
@@ -360,32 +376,30 @@ hipError_t enqueue_iteration(ntf_handle* h, const ntf_tensor& T, int r, float* c
     ha.gp_new = b.gp_new[n];
     ha.gp_hat = b.gp_hat[n];
     ha.err_part = n == N - 1 ? b.err_part : nullptr;
+    if (n == N - 1 && fuse_decide) {
+      ha.st = b.state;
+      ha.hp = p;
+      ha.normT2 = b.normT2;
+      ha.trace = trace;
+      ha.order = N;
+      ha.sweeps_src = b.sweeps;
+      ha.sel = sj;
+    }
     if ((e = launch_hals(ha, h->num_cus, s)) != hipSuccess) return e;
   }
+  if (fuse_decide) return hipSuccess;
   const int64_t IN = T.dims[N - 1];
   DecideArgs d{};
   d.st = b.state;
   d.p = p;
   d.normT2 = b.normT2;
   d.partials = b.err_part;
-  d.nparts = fused_hals(h, p, IN, r) ? hals_wgs(IN, r) : error_partial_count(IN, r);
+  d.nparts = error_partial_count(IN, r);
   d.trace = trace;
   d.order = N;
   d.sweeps_src = b.sweeps;
   d.flags = h->dev_flags;
   if ((e = launch_her_decide(d, s)) != hipSuccess) return e;
-  SelectJob sj{};
-  sj.nblocks = N;
-  for (int l = 0; l < N; ++l) {
-    sj.dst[l] = A[l];
-    sj.a_new[l] = b.A_new[l];
-    sj.a_hat[l] = b.A_hat[l];
-    sj.n[l] = T.dims[l] * r;
-    sj.ddst[l] = b.gp_cur[l];
-    sj.dnew[l] = b.gp_new[l];
-    sj.dhat[l] = b.gp_hat[l];
-    sj.dn[l] = gram_chunks(T.dims[l], r) * int64_t(r) * r;
-  }
   return launch_select(sj, b.state, s);
 }
 
@@ -521,18 +535,21 @@ static ntf_status solve_impl(ntf_handle* h, const ntf_tensor* T, const TuckerDes
     NTF_HIP(launch_tucker_norm2(*tk, b.tnorm, b.normT2, s));
   else
     NTF_HIP(launch_norm2(T->data, T->dtype, n_all, b.norm_part, b.normT2, s));
+  // (into both candidate caches: whichever the restart flag selects holds the chunks of A)
   GramJob gj{};
   gj.nfac = N;
   for (int l = 0; l < N; ++l) {
     gj.A[l] = A[l];
-    gj.out[l] = b.gp_cur[l];
+    gj.out[l] = b.gp_hat[l];
     gj.rows[l] = T->dims[l];
   }
+  NTF_HIP(launch_gram_partials(gj, r, s));
+  for (int l = 0; l < N; ++l) gj.out[l] = b.gp_new[l];
   NTF_HIP(launch_gram_partials(gj, r, s));
   if (!resume) {
     HadamardJob hj{};
     for (int l = 0; l < N - 1; ++l) {
-      hj.part[hj.nfac] = b.gp_cur[l];
+      hj.part[hj.nfac] = b.gp_hat[l];
       hj.nchunks[hj.nfac] = gram_chunks(T->dims[l], r);
       hj.nfac++;
     }
