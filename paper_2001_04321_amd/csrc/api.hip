@@ -809,7 +809,7 @@ ntf_status solve_batched_impl(ntf_handle* h, int32_t nprob, const ntf_problem* p
       d.A[n] = q.A[n];
     }
     d.r = q.r;
-    d.rb = (q.r + 7) / 8 * 8;
+    d.rb = (q.r + 3) / 4 * 4;
     d.state = q.state;
     d.tr_fhat = q.trace_fhat;
     d.tr_restart = q.trace_restart;

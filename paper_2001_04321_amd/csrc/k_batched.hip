@@ -17,7 +17,7 @@
 // of Sec. 4.1 on the workgroup-wide ||W_s - W_{s-1}||). The HER scalars and the survivor
 // buffer of each block live in device memory between launches. Extrapolation (eq.
 // extproj_her), Grams, F-hat and the decision are float64; every reduction has a fixed
-// order. Ranks are padded to a multiple of 8 (RB) with zero columns.
+// order. Ranks are padded to a multiple of 4 (RB) with zero columns.
 #include "ntf_internal.h"
 
 namespace ntf {
@@ -191,9 +191,13 @@ __global__ __launch_bounds__(kGT) void by_kernel(BArgs a) {
   item_of(a, b, t);
   const BProb& pb = a.probs[b];
   switch (pb.rb) {
+    case 4: y_tile<4>(pb, t, lds); break;
     case 8: y_tile<8>(pb, t, lds); break;
+    case 12: y_tile<12>(pb, t, lds); break;
     case 16: y_tile<16>(pb, t, lds); break;
+    case 20: y_tile<20>(pb, t, lds); break;
     case 24: y_tile<24>(pb, t, lds); break;
+    case 28: y_tile<28>(pb, t, lds); break;
     default: y_tile<32>(pb, t, lds); break;
   }
 }
@@ -313,9 +317,13 @@ __global__ __launch_bounds__(kGT) void blast_kernel(BArgs a, int init) {
   item_of(a, b, t);
   const BProb& pb = a.probs[b];
   switch (pb.rb) {
+    case 4: last_tile<4>(a, pb, t, init, lds); break;
     case 8: last_tile<8>(a, pb, t, init, lds); break;
+    case 12: last_tile<12>(a, pb, t, init, lds); break;
     case 16: last_tile<16>(a, pb, t, init, lds); break;
+    case 20: last_tile<20>(a, pb, t, init, lds); break;
     case 24: last_tile<24>(a, pb, t, init, lds); break;
+    case 28: last_tile<28>(a, pb, t, init, lds); break;
     default: last_tile<32>(a, pb, t, init, lds); break;
   }
 }
@@ -395,12 +403,13 @@ __device__ int hals_rows(const float* __restrict__ W0, float* __restrict__ Wn,
 #pragma unroll
         for (int l4 = 0; l4 < RB / 4; ++l4) gb[(j + 1) & 1][l4] = G4[(j + 1) * (RB / 4) + l4];
       }
-      // four partial sums; the terms are taken in the order l = j, j + 1, ..., j - 1
-      // (cyclically), so the column updated last enters last and the chain from it to
-      // W_j is one multiply-add, the two adds and the max
+      // four partial sums; the terms are taken in the order l = j + 1, ..., j - 1
+      // (cyclically; the l = j term of Gt is zero and adds nothing), so the column updated
+      // last enters last and the chain from it to W_j is one multiply-add, the two adds and
+      // the max
       float acc[4] = {pinv[j], 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int m = 0; m < RB; ++m) {
+      for (int m = 1; m < RB; ++m) {
         const int l = (j + m) % RB;
         const float4 g4 = gb[j & 1][l / 4];
         const float g = (l & 3) == 0 ? g4.x : (l & 3) == 1 ? g4.y : (l & 3) == 2 ? g4.z : g4.w;
@@ -547,9 +556,13 @@ __global__ __launch_bounds__(kBT) void bhals_kernel(BArgs a, int n) {
   __shared__ double G64s[kBatchedMaxRank * kBatchedMaxRank];
   const BProb& pb = a.probs[a.order[blockIdx.x]];
   switch (pb.rb) {
+    case 4: block_update<4>(a, pb, n, s_red, G32s, ginv, G64s, s_rows); break;
     case 8: block_update<8>(a, pb, n, s_red, G32s, ginv, G64s, s_rows); break;
+    case 12: block_update<12>(a, pb, n, s_red, G32s, ginv, G64s, s_rows); break;
     case 16: block_update<16>(a, pb, n, s_red, G32s, ginv, G64s, s_rows); break;
+    case 20: block_update<20>(a, pb, n, s_red, G32s, ginv, G64s, s_rows); break;
     case 24: block_update<24>(a, pb, n, s_red, G32s, ginv, G64s, s_rows); break;
+    case 28: block_update<28>(a, pb, n, s_red, G32s, ginv, G64s, s_rows); break;
     default: block_update<32>(a, pb, n, s_red, G32s, ginv, G64s, s_rows); break;
   }
 }
@@ -598,9 +611,13 @@ __global__ __launch_bounds__(kBT) void bsetup_kernel(BArgs a) {
   __shared__ double s_red[kBW + 1];
   const BProb& pb = a.probs[a.order[blockIdx.x]];
   switch (pb.rb) {
+    case 4: setup_problem<4>(a, pb, s_red); break;
     case 8: setup_problem<8>(a, pb, s_red); break;
+    case 12: setup_problem<12>(a, pb, s_red); break;
     case 16: setup_problem<16>(a, pb, s_red); break;
+    case 20: setup_problem<20>(a, pb, s_red); break;
     case 24: setup_problem<24>(a, pb, s_red); break;
+    case 28: setup_problem<28>(a, pb, s_red); break;
     default: setup_problem<32>(a, pb, s_red); break;
   }
 }
@@ -624,9 +641,13 @@ __global__ __launch_bounds__(kBT) void bfhat0_kernel(BArgs a) {
   __shared__ double s_red[kBW + 1];
   const BProb& pb = a.probs[a.order[blockIdx.x]];
   switch (pb.rb) {
+    case 4: fhat0_problem<4>(pb, s_red); break;
     case 8: fhat0_problem<8>(pb, s_red); break;
+    case 12: fhat0_problem<12>(pb, s_red); break;
     case 16: fhat0_problem<16>(pb, s_red); break;
+    case 20: fhat0_problem<20>(pb, s_red); break;
     case 24: fhat0_problem<24>(pb, s_red); break;
+    case 28: fhat0_problem<28>(pb, s_red); break;
     default: fhat0_problem<32>(pb, s_red); break;
   }
 }

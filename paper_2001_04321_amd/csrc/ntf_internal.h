@@ -441,7 +441,7 @@ constexpr size_t kBatchedDescBytes = 512;
 struct BatchedProblem {
   const float* T;
   int I[3];
-  int r, rb;            // rank and its padding to a multiple of 8
+  int r, rb;            // rank and its padding to a multiple of 4
   float* A[3];
   char* ws;             // batched_problem_bytes(I, rb) bytes of device workspace
   ntf_her_state* state; // may be null
