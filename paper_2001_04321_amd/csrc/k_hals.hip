@@ -431,28 +431,30 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   // setup: the scaled G table and this workgroup's P block (rows row0 .. row0+nrows-1,
   // contiguous in memory), in batches whose loads are all in flight before any is used;
   // the first batches of both go out together
-  constexpr int kB = 8;
+  // loads per thread and batch: the whole table in one batch up to r = 64
+  constexpr int kB = RB * RMAX > 8 * kThreads ? 16 : 8;
+  static_assert(kThreads % RMAX == 0, "a thread's entries share one column k");
   const int np = nrows * r;
   const float* Pb = a.P + row0 * r;
-  auto g_load = [&](int base, float (&gv)[kB], float (&gd)[kB]) {
+  const int kcol = tid % RMAX;  // the column of every table entry this thread writes
+  const float gdk = kcol < r ? a.G[kcol * r + kcol] : 0.f;
+  auto g_load = [&](int base, float (&gv)[kB]) {
 #pragma unroll
     for (int i = 0; i < kB; ++i) {
       const int e = base + i * kThreads + tid;
       const int j = e / RMAX;
-      const int k = e - j * RMAX;
-      const bool ok = e < RB * RMAX && j < r && k < r;
-      gv[i] = ok ? a.G[j * r + k] : 0.f;
-      gd[i] = ok ? a.G[k * r + k] : 0.f;
+      const bool ok = e < RB * RMAX && j < r && kcol < r;
+      gv[i] = ok ? a.G[j * r + kcol] : 0.f;
     }
   };
-  auto g_store = [&](int base, const float (&gv)[kB], const float (&gd)[kB]) {
+  auto g_store = [&](int base, const float (&gv)[kB]) {
 #pragma unroll
     for (int i = 0; i < kB; ++i) {
       const int e = base + i * kThreads + tid;
       const int j = e / RMAX;
-      const int k = e - j * RMAX;
+      const bool ok = j < r && kcol < r;
       if (e < RB * RMAX)
-        s_g[e] = gd[i] != 0.f ? (j == k ? -1.f : -(gv[i] * (1.f / gd[i]))) : 0.f;
+        s_g[e] = (ok && gdk != 0.f) ? (j == kcol ? -1.f : -(gv[i] * (1.f / gdk))) : 0.f;
     }
   };
   auto p_load = [&](int base, float (&pv)[kB]) {
@@ -470,16 +472,16 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
     }
   };
   {
-    float gv[kB], gd[kB], pv[kB];
-    g_load(0, gv, gd);
+    float gv[kB], pv[kB];
+    g_load(0, gv);
     p_load(0, pv);
-    g_store(0, gv, gd);
+    g_store(0, gv);
     p_store(0, pv);
   }
   for (int base = kB * kThreads; base < RB * RMAX; base += kB * kThreads) {
-    float gv[kB], gd[kB];
-    g_load(base, gv, gd);
-    g_store(base, gv, gd);
+    float gv[kB];
+    g_load(base, gv);
+    g_store(base, gv);
   }
   for (int base = kB * kThreads; base < np; base += kB * kThreads) {
     float pv[kB];
