@@ -31,12 +31,8 @@ COMMON = [
 ]
 
 
-# per-file additions. A-HALS: without the atomic optimizer, the per-sweep arrival counter's
-# fetch-add is not rewritten into a form that waits for the returned value at once (the
-# value is first needed one sweep later).
-EXTRA = {
-    "k_hals.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
-}
+# per-file additions (none at present)
+EXTRA: dict = {}
 
 
 def sources():

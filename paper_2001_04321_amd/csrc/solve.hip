@@ -37,7 +37,7 @@ struct SolveKey {
 
 // One outer iteration, and kGraphUnroll iterations back to back (consecutive graph launches
 // leave a gap of several microseconds between them, which the longer graph amortizes).
-constexpr int kGraphUnroll = 4;
+constexpr int kGraphUnroll = 8;
 struct SolveGraph {
   SolveKey key;
   hipGraph_t graph = nullptr;
