@@ -284,6 +284,35 @@ def test_hals_largest_covered_blocks(ntf, rows, r):
                             max_sweeps=2, tol=0.0)
 
 
+@pytest.mark.parametrize("rows,r,seed", [(300, 24, 2), (600, 24, 3), (1200, 24, 1),
+                                          (2400, 24, 3), (600, 40, 3)])
+def test_hals_stopping_rule_workgroup_counts(ntf, rows, r, seed):
+    """The stopping rule at the default tolerance for 25, 50, 100 and 200 workgroups (each
+    count takes its own form of the rule's cross-workgroup sum: 16, 8 or 4 sweeps per
+    round trip, 8 or 16 slot loads per lane) and for 64-lane rows, against the oracle's
+    sweep count and iterate. Seeds chosen so that no sweep's ratio lies within 1 % of the
+    threshold."""
+    g = np.random.default_rng(1000 * rows + r + seed)
+    B = g.random((2000, r))
+    P = (g.random((rows, 2000)).astype(np.float32) @ B.astype(np.float32)).astype(np.float32)
+    G = (B.T @ B).astype(np.float32)
+    W0 = g.random((rows, r)).astype(np.float32)
+    W_ref, s_ref, deltas = oracle.hals(W0.astype(np.float64), P.astype(np.float64),
+                                       G.astype(np.float64), max_sweeps=30, tol=1e-2)
+    assert all(abs(d / deltas[0] - 1e-2) > 1e-4 for d in deltas)
+    Wd = dev_f32(W0)
+    sw = ntf.ntf_hals_update(Wd, dev_f32(P), dev_f32(G), max_sweeps=30, tol=1e-2)
+    W_np32 = _hals_f32(W0, P, G, s_ref)
+    err_gpu, err_np = rel_fro(to_np(Wd), W_ref), rel_fro(W_np32, W_ref)
+    print(f"hals rows={rows} r={r} sweeps={int(sw.item())}/{s_ref} gpu={err_gpu:.3e} "
+          f"np32={err_np:.3e}")
+    assert int(sw.item()) == s_ref
+    # as in test_hals_largest_covered_blocks: the step form's rank-one updates between
+    # refreshes add about sqrt(4r) u cond(G) to the literal float32 sweeps' error
+    ev = np.linalg.eigvalsh(G.astype(np.float64))
+    assert err_gpu <= 4 * err_np + np.sqrt(4 * r) * 2.0 ** -24 * (ev[-1] / ev[0])
+
+
 def test_hals_stopping_rule_matches_oracle(ntf):
     # seed chosen so that no sweep's delta ratio lies within 1% of the 1e-2 threshold
     pr = synth.make_problem((300, 40, 50), 16, snr_db=30.0, data_seed=29, init_seed=30)
