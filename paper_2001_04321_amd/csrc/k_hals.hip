@@ -17,7 +17,7 @@
 // Stopping rule: a fourth wave of each workgroup runs it while three waves sweep (so it has
 // a SIMD of its own and takes no issue cycles from a row wave). It sums the row waves'
 // shares of ||W_s - W_{s-1}||^2 (float64, fixed order), publishes the workgroup's share,
-// sums every workgroup's shares in workgroup order (so every workgroup takes the same
+// sums every workgroup's shares in a fixed order (so every workgroup takes the same
 // decision) and posts the decisions in LDS. Row waves run up to `lag` sweeps past the last
 // decision, keeping those iterates in an LDS ring, and restore the iterate of the sweep
 // the rule stops at. Waits are bounded by a wall-clock deadline
@@ -27,7 +27,10 @@
 // Fused around the sweeps (each optional):
 //  - epilogue: extrapolation A_hat = max(0, W + beta (W - W_0)) (eq. extproj_her), the
 //    float64 partial Grams of the new and extrapolated rows (Gram cache of the solver), and
-//    the workgroup's share of 2 <P, W> - <G, W^T W> for the restart surrogate F-hat.
+//    the workgroup's share of 2 <P, W> - <G, W^T W> for the restart surrogate F-hat;
+//  - the outer iteration's HER decision (Algorithm 2, last block): every workgroup reads
+//    every share, forms F-hat in the decision kernel's order, applies the restart test and
+//    writes its part of the survivor selection; workgroup 0 updates the state.
 #include "gram_chunk.h"
 #include "her_update.h"
 #include "ntf_internal.h"
