@@ -440,14 +440,24 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
   const int np = nrows * r;
   const float* Pb = a.P + row0 * r;
   const int kcol = tid % RMAX;  // the column of every table entry this thread writes
-  const float gdk = kcol < r ? a.G[kcol * r + kcol] : 0.f;
+  // G's address in vector registers (the loads are per lane anyway): short of scalar
+  // registers, the compiler would reload it from the kernel arguments before every load of
+  // the batch, each reload waited for
+  const float* Gv = a.G;
+  asm volatile("" : "+v"(Gv));
+  const float gdk = kcol < r ? Gv[kcol * r + kcol] : 0.f;
+  const float ginvk = gdk != 0.f ? 1.f / gdk : 0.f;  // one division per thread
+  // the batches tile the table exactly (no entry past its end) when this holds
+  constexpr bool kFull = (RB * RMAX) % (kB * kThreads) == 0;
+  // loads at clamped (in-range) indexes and selects instead of branches around them
   auto g_load = [&](int base, float (&gv)[kB]) {
 #pragma unroll
     for (int i = 0; i < kB; ++i) {
       const int e = base + i * kThreads + tid;
       const int j = e / RMAX;
-      const bool ok = e < RB * RMAX && j < r && kcol < r;
-      gv[i] = ok ? a.G[j * r + kcol] : 0.f;
+      const bool ok = (kFull || e < RB * RMAX) && j < r && kcol < r;
+      const float x = Gv[min(j, r - 1) * r + min(kcol, r - 1)];
+      gv[i] = ok ? x : 0.f;
     }
   };
   auto g_store = [&](int base, const float (&gv)[kB]) {
@@ -456,15 +466,16 @@ __global__ __launch_bounds__(kThreads) void hals_kernel(HKArgs a) {
       const int e = base + i * kThreads + tid;
       const int j = e / RMAX;
       const bool ok = j < r && kcol < r;
-      if (e < RB * RMAX)
-        s_g[e] = (ok && gdk != 0.f) ? (j == kcol ? -1.f : -(gv[i] * (1.f / gdk))) : 0.f;
+      if (kFull || e < RB * RMAX)
+        s_g[e] = (ok && gdk != 0.f) ? (j == kcol ? -1.f : -(gv[i] * ginvk)) : 0.f;
     }
   };
   auto p_load = [&](int base, float (&pv)[kB]) {
 #pragma unroll
     for (int i = 0; i < kB; ++i) {
       const int e = base + i * kThreads + tid;
-      pv[i] = e < np ? Pb[e] : 0.f;
+      const float x = Pb[min(e, np - 1)];
+      pv[i] = e < np ? x : 0.f;
     }
   };
   auto p_store = [&](int base, const float (&pv)[kB]) {
