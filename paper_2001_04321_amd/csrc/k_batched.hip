@@ -107,6 +107,20 @@ __device__ double block_sum(double x, double* s_red) {
   return r;
 }
 
+// The same sum with one barrier, for the A-HALS sweeps: each wave's sum goes to buffer
+// `parity` of buf (2 x kBW; alternate the parity every call: a wave can only write the
+// same buffer again after the next call's barrier, which every wave reaches after its reads
+// of this one), then every thread adds the waves' sums in order: the bits of block_sum.
+__device__ double sweep_sum(double x, double* buf, int parity) {
+  const double w = wave_sum(x);
+  double* b = buf + parity * kBW;
+  if ((threadIdx.x & 63) == 0) b[threadIdx.x >> 6] = w;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < kBW; ++k) t += b[k];
+  return t;
+}
+
 // Gram of a rows x RB buffer (float64, rows in order); out: rb x rb global.
 template <int RB>
 __device__ void gram_of(const float* X, int rows, double* out) {
@@ -420,7 +434,7 @@ __device__ int hals_rows(const float* __restrict__ W0, float* __restrict__ Wn,
       d2 = fma(dd, dd, d2);
       w[j] = wn;
     }
-    const double D = block_sum(d2, s_red);
+    const double D = sweep_sum(d2, s_red + kBW + 1, s & 1);
     if (s == 1) lim = tol2 * D;
     if (D <= lim) {
       done = s;
@@ -550,7 +564,7 @@ __device__ void block_update(const BArgs& a, const BProb& pb, int n, double* s_r
 
 __global__ __launch_bounds__(kBT) void bhals_kernel(BArgs a, int n) {
   extern __shared__ __attribute__((aligned(16))) float s_rows[];  // 2 I_n x RB
-  __shared__ double s_red[kBW + 1];
+  __shared__ double s_red[3 * kBW + 1];  // block_sum's, then the sweep sums' two buffers
   __shared__ __attribute__((aligned(16))) float G32s[kBatchedMaxRank * kBatchedMaxRank];
   __shared__ __attribute__((aligned(16))) float ginv[kBatchedMaxRank];
   __shared__ double G64s[kBatchedMaxRank * kBatchedMaxRank];
