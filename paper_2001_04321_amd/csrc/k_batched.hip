@@ -11,6 +11,9 @@
 //                  sums over chunks of four i, added in chunk order by bsum
 //   bhals (block 3, then F-hat by the Gram trick of Sec. 3.1.3 and the restart decision)
 //
+// The set-up (once per call) sums ||T||^2 over the same Y tiles (bnorm), then per problem
+// stages A_0 and its Grams (bsetup) and forms F-hat_0 from a last-mode pass.
+//
 // The tensor passes (Y, the last mode) and the folds give each problem many workgroups
 // (tiles of rows), so the large problems of a batch no longer set the pace on one compute
 // unit; the A-HALS blocks take one workgroup per problem (one lane per row, stopping rule
@@ -49,6 +52,7 @@ struct BProb {
   float* Y;            // I_1 I_2 x rb
   float* P;            // I_max x rb
   float* part;         // ceil(I_1 / 4) x I_3 x rb: last-mode partial sums
+  double* normp;       // ||T||^2 over each Y tile's rows (set-up)
   BScal* sc;
   ntf_her_state* st;
   double* tr_fhat;
@@ -596,9 +600,10 @@ __device__ void setup_problem(const BArgs& a, const BProb& pb, double* s_red) {
   }
   __syncthreads();
   for (int n = 0; n < 3; ++n) gram_of<RB>(pb.buf[n][0], pb.I[n], pb.gram[n][0]);
-  const int64_t tot = int64_t(pb.I[0]) * pb.I[1] * pb.I[2];
+  // ||T||^2: the Y tiles' sums (bnorm_kernel), thread k adding tiles k, k + kBT, ... in order
+  const int ntiles = int((int64_t(pb.I[0]) * pb.I[1] + kYRows - 1) / kYRows);
   double acc = 0.0;
-  for (int64_t e = tid; e < tot; e += kBT) acc = fma(double(pb.T[e]), double(pb.T[e]), acc);
+  for (int t = tid; t < ntiles; t += kBT) acc += pb.normp[t];
   const double nt2 = block_sum(acc, s_red);
   if (tid == 0) {
     BScal* sc = pb.sc;
@@ -619,6 +624,38 @@ __device__ void setup_problem(const BArgs& a, const BProb& pb, double* s_red) {
       sc->nrestarts = 0.0;
     }
   }
+}
+
+// Sum of T^2 over the rows of one Y tile (rows t * kYRows .. +kYRows of I_1 I_2, each I_3
+// contiguous elements): eight loads in flight per thread at clamped in-range offsets, four
+// float64 chains, then the fixed-order block sum. Many workgroups per problem, so the
+// set-up reads the tensors at streaming rate.
+__global__ __launch_bounds__(kGT) void bnorm_kernel(BArgs a) {
+  __shared__ double s_red[kBW + 1];
+  int b, t;
+  item_of(a, b, t);
+  const BProb& pb = a.probs[b];
+  const int64_t I2 = pb.I[2];
+  const int64_t R = int64_t(pb.I[0]) * pb.I[1];
+  const int64_t lo = int64_t(t) * kYRows * I2;
+  const int64_t hi = std::min<int64_t>(R, int64_t(t + 1) * kYRows) * I2;
+  const float* __restrict__ T = pb.T;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t e0 = lo + threadIdx.x; e0 < hi; e0 += 8 * kGT) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t e = e0 + int64_t(u) * kGT;
+      v[u] = T[e < hi ? e : lo];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double x = fma(double(v[u]), double(v[u]), acc[u & 3]);
+      acc[u & 3] = e0 + int64_t(u) * kGT < hi ? x : acc[u & 3];
+    }
+  }
+  const double sum = block_sum((acc[0] + acc[1]) + (acc[2] + acc[3]), s_red);
+  if (threadIdx.x == 0) pb.normp[t] = sum;
 }
 
 __global__ __launch_bounds__(kBT) void bsetup_kernel(BArgs a) {
@@ -697,7 +734,7 @@ int last_chunks(const int I[3]) { return int(ceil_div(I[0], kLastChunk)); }
 
 // Per-problem device workspace layout (bytes), shared by sizing and carving.
 struct BatchedLayout {
-  size_t buf[3], gram, Y, P, part, sc, st, total;
+  size_t buf[3], gram, Y, P, part, normp, sc, st, total;
 };
 
 BatchedLayout batched_layout(const int I[3], int rb) {
@@ -714,6 +751,7 @@ BatchedLayout batched_layout(const int I[3], int rb) {
   L.Y = take(size_t(I[0]) * I[1] * rb * sizeof(float));
   L.P = take(size_t(std::max({I[0], I[1], I[2]})) * rb * sizeof(float));
   L.part = take(size_t(last_chunks(I)) * I[2] * rb * sizeof(float));
+  L.normp = take(size_t(y_tiles(I)) * sizeof(double));
   L.sc = take(sizeof(BScal));
   L.st = take(sizeof(ntf_her_state));
   L.total = align_up(off, 256);
@@ -837,6 +875,7 @@ hipError_t batched_upload(const BatchedJob& job, const BatchedPlan& pl, hipStrea
     d.Y = reinterpret_cast<float*>(base + L.Y);
     d.P = reinterpret_cast<float*>(base + L.P);
     d.part = reinterpret_cast<float*>(base + L.part);
+    d.normp = reinterpret_cast<double*>(base + L.normp);
     d.sc = reinterpret_cast<BScal*>(base + L.sc);
     d.st = q.state ? q.state : reinterpret_cast<ntf_her_state*>(base + L.st);
     d.tr_fhat = q.tr_fhat;
@@ -869,6 +908,9 @@ hipError_t batched_setup(const BatchedJob& job, const BatchedPlan& pl, hipStream
   hipError_t e = launch_attrs();
   if (e != hipSuccess) return e;
   const BArgs a = make_args(job, pl, nullptr);
+  hipLaunchKernelGGL(bnorm_kernel, dim3(unsigned(pl.n_y)), dim3(kGT), 0, s,
+                     make_args(job, pl, list_ptr(job, pl.off_y)));
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(bsetup_kernel, dim3(job.nprob), dim3(kBT), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess || job.resume) return e;
