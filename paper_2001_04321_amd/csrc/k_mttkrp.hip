@@ -1096,18 +1096,42 @@ __global__ __launch_bounds__(256) void fold_u_kernel(const float* __restrict__ Y
   for (int p0 = 0; p0 < r; p0 += 32) {
     const int p = p0 + (tid & 31);
     const int g = tid >> 5;
-    // four independent partial sums (u = g + 8 (4 t + j)), combined in a fixed order, so
-    // that several loads are in flight per thread
+    // four independent partial sums (u = g + 8 (4 t + j)), combined in a fixed order: a
+    // step t adds u, u + 8, u + 16, u + 24 into a0..a3 while u + 24 < U, then the rest
+    // (at most three) go into a0. The loads of four steps (and of the rest) are issued
+    // together at clamped in-range u; steps past the bound add nothing.
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
     if (p < r) {
       int64_t u = g;
-      for (; u + 24 < U; u += 32) {
-        a0 = fmaf(X[u * r + p], yi[u * r + p], a0);
-        a1 = fmaf(X[(u + 8) * r + p], yi[(u + 8) * r + p], a1);
-        a2 = fmaf(X[(u + 16) * r + p], yi[(u + 16) * r + p], a2);
-        a3 = fmaf(X[(u + 24) * r + p], yi[(u + 24) * r + p], a3);
+      while (u + 24 < U) {
+        float xv[16], yv[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int64_t uu = std::min<int64_t>(u + 8 * k, U - 1);
+          xv[k] = X[uu * r + p];
+          yv[k] = yi[uu * r + p];
+        }
+        int nv = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const bool ok = u + 32 * t + 24 < U;
+          nv += ok ? 1 : 0;
+          a0 = ok ? fmaf(xv[4 * t], yv[4 * t], a0) : a0;
+          a1 = ok ? fmaf(xv[4 * t + 1], yv[4 * t + 1], a1) : a1;
+          a2 = ok ? fmaf(xv[4 * t + 2], yv[4 * t + 2], a2) : a2;
+          a3 = ok ? fmaf(xv[4 * t + 3], yv[4 * t + 3], a3) : a3;
+        }
+        u += 32 * nv;
       }
-      for (; u < U; u += 8) a0 = fmaf(X[u * r + p], yi[u * r + p], a0);
+      float xt[3], yt[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int64_t uu = std::min<int64_t>(u + 8 * k, U - 1);
+        xt[k] = X[uu * r + p];
+        yt[k] = yi[uu * r + p];
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a0 = u + 8 * k < U ? fmaf(xt[k], yt[k], a0) : a0;
     }
     s[g][tid & 31] = (a0 + a1) + (a2 + a3);
     __syncthreads();
