@@ -244,13 +244,30 @@ __global__ __launch_bounds__(kGT) void bfold_kernel(BArgs a, int mode) {
   const float* __restrict__ Y = pb.Y;
   const int64_t ystep = mode == 0 ? int64_t(RB) : int64_t(I1) * RB;
   const float* y = Y + (mode == 0 ? int64_t(o) * I1 * RB : int64_t(o) * RB) + pp;
+  // a step adds k into acc0 and k + 2 into acc1 while k + 2 < Isum (k += 4), then the
+  // last k (if any) into acc0; eight steps' loads are issued together at clamped in-range
+  // k, and steps past the bound add nothing
   float acc0 = 0.f, acc1 = 0.f;
   int k = g;
-  for (; k + 2 < Isum; k += 4) {
-    acc0 = fmaf(W[k * RB + pp], y[k * ystep], acc0);
-    acc1 = fmaf(W[(k + 2) * RB + pp], y[(k + 2) * ystep], acc1);
+  while (k + 2 < Isum) {
+    float wv[16], yv[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int kk = min(k + 2 * m, Isum - 1);
+      wv[m] = W[kk * RB + pp];
+      yv[m] = y[kk * ystep];
+    }
+    int nv = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const bool ok = k + 4 * t + 2 < Isum;
+      nv += ok ? 1 : 0;
+      acc0 = ok ? fmaf(wv[2 * t], yv[2 * t], acc0) : acc0;
+      acc1 = ok ? fmaf(wv[2 * t + 1], yv[2 * t + 1], acc1) : acc1;
+    }
+    k += 4 * nv;
   }
-  for (; k < Isum; k += 2) acc0 = fmaf(W[k * RB + pp], y[k * ystep], acc0);
+  if (k < Isum) acc0 = fmaf(W[k * RB + pp], y[k * ystep], acc0);
   float s = acc0 + acc1;
   const float other = __shfl_xor(s, 32);
   s = g == 0 ? s + other : other + s;  // (group 0) + (group 1)
