@@ -23,7 +23,9 @@ constexpr int kRowThreads = 256;
 // zeros and are skipped; predicated, so the loops unroll and w stays in registers). G is in
 // LDS transposed, s_gt[j * RM + l] = G[l][j]; column j's terms are taken in the order
 // l = j + 1, ..., j - 1 (cyclically) over four partial sums, so the column updated last
-// enters last, and row j + 1 of s_gt is read while column j is updated.
+// enters last, and row j + 1 of s_gt is read while column j is updated. The division by
+// G[j][j] is a product with its reciprocal, formed once per launch (a dead component,
+// G[j][j] <= 0, keeps the reciprocal 0 and its column 0).
 template <int RM, bool EXACT, int PASS>
 __global__ __launch_bounds__(kRowThreads) void hals_rows_kernel(HalsRowsArgs a) {
   __shared__ float s_gt[RM * RM];
@@ -46,6 +48,12 @@ __global__ __launch_bounds__(kRowThreads) void hals_rows_kernel(HalsRowsArgs a) 
     const float pw = a.P[base + jj], ww = a.W0[base + jj];
     pv[j] = (live && in) ? pw : 0.f;
     w[j] = (live && in) ? ww : 0.f;
+  }
+  float ginv[RM];
+#pragma unroll
+  for (int j = 0; j < RM; ++j) {
+    const float gjj = s_gt[j * RM + j];
+    ginv[j] = gjj > 0.f ? 1.f / gjj : 0.f;
   }
   const int sweeps = PASS == 1 ? a.max_sweeps : *a.sweeps_dev;
   for (int s = 0; s < sweeps; ++s) {
@@ -72,8 +80,7 @@ __global__ __launch_bounds__(kRowThreads) void hals_rows_kernel(HalsRowsArgs a) 
           if (EXACT || l < r) acc[m & 3] = fmaf(-w[l], gb[j & 1][l], acc[m & 3]);
         }
         const float num = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-        const float gjj = gb[j & 1][j];
-        const float nw = gjj > 0.f ? fmaxf(0.f, num) / gjj : 0.f;
+        const float nw = ginv[j] != 0.f ? fmaxf(0.f, num) * ginv[j] : 0.f;
         const double df = double(nw) - double(w[j]);
         d2 = fma(df, df, d2);
         w[j] = nw;
