@@ -23,9 +23,9 @@ constexpr int kProjOut = 8 * kTThreads;
 constexpr int kProjWgs = 1024;
 
 // rows per chunk: what fits 64 KB of LDS, at most 256, and few enough that the rows spread
-// over about 128 workgroups
+// over about 128 workgroups, but at least 8 (a short block gets few partials to sum)
 int proj_chunk_rows(int64_t n, int rp, int r) {
-  const int64_t spread = std::max<int64_t>(1, ceil_div(n, int64_t(128)));
+  const int64_t spread = std::max<int64_t>(8, ceil_div(n, int64_t(128)));
   return int(std::max<int64_t>(1, std::min<int64_t>({256, 16384 / (rp + r), spread})));
 }
 
@@ -69,19 +69,19 @@ __global__ __launch_bounds__(kTThreads) void tucker_proj_part_kernel(
   }
 }
 
-// Q[o] = sum over workgroups g (in order) of part[g][o]; sixteen loads in flight per thread
+// Q[o] = sum over workgroups g (in order) of part[g][o]; thirty-two loads in flight per thread
 __global__ __launch_bounds__(kTThreads) void tucker_proj_sum_kernel(
     const double* __restrict__ part, int nwg, int no, float* __restrict__ Q32,
     double* __restrict__ Q64) {
   const int o = blockIdx.x * kTThreads + threadIdx.x;
   if (o >= no) return;
   double s = 0.0;
-  for (int g0 = 0; g0 < nwg; g0 += 16) {
-    double v[16];
+  for (int g0 = 0; g0 < nwg; g0 += 32) {
+    double v[32];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = part[int64_t(min(g0 + u, nwg - 1)) * no + o];
+    for (int u = 0; u < 32; ++u) v[u] = part[int64_t(min(g0 + u, nwg - 1)) * no + o];
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
+    for (int u = 0; u < 32; ++u)
       if (g0 + u < nwg) s += v[u];
   }
   if (Q32) Q32[o] = float(s);
