@@ -128,8 +128,21 @@ __global__ __launch_bounds__(kTThreads) void tucker_expand_kernel(const float* _
   if (e >= n * r) return;
   const int64_t m = e / r;
   const int p = int(e - m * r);
+  // the chain over i = 0 .. rp - 1 in order; sixteen terms' loads issued together (clamped
+  // in range, the ones past rp add nothing)
   double acc = 0.0;
-  for (int i = 0; i < rp; ++i) acc = fma(double(U[m * rp + i]), double(Pc[i * r + p]), acc);
+  for (int i0 = 0; i0 < rp; i0 += 16) {
+    float u[16], c[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int i = min(i0 + t, rp - 1);
+      u[t] = U[m * rp + i];
+      c[t] = Pc[i * r + p];
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+      if (i0 + t < rp) acc = fma(double(u[t]), double(c[t]), acc);
+  }
   P[e] = float(acc);
 }
 
